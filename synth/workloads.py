@@ -1,0 +1,160 @@
+"""Workload presets and seeded raw draws.
+
+The paper's own test catalogue (simulated Gaia stars in a thin anticentre
+letter-box, Sec. 4) is not available; these synthetic workloads stand in for it.
+Each preset fixes a grid, a prior and a star sample:
+
+* stars either uniform in the cube, or from an exponential disc seen from an
+  observer at the centre of the y = 0 face looking along +y (the anticentre
+  direction, as in Sec. 4): density proportional to
+  exp(-y / 2.6 kpc - |z - L/2| / 0.3 kpc), restricted to |b| <= 10 degrees
+  (sin b = (z - L/2) / d) and d <= d_max, by rejection to an exact count;
+* per-star noise scales sigma (1-sigma, in mag) from the preset's law;
+* standard-normal deviates for the field (one per node) and for the
+  observation noise (one per star).
+
+Seeds: numpy PCG64 with seed 17080000 + 100 * preset + {0 field, 1 positions,
+2 noise}.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_BASE = 17080000
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: int                      # nodes per axis
+    box_pc: float               # cube side L
+    n_stars: int
+    sweeps: int
+    star_law: str = "uniform"   # "uniform" or "disc"
+    d_max_pc: float = 0.0       # disc law: truncation distance
+    b_max_deg: float = 10.0     # disc law: latitude cut
+    disc_scale_length_pc: float = 2600.0
+    disc_scale_height_pc: float = 300.0
+    noise_law: str = "const"    # "const", "uniform", "linear"
+    noise_a: float = 0.05       # const value / uniform low / linear intercept
+    noise_b: float = 0.0        # uniform high / linear slope per kpc
+    prior_mean: float = -7.0    # ln(mag/pc)
+    prior_var: float = 1.0
+    outer_scale_pc: float = 100.0
+    support_pc: float = 150.0
+    vecchia_radius_pc: float = 0.0   # 0: equal to the support radius
+    los_step_pc: float = 2.0
+    likelihood: str = "extinction"   # or "gauss_linear"
+    precision: str = "fp64"
+    moments: str = "quadrature"
+    damping: float = 1.0
+    cavity_var_floor: float = 0.0
+    seed_id: int = 1
+
+    @property
+    def N(self) -> int:
+        return self.n ** 3
+
+    @property
+    def h(self) -> float:
+        return self.box_pc / (self.n - 1)
+
+    @property
+    def observer(self):
+        return (0.5 * self.box_pc, 0.0, 0.5 * self.box_pc)
+
+    def ep_fields(self) -> dict:
+        """The fields both EP implementations take as their configuration."""
+        return dict(
+            n=self.n, box_pc=self.box_pc, observer_pc=self.observer,
+            prior_mean=self.prior_mean, prior_var=self.prior_var,
+            outer_scale_pc=self.outer_scale_pc, support_pc=self.support_pc,
+            vecchia_radius_pc=self.vecchia_radius_pc or self.support_pc,
+            los_step_pc=self.los_step_pc, likelihood=self.likelihood,
+            precision=self.precision, moments=self.moments,
+            damping=self.damping, cavity_var_floor=self.cavity_var_floor)
+
+
+PRESETS = {
+    1: Workload("cfg1-16cube-1k", n=16, box_pc=1000.0, n_stars=1000, sweeps=10,
+                star_law="uniform", noise_law="const", noise_a=0.05, seed_id=1),
+    2: Workload("cfg2-64cube-100k", n=64, box_pc=4000.0, n_stars=100_000, sweeps=20,
+                star_law="disc", d_max_pc=4000.0, noise_law="uniform",
+                noise_a=0.05, noise_b=0.2, seed_id=2),
+    3: Workload("cfg3-128cube-1M", n=128, box_pc=8000.0, n_stars=1_000_000, sweeps=20,
+                star_law="disc", d_max_pc=8000.0, noise_law="linear",
+                noise_a=0.02, noise_b=0.03, precision="mixed", seed_id=3),
+}
+
+
+def preset(i: int, **over) -> Workload:
+    """A preset, optionally with fields replaced (e.g. a smaller star count)."""
+    return dataclasses.replace(PRESETS[i], **over)
+
+
+def _disc_positions(w: Workload, rng: np.random.Generator, count: int) -> np.ndarray:
+    L = w.box_pc
+    ox, oy, oz = w.observer
+    sinb = math.sin(math.radians(w.b_max_deg))
+    ymax = min(L, w.d_max_pc)
+    out = []
+    have = 0
+    while have < count:
+        m = max(4 * (count - have), 4096)
+        # y: exponential, truncated to [0, ymax] (inverse cdf)
+        u = rng.random(m)
+        hl = w.disc_scale_length_pc
+        y = -hl * np.log1p(-u * (1.0 - math.exp(-ymax / hl)))
+        # z - L/2: Laplace, truncated to [-L/2, L/2]
+        u = rng.random(m)
+        hz = w.disc_scale_height_pc
+        az = -hz * np.log1p(-u * (1.0 - math.exp(-0.5 * L / hz)))
+        sgn = np.where(rng.random(m) < 0.5, -1.0, 1.0)
+        z = oz + sgn * az
+        x = rng.random(m) * L
+        d = np.sqrt((x - ox) ** 2 + (y - oy) ** 2 + (z - oz) ** 2)
+        ok = (d <= w.d_max_pc) & (d > 0.0) & (np.abs(z - oz) <= sinb * d)
+        sel = np.stack([x[ok], y[ok], z[ok]], axis=1)
+        out.append(sel)
+        have += sel.shape[0]
+    return np.concatenate(out, axis=0)[:count]
+
+
+def draw(w: Workload, n_stars: int | None = None, field: bool = True) -> dict:
+    """Raw seeded draws for a workload.
+
+    Returns a dict with
+      xyz    (S, 3) star positions in the cube frame, pc
+      sigma  (S,)   1-sigma observation noise, mag
+      eps    (S,)   standard-normal noise deviates
+      xi     (N,)   standard-normal field deviates (if field=True)
+    """
+    S = w.n_stars if n_stars is None else n_stars
+    rng_pos = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * w.seed_id + 1))
+    rng_noise = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * w.seed_id + 2))
+    if w.star_law == "uniform":
+        xyz = rng_pos.random((S, 3)) * w.box_pc
+    elif w.star_law == "disc":
+        xyz = _disc_positions(w, rng_pos, S)
+    else:
+        raise ValueError(w.star_law)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    d = np.sqrt(((xyz - np.asarray(w.observer)) ** 2).sum(axis=1))
+    if w.noise_law == "const":
+        sigma = np.full(S, w.noise_a)
+    elif w.noise_law == "uniform":
+        sigma = w.noise_a + (w.noise_b - w.noise_a) * rng_noise.random(S)
+    elif w.noise_law == "linear":
+        sigma = w.noise_a + w.noise_b * d / 1000.0
+    else:
+        raise ValueError(w.noise_law)
+    eps = rng_noise.standard_normal(S)
+    out = dict(xyz=xyz, sigma=np.ascontiguousarray(sigma, dtype=np.float64),
+               eps=np.ascontiguousarray(eps, dtype=np.float64))
+    if field:
+        rng_f = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * w.seed_id + 0))
+        out["xi"] = rng_f.standard_normal(w.N)
+    return out

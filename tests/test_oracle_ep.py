@@ -1,0 +1,125 @@
+"""Pins for the oracle's parallel EP (Sec. 3.1 steps; App. A parallel
+procedure and moment matching)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import epo
+from synth import Workload, draw
+
+
+def _small(n=8, L=500.0, stars=60, lik="extinction", **kw):
+    w = Workload("tiny", n=n, box_pc=L, n_stars=stars, sweeps=3, star_law="uniform",
+                 noise_law="const", noise_a=0.05, likelihood=lik, seed_id=90)
+    cfg = w.ep_fields()
+    cfg.update(kw)
+    return w, cfg
+
+
+def test_gaussian_likelihood_exact_in_one_sweep():
+    """Gaussian likelihood: one undamped sweep from zero sites gives the exact
+    GP regression posterior (Sec. 2, conditioning on noisy observations)."""
+    w, cfg = _small(lik="gauss_linear")
+    raw = draw(w)
+    f_true, a_obs, sl = epo.simulate(cfg, raw)
+    ep = epo.DenseEP(cfg, raw["xyz"], a_obs, raw["sigma"], sightlines=sl)
+    ep.sweep()
+    # sites equal the likelihood exactly
+    assert np.allclose(ep.tau, 1.0 / raw["sigma"] ** 2, rtol=1e-9)
+    assert np.allclose(ep.nu, a_obs / raw["sigma"] ** 2, rtol=1e-8, atol=1e-8)
+    # posterior = m + K H^T (H K H^T + S)^{-1} (y - c - H m), K = Q0^{-1}
+    gval, _, c = sl.linearise(np.full(sl.grid.N, cfg["prior_mean"]))
+    H = sl.G_dense(gval)
+    K = np.linalg.inv(ep.Q0)
+    m = np.full(sl.grid.N, cfg["prior_mean"])
+    S = np.diag(raw["sigma"] ** 2)
+    M = H @ K @ H.T + S
+    mu = m + K @ H.T @ np.linalg.solve(M, a_obs - c - H @ m)
+    Sig = K - K @ H.T @ np.linalg.solve(M, H @ K)
+    assert np.allclose(ep.posterior_mean(), mu, rtol=1e-10, atol=1e-10)
+    assert np.allclose(ep.marginal_var(), np.diag(Sig), rtol=1e-9, atol=1e-12)
+    # a second sweep is a fixed point
+    tau, nu = ep.tau.copy(), ep.nu.copy()
+    ep.sweep()
+    assert np.allclose(ep.tau, tau, rtol=1e-8) and np.allclose(ep.nu, nu, rtol=1e-7, atol=1e-7)
+
+
+def test_one_star_frozen_projection_is_exact():
+    """One star, projection frozen at the prior mean: after one sweep EP holds
+    the exact posterior of f, by brute-force 1-D quadrature over s = g.f."""
+    w, cfg = _small(stars=1, relinearize=False)
+    raw = draw(w)
+    raw["xyz"] = np.array([[300.0, 420.0, 180.0]])
+    f_true, A_obs, sl = epo.simulate(cfg, raw)
+    ep = epo.DenseEP(cfg, raw["xyz"], A_obs, raw["sigma"], sightlines=sl)
+    ep.sweep()
+    mu_ep, Sig_ep, G, c = ep.posterior()
+    g = G[0]
+    K = np.linalg.inv(ep.Q0)
+    m = np.full(sl.grid.N, cfg["prior_mean"])
+    ms = c[0] + g @ m
+    vs = g @ K @ g
+    A, s = A_obs[0], raw["sigma"][0]
+    dens = lambda a: math.exp(-(a - ms) ** 2 / (2 * vs) - (A - math.exp(a)) ** 2 / (2 * s * s))
+    lo, hi = ms - 12 * math.sqrt(vs), ms + 12 * math.sqrt(vs)
+    Z = integrate.quad(dens, lo, hi, epsrel=1e-13, limit=500, points=[math.log(max(A, 1e-3))])[0]
+    Es = integrate.quad(lambda a: a * dens(a), lo, hi, epsrel=1e-13, limit=500,
+                        points=[math.log(max(A, 1e-3))])[0] / Z
+    Vs = integrate.quad(lambda a: (a - Es) ** 2 * dens(a), lo, hi, epsrel=1e-12, limit=500,
+                        points=[math.log(max(A, 1e-3))])[0] / Z
+    Kg = K @ g
+    mu_exact = m + Kg * (Es - ms) / vs
+    Sig_exact = K - np.outer(Kg, Kg) * (vs - Vs) / vs ** 2
+    assert np.allclose(mu_ep, mu_exact, rtol=1e-9, atol=1e-9)
+    assert np.allclose(np.diag(Sig_ep), np.diag(Sig_exact), rtol=1e-9, atol=1e-12)
+
+
+def test_moment_matching_invariant_at_convergence():
+    """At an EP fixed point the q-marginal of every a_n equals the moments of
+    its tilted distribution (App. A, moment matching)."""
+    w, cfg = _small(stars=25, relinearize=False, damping=0.5)
+    raw = draw(w)
+    f_true, A_obs, sl = epo.simulate(cfg, raw)
+    ep = epo.DenseEP(cfg, raw["xyz"], A_obs, raw["sigma"], sightlines=sl)
+    for _ in range(80):
+        st = ep.sweep()
+    assert st["max_dtau"] < 1e-9
+    mu, Sig, G, c = ep.posterior()
+    qm = c + G @ mu
+    qv = np.einsum("ij,ij->i", G @ Sig, G)
+    # tilted moments from the same q
+    tau_c = 1 / qv - ep.tau
+    nu_c = qm / qv - ep.nu
+    _, mh, vh = epo.tilted(0, nu_c / tau_c, 1 / tau_c, A_obs, raw["sigma"])
+    assert np.allclose(qm, mh, rtol=1e-8, atol=1e-8)
+    assert np.allclose(qv, vh, rtol=1e-8)
+
+
+def test_calibration_of_posterior_on_true_field():
+    """z-scores of the true field under the EP posterior are roughly standard
+    normal where the data constrain it (cf. the residual histograms of Sec. 4)."""
+    w, cfg = _small(n=10, L=660.0, stars=400)
+    raw = draw(w)
+    f_true, A_obs, sl = epo.simulate(cfg, raw)
+    ep = epo.DenseEP(cfg, raw["xyz"], A_obs, raw["sigma"], sightlines=sl)
+    for _ in range(6):
+        ep.sweep()
+    mu = ep.posterior_mean()
+    var = ep.marginal_var()
+    z = (f_true - mu) / np.sqrt(var)
+    assert abs(np.mean(z)) < 0.3
+    assert 0.6 < np.std(z) < 1.4
+    assert np.all(var <= cfg["prior_var"] * 1.0001)   # data only shrink variance
+
+
+def test_site_update_algebra():
+    """Replacing a site by (tilted / cavity) gives back the tilted moments as the
+    new marginal when the projection is a single coordinate."""
+    tau_c, nu_c = 2.0, -1.2
+    _, mh, vh = epo.tilted(0, [nu_c / tau_c], [1 / tau_c], [0.4], [0.05])
+    tau_new = 1 / vh[0] - tau_c
+    nu_new = mh[0] / vh[0] - nu_c
+    assert 1 / (tau_c + tau_new) == pytest.approx(vh[0], rel=1e-14)
+    assert (nu_c + nu_new) / (tau_c + tau_new) == pytest.approx(mh[0], rel=1e-13)
