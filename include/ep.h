@@ -1,0 +1,195 @@
+/*
+ * ep.h -- C ABI of the MI355X expectation-propagation library for
+ * three-dimensional Gaussian-process extinction mapping.
+ *
+ * Method: Sale & Magorrian, "Large-scale three-dimensional Gaussian process
+ * extinction mapping" (arXiv:1708.09705).
+ *
+ * Model.  The unknown is the log extinction pseudo-density
+ * f(x) = ln(rho kappa)(x) (Sec. 4: dA/ds = rho kappa) on a regular n^3 grid.
+ * Its prior is a Gaussian process (Sec. 2) with a turbulence-shaped
+ * covariance (Sec. 1: Kolmogorov spectrum truncated at the outer scale, here
+ * a Matern nu = 1/3 kernel with length scale equal to the outer scale)
+ * tapered to a compact support and made sparse by a Vecchia
+ * (inverse-Cholesky) precision Q0.  Each star n at a known distance
+ * (Sec. 3, simplified case) has extinction A_n = integral of exp(f) along
+ * its sightline; its likelihood is N(A_obs_n | A_n, sigma_n^2).
+ *
+ * Inference is parallel expectation propagation (Sec. 3.1; App. A): one
+ * Gaussian site per star in a_n = ln A_n, cavity -> tilted -> moment
+ * matching, every site updated from the same posterior in a sweep.  The
+ * posterior precision Q = Q0 + sum_n tau_n g_n g_n^T is factored by a
+ * multifrontal Cholesky on the GPU; the posterior mean comes from the
+ * triangular solves and the marginal variances (Sec. 4: maps of marginal
+ * posterior mean and variance) from selected inversion.
+ *
+ * Conventions
+ *  - Every call returns an ep_status (0 = success).  On failure
+ *    ep_last_error(ctx) (or ep_last_error(NULL) for failures without a
+ *    context) holds a message.
+ *  - Host pointers unless stated otherwise.  The library copies every input
+ *    it keeps; the caller owns every buffer it passes.
+ *  - Grid node p = i + n (j + n k) sits at h (i, j, k), h = box/(n-1).
+ *  - Work runs on the context's HIP stream; calls return after completion.
+ *    A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef EP_H
+#define EP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EP_OK = 0,
+    EP_ERR_INVALID_ARG = -1, /* bad argument or configuration */
+    EP_ERR_OOM = -2,         /* device allocation failed or exceeded hbm_cap_bytes */
+    EP_ERR_NOT_PD = -3,      /* a pivot of the posterior precision was not positive */
+    EP_ERR_DEVICE = -4,      /* HIP runtime error */
+    EP_ERR_STATE = -5,       /* call not valid in the context's state */
+    EP_ERR_NUMERIC = -6      /* non-finite value in the sites or the posterior */
+} ep_status;
+
+typedef enum { EP_LIK_EXTINCTION = 0, EP_LIK_GAUSS_LINEAR = 1 } ep_likelihood;
+typedef enum { EP_PREC_FP64 = 0, EP_PREC_MIXED = 1 } ep_precision;
+typedef enum { EP_MOM_QUADRATURE = 0, EP_MOM_SURROGATE = 1 } ep_moments;
+
+typedef struct ep_config {
+    /* grid */
+    int32_t n;                 /* nodes per axis (>= 2) */
+    double box_pc;             /* cube side L in pc; nodes span [0, L]^3 */
+    double observer_pc[3];     /* observer position (the sightlines start here) */
+    /* prior on f = ln(rho kappa) */
+    double prior_mean;         /* constant mean m0, ln(mag/pc) */
+    double prior_var;          /* variance sigma_f^2 */
+    double outer_scale_pc;     /* Matern length scale (the outer scale) */
+    double support_pc;         /* taper radius r_s: covariance is 0 beyond it */
+    double vecchia_radius_pc;  /* conditioning radius rho; 0 means support_pc */
+    /* forward model */
+    double los_step_pc;        /* trapezoid steps are d/T <= this, T = ceil(d/step) */
+    /* modes */
+    int32_t likelihood;        /* ep_likelihood */
+    int32_t precision;         /* ep_precision */
+    int32_t moments;           /* ep_moments */
+    /* EP controls */
+    double damping;            /* delta in (0, 1]: site <- (1-delta) old + delta new */
+    double cavity_var_floor;   /* cavity variance floor (Sec. 4), 0 = none */
+    int32_t relinearize;       /* 1: relinearise each sweep at the posterior mean;
+                                  0: freeze g_n, c_n at the prior mean */
+    /* device */
+    int32_t device;            /* HIP device ordinal */
+    void *stream;              /* hipStream_t to run on; NULL = library-owned stream */
+    int32_t leaf_size;         /* ordering: largest dissection leaf (0 = 512) */
+    int64_t hbm_cap_bytes;     /* refuse to allocate more than this (0 = no cap) */
+} ep_config;
+
+typedef struct ep_sweep_stats {
+    double ms_linearise;       /* line-of-sight linearisation */
+    double ms_assemble;        /* Q and b assembly */
+    double ms_factor;          /* multifrontal Cholesky + diagonal-block inverses */
+    double ms_solve;           /* triangular solves -> posterior mean */
+    double ms_selinv;          /* selected inversion -> Sigma on the front pattern */
+    double ms_star;            /* per-star phase: cavity + tilted moments + site update */
+    double ms_total;           /* the whole sweep */
+    int64_t updated;           /* sites replaced */
+    int64_t skipped_cavity;    /* cavity precision <= 0 */
+    int64_t skipped_negsite;   /* new site precision < 0 or non-finite */
+    double max_dtau;           /* max |change of site precision| */
+    double max_dmu;            /* max |posterior mean - previous linearisation point| */
+} ep_sweep_stats;
+
+typedef struct ep_structure_stats {
+    int64_t n_nodes;
+    int64_t n_stars;
+    int64_t nnz_g;             /* total sightline support size */
+    int64_t n_fronts;
+    int32_t n_levels;
+    int64_t front_elems;       /* sum of m^2 over fronts (factor / Sigma storage) */
+    int64_t max_front;         /* largest front order */
+    double factor_flops;       /* partial Cholesky flops of all fronts */
+    double selinv_flops;       /* selected-inversion flops */
+    int64_t device_bytes;      /* bytes the context holds on the device */
+} ep_structure_stats;
+
+typedef struct ep_ctx ep_ctx;
+
+/* Fill *cfg with defaults: n=16, box 1000 pc, observer at the centre of the
+ * y=0 face, m0=-7, variance 1, outer scale 100 pc, support 150 pc,
+ * step 2 pc, extinction likelihood, FP64, quadrature, damping 1. */
+void ep_config_default(ep_config *cfg);
+
+/* Create a context: build the Vecchia prior, the sightline supports, the
+ * nested-dissection ordering and the front layout (host), upload the
+ * structure, and set every site to zero and the linearisation point to the
+ * prior mean.  xyz: n_stars x 3 positions (pc, cube frame) at known
+ * distances (Sec. 3); A_obs: observed extinction (mag; in the
+ * gauss_linear mode the observed log-extinction); sigma: 1-sigma noise
+ * (> 0).  Errors: INVALID_ARG (bad config, non-finite input, star outside
+ * the cube), OOM, DEVICE. */
+int ep_init(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *A_obs,
+            const double *sigma, ep_ctx **out);
+
+/* One parallel EP sweep (App. A, parallel procedure): linearise every
+ * sightline at the current point, assemble and factor the posterior
+ * precision, posterior mean and selected inverse, then for every star the
+ * cavity, the tilted moments (Sec. 3.1) and the damped site update; finally
+ * move the linearisation point to the posterior mean.  stats may be NULL.
+ * On NOT_PD or NUMERIC the sites and the linearisation point are left as
+ * they were before the call. */
+int ep_sweep(ep_ctx *ctx, ep_sweep_stats *stats);
+
+/* Posterior mean of f at every node (n^3 doubles, node order) with the
+ * current sites at the current linearisation point.  Changes no state. */
+int ep_posterior_mean(ep_ctx *ctx, double *out);
+
+/* Marginal posterior variance of f at every node (n^3 doubles). */
+int ep_marginal_var(ep_ctx *ctx, double *out);
+
+/* Release everything.  NULL is allowed. */
+void ep_free(ep_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the calling thread when ctx is
+ * NULL).  Never NULL. */
+const char *ep_last_error(const ep_ctx *ctx);
+
+/* Site natural parameters (tau_n, nu_n) per star: get copies them out, set
+ * replaces them (checkpoint / resume). */
+int ep_get_sites(ep_ctx *ctx, double *tau, double *nu);
+int ep_set_sites(ep_ctx *ctx, const double *tau, const double *nu);
+
+/* Linearisation point fhat (n^3 doubles). */
+int ep_get_linpoint(ep_ctx *ctx, double *f);
+int ep_set_linpoint(ep_ctx *ctx, const double *f);
+
+/* Per-star quantities of the last sweep: ln A_n at the linearisation
+ * point, cavity mean and variance of a_n, and the tilted moments
+ * (ln Z, mean, variance).  Each array has n_stars doubles; any may be
+ * NULL. */
+int ep_star_state(ep_ctx *ctx, double *lnA, double *cav_mu, double *cav_var, double *lnZ,
+                  double *tmean, double *tvar);
+
+/* Batch tilted moments (the per-star moment matching of Sec. 3.1), without
+ * a context.  mode: ep_likelihood.  Inputs and outputs: n doubles each,
+ * host memory. */
+int ep_tilted_moments(int32_t mode, int64_t n, const double *mu_c, const double *v_c,
+                      const double *A, const double *sigma, double *lnZ, double *mean,
+                      double *var, int32_t device);
+
+/* Synthetic observations with the library's own arithmetic (for
+ * benchmarks): f_true = m0 + (I-B)^{-1} D^{1/2} xi (exact draw from the
+ * Vecchia prior) and A_obs = A(f_true) + sigma * eps (extinction) or
+ * c_n + g_n.f_true + sigma * eps with g, c at the prior mean
+ * (gauss_linear).  xi: n^3 deviates; xyz, sigma, eps per star.  Outputs:
+ * f_true (n^3) and A_obs (n_stars), either may be NULL. */
+int ep_simulate(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *sigma,
+                const double *eps, const double *xi, double *f_true, double *A_obs);
+
+/* Structure and memory figures of a context. */
+int ep_structure(const ep_ctx *ctx, ep_structure_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EP_H */

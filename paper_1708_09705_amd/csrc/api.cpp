@@ -1,0 +1,1084 @@
+// C ABI of the EP library: context set-up (host analysis + device upload),
+// the sweep driver and the outputs.  Every numerical step of the sweep runs
+// in the HIP kernels of kernels.hip; the host only enqueues them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "kernels.h"
+#include "prior.h"
+#include "symbolic.h"
+
+using namespace ep;
+
+static thread_local std::string g_tls_err = "no error";
+
+namespace {
+
+struct Launch {   // a batch of implicitly enumerated tile tasks
+    int64_t be_off = 0;
+    int nbe = 0;
+    int64_t ntasks = 0;
+};
+struct FList {
+    int64_t off = 0;
+    int n = 0;
+};
+struct TaskRange {
+    int64_t off = 0;
+    int64_t n = 0;
+};
+struct LevelPlan {
+    std::vector<FList> potrf;   // per right-looking step
+    std::vector<Launch> trsm, syrk;
+    Launch extend;              // also the Sigma-gather enumeration
+    Launch fwd_xv, fwd_r, bwd_t, bwd_x;
+    FList fronts;
+    TaskRange selW, selS21, selS11;
+};
+
+}  // namespace
+
+struct ep_ctx {
+    ep_config cfg{};
+    GridGeom g;
+    PriorParams pp;
+    Stencil st;
+    Vecchia vec;
+    Supports sup;
+    Symbolic sym;
+    int64_t S = 0;
+    int max_support = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err = "no error";
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+
+    std::vector<int64_t> xoff;   // X block offset per front
+    double *d_fronts = nullptr, *d_X = nullptr, *d_W = nullptr;
+    int64_t W_elems = 0, X_elems = 0;
+    int64_t *d_off = nullptr, *d_first = nullptr, *d_rptr = nullptr, *d_xoff = nullptr;
+    int32_t *d_m = nullptr, *d_nv = nullptr, *d_nvpad = nullptr, *d_nr = nullptr, *d_parent = nullptr;
+    int32_t *d_rrows = nullptr, *d_relmap = nullptr, *d_perm = nullptr, *d_snode = nullptr;
+    int64_t *d_q0_dest = nullptr, *d_pad_dest = nullptr;
+    double* d_q0_val = nullptr;
+    int64_t n_q0 = 0, n_pad = 0;
+    int32_t* d_flists = nullptr;
+    BatchEnt* d_batches = nullptr;
+    GemmTask* d_tasks = nullptr;
+    int* d_err = nullptr;
+    double *d_xyz = nullptr, *d_A = nullptr, *d_sigma = nullptr, *d_g = nullptr, *d_lnA = nullptr, *d_c = nullptr;
+    double *d_tau = nullptr, *d_nu = nullptr, *d_cmu = nullptr, *d_cvar = nullptr, *d_lnZ = nullptr;
+    double *d_tmean = nullptr, *d_tvar = nullptr, *d_dtau = nullptr;
+    double *d_tau_bak = nullptr, *d_nu_bak = nullptr;
+    int64_t* d_sptr = nullptr;
+    int32_t *d_snodes = nullptr, *d_sloc = nullptr, *d_sord = nullptr, *d_sfront = nullptr, *d_nsamp = nullptr;
+    int32_t* d_status = nullptr;
+    double *d_fhat = nullptr, *d_b0 = nullptr, *d_borig = nullptr, *d_y = nullptr, *d_x = nullptr, *d_t = nullptr;
+    double *d_mu = nullptr, *d_var = nullptr;
+
+    std::vector<LevelPlan> levels;
+    std::vector<TaskRange> trtri1, trtri2;   // per doubling stage
+    bool linearised = false;                 // g, c valid for the current fhat (frozen modes)
+
+    FrontsDev F{};
+    StarsDev SD{};
+    GridDev GD{};
+};
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ctx->err = std::string("HIP error ") + hipGetErrorString(e_) + " at " #expr; \
+            return EP_ERR_DEVICE;                                                        \
+        }                                                                                \
+    } while (0)
+
+#define TRY(x)                      \
+    do {                            \
+        int r_ = (x);               \
+        if (r_ != EP_OK) return r_; \
+    } while (0)
+
+template <class T>
+static int dev_alloc(ep_ctx* ctx, T** p, int64_t count) {
+    int64_t bytes = std::max<int64_t>(count, 1) * (int64_t)sizeof(T);
+    if (ctx->cfg.hbm_cap_bytes > 0 && ctx->dev_bytes + bytes > ctx->cfg.hbm_cap_bytes) {
+        ctx->err = "device allocation of " + std::to_string(bytes) + " bytes exceeds hbm_cap_bytes";
+        return EP_ERR_OOM;
+    }
+    hipError_t e = hipMalloc((void**)p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+        return EP_ERR_OOM;
+    }
+    ctx->dev_bytes += bytes;
+    ctx->allocs.push_back((void*)*p);
+    return EP_OK;
+}
+
+template <class T>
+static int upload(ep_ctx* ctx, T** p, const std::vector<T>& v) {
+    TRY(dev_alloc(ctx, p, (int64_t)v.size()));
+    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EP_OK;
+}
+
+static int32_t front_local(const Symbolic& sym, const Front& f, int64_t newidx) {
+    if (newidx >= f.first && newidx < f.first + f.nv) return (int32_t)(newidx - f.first);
+    const int64_t* b = sym.rrows.data() + f.rptr;
+    const int64_t* e = b + f.nr;
+    const int64_t* it = std::lower_bound(b, e, newidx);
+    if (it == e || *it != newidx) return -1;
+    return f.nvpad + (int32_t)(it - b);
+}
+
+static GemmSeg mkseg(int bufA, int64_t a, int64_t sa, int lda, bool ta, bool neg, int bufB, int64_t b, int64_t sb,
+                     int ldb, bool tb, int nk) {
+    GemmSeg s{};
+    s.a = a;
+    s.sa = sa;
+    s.lda = lda;
+    s.b = b;
+    s.sb = sb;
+    s.ldb = ldb;
+    s.nk = nk;
+    s.flags = (ta ? 1 : 0) | (tb ? 2 : 0) | (neg ? 4 : 0) | (bufA << 8) | (bufB << 10);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Schedules.  All tile addresses are absolute element offsets into their
+// buffer (fronts, X = diagonal-block inverses, W = scratch).
+//   front f, tile (i, j):       off_f + 64 i + 64 j m_f
+//   X block of f, tile (i, j):  xoff_f + 64 i + 64 j nvpad_f
+// ---------------------------------------------------------------------------
+static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<BatchEnt>& batches,
+                       std::vector<GemmTask>& tasks) {
+    const Symbolic& sym = ctx->sym;
+    const int64_t nf = (int64_t)sym.fronts.size();
+    const int L = sym.nlevels;
+    // X layout
+    ctx->xoff.assign(nf, 0);
+    int64_t xo = 0;
+    for (int64_t f = 0; f < nf; f++) {
+        ctx->xoff[f] = xo;
+        xo += (int64_t)sym.fronts[f].nvpad * sym.fronts[f].nvpad;
+    }
+    ctx->X_elems = std::max<int64_t>(xo, 1);
+    std::vector<std::vector<int32_t>> lv(L);
+    for (int64_t f = 0; f < nf; f++) lv[sym.fronts[f].level].push_back((int32_t)f);
+    auto P_of = [&](int f) { return sym.fronts[f].nvpad / TS; };
+    auto M_of = [&](int f) { return sym.fronts[f].m / TS; };
+    auto MR_of = [&](int f) { return (sym.fronts[f].nr + TS - 1) / TS; };
+    auto mk_launch = [&](const std::vector<std::pair<int, int64_t>>& fc) {
+        Launch l;
+        l.be_off = (int64_t)batches.size();
+        int64_t base = 0;
+        for (auto& x : fc) {
+            if (x.second <= 0) continue;
+            BatchEnt e{};
+            e.front = x.first;
+            e.base = base;
+            batches.push_back(e);
+            base += x.second;
+        }
+        l.nbe = (int)((int64_t)batches.size() - l.be_off);
+        l.ntasks = base;
+        return l;
+    };
+    ctx->levels.assign(L, LevelPlan{});
+    int64_t Wmax = 0;
+    for (int l = 0; l < L; l++) {
+        LevelPlan& P = ctx->levels[l];
+        int Pmax = 0;
+        for (int f : lv[l]) Pmax = std::max(Pmax, P_of(f));
+        for (int k = 0; k < Pmax; k++) {
+            FList fl;
+            fl.off = (int64_t)flists.size();
+            std::vector<std::pair<int, int64_t>> tr, sy;
+            for (int f : lv[l]) {
+                if (P_of(f) <= k) continue;
+                flists.push_back(f);
+                int64_t T = M_of(f) - k - 1;
+                tr.emplace_back(f, T);
+                sy.emplace_back(f, T * (T + 1) / 2);
+            }
+            fl.n = (int)((int64_t)flists.size() - fl.off);
+            P.potrf.push_back(fl);
+            P.trsm.push_back(mk_launch(tr));
+            P.syrk.push_back(mk_launch(sy));
+        }
+        std::vector<std::pair<int, int64_t>> ea, fx, fr;
+        for (int f : lv[l]) {
+            int64_t MR = MR_of(f);
+            if (sym.fronts[f].parent >= 0) ea.emplace_back(f, MR * (MR + 1) / 2);
+            fx.emplace_back(f, P_of(f));
+            fr.emplace_back(f, MR);
+        }
+        P.extend = mk_launch(ea);
+        P.fwd_xv = mk_launch(fx);
+        P.fwd_r = mk_launch(fr);
+        P.bwd_t = mk_launch(fx);
+        P.bwd_x = mk_launch(fx);
+        P.fronts.off = (int64_t)flists.size();
+        for (int f : lv[l]) flists.push_back(f);
+        P.fronts.n = (int)lv[l].size();
+
+        // ---- selected inversion of the level's fronts ----
+        //   W    = L21 X                  (R x V, scratch)
+        //   S21  = -S22 W                 (overwrites L21)
+        //   S11  = X^T X - W^T S21        (overwrites L11)
+        std::vector<int64_t> wbase(lv[l].size());
+        int64_t wb = 0;
+        for (size_t q = 0; q < lv[l].size(); q++) {
+            wbase[q] = wb;
+            wb += (int64_t)TS * MR_of(lv[l][q]) * (int64_t)sym.fronts[lv[l][q]].nvpad;
+        }
+        Wmax = std::max(Wmax, wb);
+        P.selW.off = (int64_t)tasks.size();
+        for (size_t q = 0; q < lv[l].size(); q++) {
+            const int f = lv[l][q];
+            const Front& Fr = sym.fronts[f];
+            const int Pf = P_of(f), MR = MR_of(f);
+            const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
+            for (int i = 0; i < MR; i++)
+                for (int k = 0; k < Pf; k++) {
+                    GemmTask t{};
+                    t.c = wbase[q] + TS * i + TS * k * ldw;
+                    t.ldc = (int32_t)ldw;
+                    t.flags = 1 | (1 << 4) | (BUF_W << 8);
+                    // sum_{j=k}^{P-1} L(R_i, j) X(j, k)
+                    t.s[0] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
+                                   xb + TS * k + TS * k * nvp, TS, (int)nvp, false, Pf - k);
+                    tasks.push_back(t);
+                }
+        }
+        P.selW.n = (int64_t)tasks.size() - P.selW.off;
+        P.selS21.off = (int64_t)tasks.size();
+        for (size_t q = 0; q < lv[l].size(); q++) {
+            const int f = lv[l][q];
+            const Front& Fr = sym.fronts[f];
+            const int Pf = P_of(f), MR = MR_of(f);
+            const int64_t ldw = (int64_t)TS * MR, m = Fr.m, nvp = Fr.nvpad;
+            for (int i = 0; i < MR; i++)
+                for (int k = 0; k < Pf; k++) {
+                    GemmTask t{};
+                    t.c = Fr.off + nvp + TS * i + TS * k * m;
+                    t.ldc = (int32_t)m;
+                    int nseg = 0;
+                    // l <= i: S22 tile (i, l) as stored
+                    t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * i + nvp * m, TS * m, (int)m, false, true, BUF_W,
+                                        wbase[q] + TS * k * ldw, TS, (int)ldw, false, i + 1);
+                    // l > i: S22 tile (l, i) transposed
+                    if (i + 1 < MR)
+                        t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * (i + 1) + (nvp + TS * i) * m, TS, (int)m,
+                                            true, true, BUF_W, wbase[q] + TS * (i + 1) + TS * k * ldw, TS, (int)ldw,
+                                            false, MR - i - 1);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8);
+                    tasks.push_back(t);
+                }
+        }
+        P.selS21.n = (int64_t)tasks.size() - P.selS21.off;
+        P.selS11.off = (int64_t)tasks.size();
+        for (size_t q = 0; q < lv[l].size(); q++) {
+            const int f = lv[l][q];
+            const Front& Fr = sym.fronts[f];
+            const int Pf = P_of(f), MR = MR_of(f);
+            const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
+            for (int k = 0; k < Pf; k++)
+                for (int j = 0; j <= k; j++) {
+                    GemmTask t{};
+                    t.c = Fr.off + TS * k + TS * j * m;
+                    t.ldc = (int32_t)m;
+                    int nseg = 0;
+                    // sum_{r=k}^{P-1} X(r, k)^T X(r, j)
+                    t.s[nseg++] = mkseg(BUF_X, xb + TS * k + TS * k * nvp, TS, (int)nvp, true, false, BUF_X,
+                                        xb + TS * k + TS * j * nvp, TS, (int)nvp, false, Pf - k);
+                    // - sum_i W(i, k)^T S21(i, j)
+                    if (MR > 0)
+                        t.s[nseg++] = mkseg(BUF_W, wbase[q] + TS * k * ldw, TS, (int)ldw, true, true, BUF_FRONTS,
+                                            Fr.off + nvp + TS * j * m, TS, (int)m, false, MR);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8);
+                    tasks.push_back(t);
+                }
+        }
+        P.selS11.n = (int64_t)tasks.size() - P.selS11.off;
+    }
+    // ---- inverse of each L11 by doubling over all fronts ----
+    // blocks [t0, b0) (top, inverted) and [b0, b1) (bottom, inverted):
+    //   T   = L(bot, top) X(top, top)        (scratch W)
+    //   X21 = - X(bot, bot) T
+    int64_t Tmax = 0;
+    int Pall = 0;
+    for (int64_t f = 0; f < nf; f++) Pall = std::max(Pall, P_of((int)f));
+    for (int b = 1; b < Pall; b *= 2) {
+        std::vector<std::tuple<int, int, int, int, int64_t>> pairs;
+        int64_t tb = 0;
+        for (int64_t f = 0; f < nf; f++) {
+            const int Pf = P_of((int)f);
+            for (int t0 = 0; t0 + b < Pf; t0 += 2 * b) {
+                const int b0 = t0 + b, b1 = std::min(t0 + 2 * b, Pf);
+                pairs.emplace_back((int)f, t0, b0, b1, tb);
+                tb += (int64_t)(b1 - b0) * TS * (int64_t)b * TS;
+            }
+        }
+        Tmax = std::max(Tmax, tb);
+        TaskRange r1, r2;
+        r1.off = (int64_t)tasks.size();
+        for (auto& pr : pairs) {
+            int f, t0, b0, b1;
+            int64_t tbase;
+            std::tie(f, t0, b0, b1, tbase) = pr;
+            const Front& Fr = sym.fronts[f];
+            const int64_t ldt = (int64_t)TS * (b1 - b0), m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
+            for (int i = b0; i < b1; i++)
+                for (int k = t0; k < b0; k++) {
+                    GemmTask t{};
+                    t.c = tbase + TS * (i - b0) + TS * (k - t0) * ldt;
+                    t.ldc = (int32_t)ldt;
+                    t.flags = 1 | (1 << 4) | (BUF_W << 8);
+                    // sum_{j=k}^{b0-1} L(i, j) X(j, k)
+                    t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
+                                   xb + TS * k + TS * k * nvp, TS, (int)nvp, false, b0 - k);
+                    tasks.push_back(t);
+                }
+        }
+        r1.n = (int64_t)tasks.size() - r1.off;
+        r2.off = (int64_t)tasks.size();
+        for (auto& pr : pairs) {
+            int f, t0, b0, b1;
+            int64_t tbase;
+            std::tie(f, t0, b0, b1, tbase) = pr;
+            const Front& Fr = sym.fronts[f];
+            const int64_t ldt = (int64_t)TS * (b1 - b0), xb = ctx->xoff[f], nvp = Fr.nvpad;
+            for (int i = b0; i < b1; i++)
+                for (int k = t0; k < b0; k++) {
+                    GemmTask t{};
+                    t.c = xb + TS * i + TS * k * nvp;
+                    t.ldc = (int32_t)nvp;
+                    t.flags = 1 | (1 << 4) | (BUF_X << 8);
+                    // - sum_{j=b0}^{i} X(i, j) T(j, k)
+                    t.s[0] = mkseg(BUF_X, xb + TS * i + TS * b0 * nvp, TS * nvp, (int)nvp, false, true, BUF_W,
+                                   tbase + TS * (k - t0) * ldt, TS, (int)ldt, false, i - b0 + 1);
+                    tasks.push_back(t);
+                }
+        }
+        r2.n = (int64_t)tasks.size() - r2.off;
+        ctx->trtri1.push_back(r1);
+        ctx->trtri2.push_back(r2);
+    }
+    ctx->W_elems = std::max<int64_t>(std::max(Wmax, Tmax), 1);
+    return EP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+static int validate(const ep_config* c, int64_t S, const double* xyz, const double* A, const double* sig,
+                    std::string& err) {
+    if (!c) { err = "cfg is NULL"; return EP_ERR_INVALID_ARG; }
+    if (c->n < 2 || c->n > 1290) { err = "n must be in [2, 1290]"; return EP_ERR_INVALID_ARG; }
+    if (!(c->box_pc > 0)) { err = "box_pc must be > 0"; return EP_ERR_INVALID_ARG; }
+    if (!(c->prior_var > 0) || !(c->outer_scale_pc > 0) || !(c->support_pc > 0)) {
+        err = "prior_var, outer_scale_pc and support_pc must be > 0";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (!(c->los_step_pc > 0)) { err = "los_step_pc must be > 0"; return EP_ERR_INVALID_ARG; }
+    if (!(c->damping > 0 && c->damping <= 1)) { err = "damping must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
+    if (c->likelihood != EP_LIK_EXTINCTION && c->likelihood != EP_LIK_GAUSS_LINEAR) {
+        err = "unknown likelihood";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (c->precision != EP_PREC_FP64) { err = "only the FP64 precision mode is available"; return EP_ERR_INVALID_ARG; }
+    if (c->moments != EP_MOM_QUADRATURE) { err = "only quadrature moments are available"; return EP_ERR_INVALID_ARG; }
+    for (int a = 0; a < 3; a++)
+        if (!(c->observer_pc[a] >= 0 && c->observer_pc[a] <= c->box_pc)) {
+            err = "observer must lie in the cube";
+            return EP_ERR_INVALID_ARG;
+        }
+    if (S < 0 || (S > 0 && (!xyz || !A || !sig))) { err = "bad star arrays"; return EP_ERR_INVALID_ARG; }
+    for (int64_t s = 0; s < S; s++) {
+        for (int a = 0; a < 3; a++)
+            if (!std::isfinite(xyz[3 * s + a]) || xyz[3 * s + a] < 0 || xyz[3 * s + a] > c->box_pc) {
+                err = "star " + std::to_string(s) + " lies outside the cube or is not finite";
+                return EP_ERR_INVALID_ARG;
+            }
+        if (!std::isfinite(A[s])) { err = "A_obs of star " + std::to_string(s) + " is not finite"; return EP_ERR_INVALID_ARG; }
+        if (!(sig[s] > 0) || !std::isfinite(sig[s])) {
+            err = "sigma of star " + std::to_string(s) + " must be finite and > 0";
+            return EP_ERR_INVALID_ARG;
+        }
+    }
+    return EP_OK;
+}
+
+static void geom_from_cfg(const ep_config* c, GridGeom& g, PriorParams& p) {
+    g.n = c->n;
+    g.L = c->box_pc;
+    g.h = c->box_pc / (c->n - 1);
+    for (int a = 0; a < 3; a++) g.obs[a] = c->observer_pc[a];
+    g.step = c->los_step_pc;
+    p.mean = c->prior_mean;
+    p.var = c->prior_var;
+    p.ell = c->outer_scale_pc;
+    p.support = c->support_pc;
+    p.rho = c->vecchia_radius_pc > 0 ? c->vecchia_radius_pc : c->support_pc;
+}
+
+static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const double* sig) {
+    const ep_config& c = ctx->cfg;
+    geom_from_cfg(&c, ctx->g, ctx->pp);
+    HIPCHK(hipSetDevice(c.device));
+    if (c.stream) {
+        ctx->stream = (hipStream_t)c.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    const GridGeom& g = ctx->g;
+    const int64_t N = g.N();
+    const int64_t S = ctx->S;
+    build_stencil(g, ctx->pp.rho, ctx->st);
+    if (build_vecchia(g, ctx->pp, ctx->st, ctx->vec) != 0) {
+        ctx->err = "Vecchia conditional covariance is not positive definite";
+        return EP_ERR_NUMERIC;
+    }
+    build_supports(g, S, xyz, ctx->sup);
+    ctx->max_support = 0;
+    for (int64_t s = 0; s < S; s++)
+        ctx->max_support = std::max<int>(ctx->max_support, (int)(ctx->sup.ptr[s + 1] - ctx->sup.ptr[s]));
+    if (ctx->max_support > 1300) {
+        ctx->err = "a sightline touches more than 1300 nodes";
+        return EP_ERR_INVALID_ARG;
+    }
+    OrderingOpts opt;
+    opt.leaf_size = c.leaf_size > 0 ? c.leaf_size : 512;
+    opt.sep_halfwidth = ctx->pp.rho * (1.0 + 1e-9);
+    opt.tile = TS;
+    int rc = analyse(g, ctx->st, ctx->sup, opt, ctx->sym);
+    if (rc != 0) {
+        ctx->err = "symbolic analysis failed (" + std::to_string(rc) + ")";
+        return EP_ERR_STATE;
+    }
+    const Symbolic& sym = ctx->sym;
+    const int64_t nf = (int64_t)sym.fronts.size();
+    // schedules
+    std::vector<int32_t> flists;
+    std::vector<BatchEnt> batches;
+    std::vector<GemmTask> tasks;
+    TRY(build_plans(ctx, flists, batches, tasks));
+    // Q0 entries -> front positions
+    Q0Table q0;
+    build_q0(g, ctx->st, ctx->vec, q0);
+    std::vector<int64_t> q0dest;
+    std::vector<double> q0val;
+    q0dest.reserve((size_t)N * q0.nlower / 2);
+    q0val.reserve((size_t)N * q0.nlower / 2);
+    const int n = g.n;
+    for (int64_t p = 0; p < N; p++) {
+        int64_t i = p % n, j = (p / n) % n, k = p / ((int64_t)n * n);
+        for (int o = 0; o < q0.nlower; o++) {
+            double v = q0.val[(size_t)p * q0.nlower + o];
+            if (v == 0.0) continue;
+            int64_t ii = i + q0.lower[3 * o], jj = j + q0.lower[3 * o + 1], kk = k + q0.lower[3 * o + 2];
+            if (ii < 0 || jj < 0 || kk < 0 || ii >= n || jj >= n || kk >= n) continue;
+            int64_t q = ii + (int64_t)n * (jj + (int64_t)n * kk);
+            int64_t a = sym.iperm[p], b = sym.iperm[q];
+            int64_t lo = std::min(a, b), hi = std::max(a, b);
+            const Front& Fr = sym.fronts[sym.snode[lo]];
+            int32_t row = front_local(sym, Fr, hi);
+            if (row < 0) {
+                ctx->err = "prior stencil entry outside the front structure";
+                return EP_ERR_STATE;
+            }
+            q0dest.push_back(Fr.off + row + (lo - Fr.first) * (int64_t)Fr.m);
+            q0val.push_back(v);
+        }
+    }
+    std::vector<int64_t> paddest;
+    for (int64_t f = 0; f < nf; f++) {
+        const Front& Fr = sym.fronts[f];
+        for (int l = Fr.nv; l < Fr.nvpad; l++) paddest.push_back(Fr.off + l + (int64_t)l * Fr.m);
+    }
+    ctx->n_q0 = (int64_t)q0dest.size();
+    ctx->n_pad = (int64_t)paddest.size();
+    std::vector<double> b0;
+    q0_times_const(g, ctx->vec, ctx->pp.mean, b0);
+    // per-star slot order by local row
+    std::vector<int32_t> sord(ctx->sup.nodes.size());
+    for (int64_t s = 0; s < S; s++) {
+        int64_t p0 = ctx->sup.ptr[s];
+        int cnt = (int)(ctx->sup.ptr[s + 1] - p0);
+        std::vector<int32_t> idx(cnt);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return sym.star_loc[p0 + a] < sym.star_loc[p0 + b]; });
+        std::copy(idx.begin(), idx.end(), sord.begin() + p0);
+    }
+    // ---- device upload ----
+    std::vector<int64_t> off(nf), first(nf), rptr(nf);
+    std::vector<int32_t> m(nf), nv(nf), nvpad(nf), nr(nf), parent(nf);
+    for (int64_t f = 0; f < nf; f++) {
+        const Front& Fr = sym.fronts[f];
+        off[f] = Fr.off; first[f] = Fr.first; rptr[f] = Fr.rptr;
+        m[f] = Fr.m; nv[f] = Fr.nv; nvpad[f] = Fr.nvpad; nr[f] = Fr.nr; parent[f] = Fr.parent;
+    }
+    std::vector<int32_t> rrows(sym.rrows.begin(), sym.rrows.end());
+    TRY(upload(ctx, &ctx->d_off, off));
+    TRY(upload(ctx, &ctx->d_first, first));
+    TRY(upload(ctx, &ctx->d_rptr, rptr));
+    TRY(upload(ctx, &ctx->d_xoff, ctx->xoff));
+    TRY(upload(ctx, &ctx->d_m, m));
+    TRY(upload(ctx, &ctx->d_nv, nv));
+    TRY(upload(ctx, &ctx->d_nvpad, nvpad));
+    TRY(upload(ctx, &ctx->d_nr, nr));
+    TRY(upload(ctx, &ctx->d_parent, parent));
+    TRY(upload(ctx, &ctx->d_rrows, rrows));
+    TRY(upload(ctx, &ctx->d_relmap, sym.relmap));
+    TRY(upload(ctx, &ctx->d_perm, sym.perm));
+    TRY(upload(ctx, &ctx->d_snode, sym.snode));
+    TRY(upload(ctx, &ctx->d_q0_dest, q0dest));
+    TRY(upload(ctx, &ctx->d_q0_val, q0val));
+    TRY(upload(ctx, &ctx->d_pad_dest, paddest));
+    TRY(upload(ctx, &ctx->d_flists, flists));
+    TRY(upload(ctx, &ctx->d_batches, batches));
+    TRY(upload(ctx, &ctx->d_tasks, tasks));
+    TRY(dev_alloc(ctx, &ctx->d_fronts, sym.total_elems));
+    TRY(dev_alloc(ctx, &ctx->d_X, ctx->X_elems));
+    TRY(dev_alloc(ctx, &ctx->d_W, ctx->W_elems));
+    TRY(dev_alloc(ctx, &ctx->d_err, 1));
+    // stars
+    std::vector<double> vx(xyz, xyz + 3 * S), vA(A, A + S), vs(sig, sig + S);
+    TRY(upload(ctx, &ctx->d_xyz, vx));
+    TRY(upload(ctx, &ctx->d_A, vA));
+    TRY(upload(ctx, &ctx->d_sigma, vs));
+    TRY(upload(ctx, &ctx->d_sptr, ctx->sup.ptr));
+    TRY(upload(ctx, &ctx->d_snodes, ctx->sup.nodes));
+    TRY(upload(ctx, &ctx->d_sloc, sym.star_loc));
+    TRY(upload(ctx, &ctx->d_sord, sord));
+    TRY(upload(ctx, &ctx->d_sfront, sym.star_front));
+    TRY(upload(ctx, &ctx->d_nsamp, ctx->sup.nsamp));
+    const int64_t nG = (int64_t)ctx->sup.nodes.size();
+    TRY(dev_alloc(ctx, &ctx->d_g, nG));
+    double** sarr[] = {&ctx->d_lnA, &ctx->d_c, &ctx->d_tau, &ctx->d_nu, &ctx->d_cmu, &ctx->d_cvar, &ctx->d_lnZ,
+                       &ctx->d_tmean, &ctx->d_tvar, &ctx->d_dtau, &ctx->d_tau_bak, &ctx->d_nu_bak};
+    for (auto p : sarr) {
+        TRY(dev_alloc(ctx, p, S));
+        launch_fill(ctx->stream, *p, S, 0.0);
+    }
+    TRY(dev_alloc(ctx, &ctx->d_status, S));
+    TRY(upload(ctx, &ctx->d_b0, b0));
+    double** varr[] = {&ctx->d_fhat, &ctx->d_borig, &ctx->d_y, &ctx->d_x, &ctx->d_t, &ctx->d_mu, &ctx->d_var};
+    for (auto p : varr) TRY(dev_alloc(ctx, p, N));
+    launch_fill(ctx->stream, ctx->d_fhat, N, ctx->pp.mean);
+    set_gauss_legendre(ctx->stream);
+
+    FrontsDev& F = ctx->F;
+    F.off = ctx->d_off; F.m = ctx->d_m; F.nv = ctx->d_nv; F.nvpad = ctx->d_nvpad; F.nr = ctx->d_nr;
+    F.first = ctx->d_first; F.rptr = ctx->d_rptr; F.parent = ctx->d_parent; F.xoff = ctx->d_xoff;
+    F.rrows = ctx->d_rrows; F.relmap = ctx->d_relmap;
+    StarsDev& SD = ctx->SD;
+    SD.n = S; SD.xyz = ctx->d_xyz; SD.A = ctx->d_A; SD.sigma = ctx->d_sigma; SD.ptr = ctx->d_sptr;
+    SD.nodes = ctx->d_snodes; SD.loc = ctx->d_sloc; SD.sord = ctx->d_sord; SD.front = ctx->d_sfront;
+    SD.nsamp = ctx->d_nsamp; SD.g = ctx->d_g; SD.lnA = ctx->d_lnA; SD.c = ctx->d_c; SD.tau = ctx->d_tau;
+    SD.nu = ctx->d_nu; SD.cav_mu = ctx->d_cmu; SD.cav_var = ctx->d_cvar; SD.lnZ = ctx->d_lnZ;
+    SD.tmean = ctx->d_tmean; SD.tvar = ctx->d_tvar; SD.status = ctx->d_status; SD.dtau = ctx->d_dtau;
+    GridDev& GD = ctx->GD;
+    GD.n = g.n; GD.h = g.h; GD.ox = g.obs[0]; GD.oy = g.obs[1]; GD.oz = g.obs[2];
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    // free host-side bulk no longer needed
+    std::vector<double>().swap(ctx->vec.val);
+    std::vector<int32_t>().swap(ctx->vec.col);
+    return EP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sweep pieces
+// ---------------------------------------------------------------------------
+static Bufs bufs(ep_ctx* ctx) { return Bufs{ctx->d_fronts, ctx->d_X, ctx->d_W}; }
+
+static bool frozen(const ep_ctx* ctx) {
+    return ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR || ctx->cfg.relinearize == 0;
+}
+
+static void enqueue_linearise(ep_ctx* ctx) {
+    if (frozen(ctx)) {
+        if (ctx->linearised) return;
+        // freeze at the prior mean
+        launch_fill(ctx->stream, ctx->d_t, ctx->g.N(), ctx->pp.mean);
+        launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_t, ctx->max_support);
+        ctx->linearised = true;
+        return;
+    }
+    launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
+}
+
+static void enqueue_assemble(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    launch_fill(st, ctx->d_fronts, ctx->sym.total_elems, 0.0);
+    launch_scatter_set(st, ctx->d_fronts, ctx->d_q0_dest, ctx->d_q0_val, ctx->n_q0);
+    launch_scatter_const(st, ctx->d_fronts, ctx->d_pad_dest, ctx->n_pad, 1.0);
+    launch_assemble_stars(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->max_support);
+    hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st);
+    launch_assemble_b(st, ctx->SD, ctx->d_borig);
+    launch_gather_perm(st, ctx->d_perm, ctx->d_borig, ctx->d_y, ctx->g.N());
+}
+
+static void enqueue_factor(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    Bufs b = bufs(ctx);
+    for (auto& P : ctx->levels) {
+        for (size_t k = 0; k < P.potrf.size(); k++) {
+            launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
+            const Launch& t = P.trsm[k];
+            launch_trsm_step(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
+            const Launch& s = P.syrk[k];
+            launch_syrk_step(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
+        }
+        const Launch& e = P.extend;
+        launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
+    }
+    for (size_t s = 0; s < ctx->trtri1.size(); s++) {
+        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri1[s].off, ctx->trtri1[s].n, b);
+        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri2[s].off, ctx->trtri2[s].n, b);
+    }
+}
+
+static void enqueue_solve(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    Bufs b = bufs(ctx);
+    for (auto& P : ctx->levels) {
+        launch_fwd_xv(st, ctx->d_batches + P.fwd_xv.be_off, P.fwd_xv.nbe, P.fwd_xv.ntasks, ctx->F, b, ctx->d_y,
+                      ctx->d_t);
+        launch_fwd_r(st, ctx->d_batches + P.fwd_r.be_off, P.fwd_r.nbe, P.fwd_r.ntasks, ctx->F, b, ctx->d_t,
+                     ctx->d_y);
+        launch_copy_v(st, ctx->d_flists + P.fronts.off, P.fronts.n, ctx->F, ctx->d_t, ctx->d_y);
+    }
+    for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
+        auto& P = ctx->levels[l];
+        launch_bwd_t(st, ctx->d_batches + P.bwd_t.be_off, P.bwd_t.nbe, P.bwd_t.ntasks, ctx->F, b, ctx->d_y, ctx->d_x,
+                     ctx->d_t);
+        launch_bwd_x(st, ctx->d_batches + P.bwd_x.be_off, P.bwd_x.nbe, P.bwd_x.ntasks, ctx->F, b, ctx->d_t,
+                     ctx->d_x);
+    }
+    launch_scatter_perm(st, ctx->d_perm, ctx->d_x, ctx->d_mu, ctx->g.N());
+}
+
+static void enqueue_selinv(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    Bufs b = bufs(ctx);
+    for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
+        auto& P = ctx->levels[l];
+        launch_sigma_gather(st, ctx->d_batches + P.extend.be_off, P.extend.nbe, P.extend.ntasks, ctx->F, b);
+        launch_gemm_tasks(st, ctx->d_tasks + P.selW.off, P.selW.n, b);
+        launch_gemm_tasks(st, ctx->d_tasks + P.selS21.off, P.selS21.n, b);
+        launch_gemm_tasks(st, ctx->d_tasks + P.selS11.off, P.selS11.n, b);
+    }
+}
+
+static int check_pivots(ep_ctx* ctx) {
+    int e = 0;
+    HIPCHK(hipMemcpyAsync(&e, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    if (e != 0) {
+        ctx->err = "posterior precision is not positive definite (front " + std::to_string(e - 1) + ")";
+        return EP_ERR_NOT_PD;
+    }
+    return EP_OK;
+}
+
+// linearise + assemble + factor (+ inverse of the diagonal blocks)
+static int run_factor(ep_ctx* ctx, hipEvent_t* ev) {
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int), st));
+    if (ev) HIPCHK(hipEventRecord(ev[0], st));
+    enqueue_linearise(ctx);
+    if (ev) HIPCHK(hipEventRecord(ev[1], st));
+    enqueue_assemble(ctx);
+    if (ev) HIPCHK(hipEventRecord(ev[2], st));
+    enqueue_factor(ctx);
+    if (ev) HIPCHK(hipEventRecord(ev[3], st));
+    return check_pivots(ctx);
+}
+
+static double ev_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
+static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->g.N(), S = ctx->S;
+    hipEvent_t ev[8];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() { for (int i = 0; i < 8; i++) hipEventDestroy(e[i]); }
+    } guard{ev};
+    TRY(run_factor(ctx, ev));
+    enqueue_solve(ctx);
+    HIPCHK(hipEventRecord(ev[4], st));
+    enqueue_selinv(ctx);
+    HIPCHK(hipEventRecord(ev[5], st));
+    // non-finite posterior mean -> NUMERIC, nothing changed
+    std::vector<double> mu(N), fh(N);
+    HIPCHK(hipMemcpyAsync(mu.data(), ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(fh.data(), ctx->d_fhat, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double dmu = 0;
+    for (int64_t i = 0; i < N; i++) {
+        if (!std::isfinite(mu[i])) {
+            ctx->err = "posterior mean is not finite";
+            return EP_ERR_NUMERIC;
+        }
+        dmu = std::max(dmu, std::fabs(mu[i] - fh[i]));
+    }
+    // per-star phase: cavity -> tilted -> site update
+    HIPCHK(hipMemcpyAsync(ctx->d_tau_bak, ctx->d_tau, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->d_nu_bak, ctx->d_nu, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipEventRecord(ev[6], st));
+    launch_cavity(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->d_mu, ctx->max_support);
+    EpParams p{ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR ? 1 : 0, ctx->cfg.damping, ctx->cfg.cavity_var_floor};
+    launch_tilted_update(st, ctx->SD, p);
+    HIPCHK(hipEventRecord(ev[7], st));
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> status(S);
+    std::vector<double> dtau(S), tau(S), nu(S);
+    HIPCHK(hipMemcpyAsync(status.data(), ctx->d_status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(dtau.data(), ctx->d_dtau, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(tau.data(), ctx->d_tau, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nu.data(), ctx->d_nu, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t s = 0; s < S; s++)
+        if (!std::isfinite(tau[s]) || !std::isfinite(nu[s])) {
+            HIPCHK(hipMemcpyAsync(ctx->d_tau, ctx->d_tau_bak, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(ctx->d_nu, ctx->d_nu_bak, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            ctx->err = "non-finite site after the update";
+            return EP_ERR_NUMERIC;
+        }
+    if (!frozen(ctx)) HIPCHK(hipMemcpyAsync(ctx->d_fhat, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+        stats->ms_linearise = ev_ms(ev[0], ev[1]);
+        stats->ms_assemble = ev_ms(ev[1], ev[2]);
+        stats->ms_factor = ev_ms(ev[2], ev[3]);
+        stats->ms_solve = ev_ms(ev[3], ev[4]);
+        stats->ms_selinv = ev_ms(ev[4], ev[5]);
+        stats->ms_star = ev_ms(ev[6], ev[7]);
+        stats->ms_total = ev_ms(ev[0], ev[7]);
+        stats->updated = stats->skipped_cavity = stats->skipped_negsite = 0;
+        stats->max_dtau = 0;
+        for (int64_t s = 0; s < S; s++) {
+            if (status[s] == 0) stats->updated++;
+            else if (status[s] == 1) stats->skipped_cavity++;
+            else stats->skipped_negsite++;
+            stats->max_dtau = std::max(stats->max_dtau, dtau[s]);
+        }
+        stats->max_dmu = dmu;
+    }
+    return EP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void ep_config_default(ep_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->n = 16;
+    c->box_pc = 1000.0;
+    c->observer_pc[0] = 500.0;
+    c->observer_pc[1] = 0.0;
+    c->observer_pc[2] = 500.0;
+    c->prior_mean = -7.0;
+    c->prior_var = 1.0;
+    c->outer_scale_pc = 100.0;
+    c->support_pc = 150.0;
+    c->vecchia_radius_pc = 0.0;
+    c->los_step_pc = 2.0;
+    c->likelihood = EP_LIK_EXTINCTION;
+    c->precision = EP_PREC_FP64;
+    c->moments = EP_MOM_QUADRATURE;
+    c->damping = 1.0;
+    c->cavity_var_floor = 0.0;
+    c->relinearize = 1;
+    c->device = 0;
+    c->stream = nullptr;
+    c->leaf_size = 0;
+    c->hbm_cap_bytes = 0;
+}
+
+void ep_free(ep_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (void* p : ctx->allocs) hipFree(p);
+    if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int ep_init(const ep_config* cfg, int64_t n_stars, const double* xyz, const double* A_obs, const double* sigma,
+            ep_ctx** out) {
+    if (!out) { g_tls_err = "out is NULL"; return EP_ERR_INVALID_ARG; }
+    *out = nullptr;
+    std::string err;
+    int rc = validate(cfg, n_stars, xyz, A_obs, sigma, err);
+    if (rc) { g_tls_err = err; return rc; }
+    ep_ctx* ctx = new ep_ctx();
+    ctx->cfg = *cfg;
+    ctx->S = n_stars;
+    try {
+        rc = init_impl(ctx, xyz, A_obs, sigma);
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        rc = EP_ERR_OOM;
+    }
+    if (rc) {
+        g_tls_err = ctx->err;
+        ep_free(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return EP_OK;
+}
+
+int ep_sweep(ep_ctx* ctx, ep_sweep_stats* stats) {
+    if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    return sweep_impl(ctx, stats);
+}
+
+int ep_posterior_mean(ep_ctx* ctx, double* out) {
+    if (!ctx || !out) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(run_factor(ctx, nullptr));
+    enqueue_solve(ctx);
+    HIPCHK(hipMemcpyAsync(out, ctx->d_mu, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    return EP_OK;
+}
+
+int ep_marginal_var(ep_ctx* ctx, double* out) {
+    if (!ctx || !out) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(run_factor(ctx, nullptr));
+    enqueue_selinv(ctx);
+    launch_diag(ctx->stream, ctx->d_perm, ctx->d_snode, ctx->F, ctx->d_fronts, ctx->d_var, ctx->g.N());
+    HIPCHK(hipMemcpyAsync(out, ctx->d_var, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    return EP_OK;
+}
+
+const char* ep_last_error(const ep_ctx* ctx) { return ctx ? ctx->err.c_str() : g_tls_err.c_str(); }
+
+int ep_get_sites(ep_ctx* ctx, double* tau, double* nu) {
+    if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
+    if (tau) HIPCHK(hipMemcpyAsync(tau, ctx->d_tau, sizeof(double) * ctx->S, hipMemcpyDeviceToHost, ctx->stream));
+    if (nu) HIPCHK(hipMemcpyAsync(nu, ctx->d_nu, sizeof(double) * ctx->S, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return EP_OK;
+}
+
+int ep_set_sites(ep_ctx* ctx, const double* tau, const double* nu) {
+    if (!ctx || !tau || !nu) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    for (int64_t s = 0; s < ctx->S; s++)
+        if (!std::isfinite(tau[s]) || !std::isfinite(nu[s])) {
+            ctx->err = "sites must be finite";
+            return EP_ERR_INVALID_ARG;
+        }
+    HIPCHK(hipMemcpyAsync(ctx->d_tau, tau, sizeof(double) * ctx->S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_nu, nu, sizeof(double) * ctx->S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return EP_OK;
+}
+
+int ep_get_linpoint(ep_ctx* ctx, double* f) {
+    if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipMemcpyAsync(f, ctx->d_fhat, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return EP_OK;
+}
+
+int ep_set_linpoint(ep_ctx* ctx, const double* f) {
+    if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    for (int64_t i = 0; i < ctx->g.N(); i++)
+        if (!std::isfinite(f[i])) { ctx->err = "linearisation point must be finite"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipMemcpyAsync(ctx->d_fhat, f, sizeof(double) * ctx->g.N(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return EP_OK;
+}
+
+int ep_star_state(ep_ctx* ctx, double* lnA, double* cav_mu, double* cav_var, double* lnZ, double* tmean,
+                  double* tvar) {
+    if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
+    const size_t b = sizeof(double) * ctx->S;
+    hipStream_t st = ctx->stream;
+    if (lnA) HIPCHK(hipMemcpyAsync(lnA, ctx->d_lnA, b, hipMemcpyDeviceToHost, st));
+    if (cav_mu) HIPCHK(hipMemcpyAsync(cav_mu, ctx->d_cmu, b, hipMemcpyDeviceToHost, st));
+    if (cav_var) HIPCHK(hipMemcpyAsync(cav_var, ctx->d_cvar, b, hipMemcpyDeviceToHost, st));
+    if (lnZ) HIPCHK(hipMemcpyAsync(lnZ, ctx->d_lnZ, b, hipMemcpyDeviceToHost, st));
+    if (tmean) HIPCHK(hipMemcpyAsync(tmean, ctx->d_tmean, b, hipMemcpyDeviceToHost, st));
+    if (tvar) HIPCHK(hipMemcpyAsync(tvar, ctx->d_tvar, b, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return EP_OK;
+}
+
+int ep_structure(const ep_ctx* ctx, ep_structure_stats* out) {
+    if (!ctx || !out) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    out->n_nodes = ctx->g.N();
+    out->n_stars = ctx->S;
+    out->nnz_g = (int64_t)ctx->sup.nodes.size();
+    out->n_fronts = (int64_t)ctx->sym.fronts.size();
+    out->n_levels = ctx->sym.nlevels;
+    out->front_elems = ctx->sym.total_elems;
+    out->max_front = ctx->sym.max_m;
+    out->factor_flops = ctx->sym.factor_flops;
+    out->selinv_flops = ctx->sym.selinv_flops;
+    out->device_bytes = ctx->dev_bytes;
+    return EP_OK;
+}
+
+int ep_tilted_moments(int32_t mode, int64_t n, const double* mu_c, const double* v_c, const double* A,
+                      const double* sigma, double* lnZ, double* mean, double* var, int32_t device) {
+    if (n < 0 || (n > 0 && (!mu_c || !v_c || !A || !sigma || !lnZ || !mean || !var))) {
+        g_tls_err = "bad arguments";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (mode != 0 && mode != 1) { g_tls_err = "unknown mode"; return EP_ERR_INVALID_ARG; }
+    for (int64_t i = 0; i < n; i++)
+        if (!(v_c[i] > 0) || !(sigma[i] > 0) || !std::isfinite(mu_c[i]) || !std::isfinite(A[i]) ||
+            !std::isfinite(v_c[i]) || !std::isfinite(sigma[i])) {
+            g_tls_err = "inputs must be finite with v_c > 0 and sigma > 0";
+            return EP_ERR_INVALID_ARG;
+        }
+    if (n == 0) return EP_OK;
+    if (hipSetDevice(device) != hipSuccess) { g_tls_err = "hipSetDevice failed"; return EP_ERR_DEVICE; }
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        g_tls_err = "stream creation failed";
+        return EP_ERR_DEVICE;
+    }
+    set_gauss_legendre(st);
+    double* d = nullptr;
+    const size_t b = sizeof(double) * n;
+    int rc = EP_OK;
+    if (hipMalloc((void**)&d, 7 * b) != hipSuccess) {
+        g_tls_err = "device allocation failed";
+        hipStreamDestroy(st);
+        return EP_ERR_OOM;
+    }
+    hipMemcpyAsync(d, mu_c, b, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(d + n, v_c, b, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(d + 2 * n, A, b, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(d + 3 * n, sigma, b, hipMemcpyHostToDevice, st);
+    launch_tilted_batch(st, mode, n, d, d + n, d + 2 * n, d + 3 * n, d + 4 * n, d + 5 * n, d + 6 * n);
+    hipMemcpyAsync(lnZ, d + 4 * n, b, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(mean, d + 5 * n, b, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(var, d + 6 * n, b, hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+        g_tls_err = "tilted-moment kernel failed";
+        rc = EP_ERR_DEVICE;
+    }
+    hipFree(d);
+    hipStreamDestroy(st);
+    return rc;
+}
+
+int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const double* sigma, const double* eps,
+                const double* xi, double* f_true, double* A_obs) {
+    std::vector<double> ones(std::max<int64_t>(n_stars, 1), 0.0);
+    std::string err;
+    std::vector<double> sg(sigma ? sigma : ones.data(), (sigma ? sigma : ones.data()) + n_stars);
+    for (auto& v : sg) if (!(v > 0)) v = 1.0;
+    int rc = validate(cfg, n_stars, xyz, ones.data(), sg.data(), err);
+    if (rc) { g_tls_err = err; return rc; }
+    if (!xi || (n_stars > 0 && (!sigma || !eps))) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    GridGeom g;
+    PriorParams pp;
+    geom_from_cfg(cfg, g, pp);
+    Stencil st;
+    build_stencil(g, pp.rho, st);
+    Vecchia v;
+    if (build_vecchia(g, pp, st, v) != 0) { g_tls_err = "Vecchia prior not positive definite"; return EP_ERR_NUMERIC; }
+    const int64_t N = g.N();
+    std::vector<double> f(N);
+    prior_draw(g, v, pp.mean, xi, f.data());
+    if (f_true) std::copy(f.begin(), f.end(), f_true);
+    if (!A_obs || n_stars == 0) return EP_OK;
+    // line-of-sight integrals on the GPU with the library's kernel
+    ep_config c2 = *cfg;
+    ep_ctx* ctx = new ep_ctx();
+    ctx->cfg = c2;
+    ctx->S = n_stars;
+    ctx->g = g;
+    ctx->pp = pp;
+    struct Del {
+        ep_ctx* c;
+        ~Del() { ep_free(c); }
+    } del{ctx};
+    HIPCHK(hipSetDevice(c2.device));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    ctx->own_stream = true;
+    build_supports(g, n_stars, xyz, ctx->sup);
+    int cap = 0;
+    for (int64_t s = 0; s < n_stars; s++) cap = std::max<int>(cap, (int)(ctx->sup.ptr[s + 1] - ctx->sup.ptr[s]));
+    if (cap > 1300) { g_tls_err = "a sightline touches more than 1300 nodes"; return EP_ERR_INVALID_ARG; }
+    std::vector<double> vx(xyz, xyz + 3 * n_stars);
+    TRY(upload(ctx, &ctx->d_xyz, vx));
+    TRY(upload(ctx, &ctx->d_sptr, ctx->sup.ptr));
+    TRY(upload(ctx, &ctx->d_snodes, ctx->sup.nodes));
+    TRY(upload(ctx, &ctx->d_nsamp, ctx->sup.nsamp));
+    TRY(dev_alloc(ctx, &ctx->d_g, (int64_t)ctx->sup.nodes.size()));
+    TRY(dev_alloc(ctx, &ctx->d_lnA, n_stars));
+    TRY(dev_alloc(ctx, &ctx->d_c, n_stars));
+    std::vector<double> field(N);
+    const bool gauss = cfg->likelihood == EP_LIK_GAUSS_LINEAR;
+    if (gauss) std::fill(field.begin(), field.end(), pp.mean);
+    else field = f;
+    TRY(upload(ctx, &ctx->d_fhat, field));
+    StarsDev SD{};
+    SD.n = n_stars; SD.xyz = ctx->d_xyz; SD.ptr = ctx->d_sptr; SD.nodes = ctx->d_snodes; SD.nsamp = ctx->d_nsamp;
+    SD.g = ctx->d_g; SD.lnA = ctx->d_lnA; SD.c = ctx->d_c;
+    GridDev GD{g.n, g.h, g.obs[0], g.obs[1], g.obs[2]};
+    launch_los(ctx->stream, GD, SD, ctx->d_fhat, cap);
+    std::vector<double> lnA(n_stars), cc(n_stars), gv(ctx->sup.nodes.size());
+    HIPCHK(hipMemcpyAsync(lnA.data(), ctx->d_lnA, sizeof(double) * n_stars, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(cc.data(), ctx->d_c, sizeof(double) * n_stars, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(gv.data(), ctx->d_g, sizeof(double) * gv.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    for (int64_t s = 0; s < n_stars; s++) {
+        double base;
+        if (gauss) {
+            base = cc[s];
+            for (int64_t e = ctx->sup.ptr[s]; e < ctx->sup.ptr[s + 1]; e++) base += gv[e] * f[ctx->sup.nodes[e]];
+        } else {
+            base = std::exp(lnA[s]);
+        }
+        A_obs[s] = base + sigma[s] * eps[s];
+    }
+    return EP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Device kernels of the EP sweep (gfx950) and their launch wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ep {
+
+constexpr int TS = 64;   // dense tile edge (doubles)
+
+// Base buffers a tile task may address.
+enum Buf : int { BUF_FRONTS = 0, BUF_X = 1, BUF_W = 2 };
+
+// One K-segment of a tile product: sum_t op(A_t) op(B_t), A_t = A + t*sa.
+struct GemmSeg {
+    int64_t a, b, sa, sb;
+    int32_t lda, ldb, nk;
+    int32_t flags;   // 1 transA, 2 transB, 4 negate; bits 8-9 buffer of A, 10-11 buffer of B
+};
+// C (64x64, column-major, ldc) = [C +] sum over segments.
+struct GemmTask {
+    int64_t c;
+    int32_t ldc;
+    int32_t flags;   // 1 overwrite (else accumulate), 2 atomic add; bits 4-5 nseg; bits 8-9 buffer of C
+    GemmSeg s[2];
+};
+
+// Front metadata (structure of arrays, device pointers).
+struct FrontsDev {
+    const int64_t* off;     // element offset of the front block
+    const int32_t* m;       // padded front order (leading dimension)
+    const int32_t* nv;
+    const int32_t* nvpad;
+    const int32_t* nr;
+    const int64_t* first;   // first new index of V
+    const int64_t* rptr;    // offset into rrows / relmap
+    const int32_t* parent;
+    const int64_t* xoff;    // offset of the nvpad x nvpad inverse block in X
+    const int32_t* rrows;   // R rows as new indices
+    const int32_t* relmap;  // R rows as local rows of the parent front
+};
+
+// Per-front task batch entry for implicitly enumerated tile tasks.
+struct BatchEnt {
+    int32_t front;
+    int32_t pad;
+    int64_t base;   // first task index of this front in the launch
+};
+
+struct Bufs {
+    double* fronts;
+    double* X;
+    double* W;
+};
+
+// ---- launch wrappers (all asynchronous on 'st') ----
+void launch_fill(hipStream_t st, double* p, int64_t n, double v);
+void launch_scatter_set(hipStream_t st, double* base, const int64_t* dest, const double* val, int64_t n);
+void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int64_t n, double v);
+
+void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b);
+void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
+void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
+void launch_syrk_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
+void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+
+// solves (vectors in the new node order)
+void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                   const double* y, double* t);
+void launch_fwd_r(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* t, double* y);
+void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y);
+void launch_bwd_t(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* y, const double* x, double* t);
+void launch_bwd_x(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* t, double* x);
+
+// star kernels
+struct StarsDev {
+    int64_t n;
+    const double* xyz;
+    const double* A;
+    const double* sigma;
+    const int64_t* ptr;
+    const int32_t* nodes;    // original node ids, sorted per star
+    const int32_t* loc;      // local row in the star's front, per slot
+    const int32_t* sord;     // slot order by ascending loc, per star (slot indices)
+    const int32_t* front;    // front per star
+    const int32_t* nsamp;    // trapezoid intervals per star
+    double* g;               // per slot
+    double* lnA;
+    double* c;
+    double* tau;
+    double* nu;
+    double* cav_mu;
+    double* cav_var;
+    double* lnZ;
+    double* tmean;
+    double* tvar;
+    int32_t* status;         // per star: 0 updated, 1 cavity skip, 2 negative site
+    double* dtau;            // per star |delta tau|
+};
+struct GridDev {
+    int n;
+    double h;
+    double ox, oy, oz;
+};
+void launch_los(hipStream_t st, GridDev g, StarsDev s, const double* f, int max_support);
+void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int max_support);
+void launch_assemble_b(hipStream_t st, StarsDev s, double* b);
+void launch_gather_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);
+void launch_scatter_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);
+void launch_diag(hipStream_t st, const int32_t* perm, const int32_t* snode, FrontsDev F, const double* fronts,
+                 double* var, int64_t n);
+void launch_cavity(hipStream_t st, StarsDev s, FrontsDev F, const double* fronts, const double* mu,
+                   int max_support);
+struct EpParams {
+    int mode;          // 0 extinction, 1 gaussian
+    double damping;
+    double vfloor;
+};
+void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p);
+void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
+                         const double* sig, double* lnZ, double* mean, double* var);
+void set_gauss_legendre(hipStream_t st);
+void launch_maxabs_diff(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
+
+}  // namespace ep

@@ -1,0 +1,1108 @@
+// Device kernels of the EP sweep for gfx950 (CDNA4, wave64).
+//
+// Dense linear algebra works on 64 x 64 FP64 tiles of the multifrontal
+// fronts.  Every tile product goes through one MFMA core
+// (v_mfma_f64_16x16x4f64: four waves, each owning a 32 x 32 quarter of the
+// output tile as 2 x 2 MFMA blocks), fed from LDS.  Tasks are either listed
+// explicitly (GemmTask) or enumerated implicitly from a per-front batch so a
+// right-looking Cholesky step over many fronts is one launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "kernels.h"
+
+namespace ep {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int LDP = TS + 1;   // padded LDS row (doubles)
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline int64_t batch_find(const BatchEnt* be, int nbe, int64_t t) {
+    int lo = 0, hi = nbe - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (be[mid].base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// t -> (i, j) with i >= j >= 0, row-major over the lower triangle
+__device__ inline void tri_decode(int64_t t, int& i, int& j) {
+    int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) r++;
+    while (r * (r + 1) / 2 > t) r--;
+    i = (int)r;
+    j = (int)(t - r * (r + 1) / 2);
+}
+
+__device__ inline double* buf_of(const Bufs& b, int id) {
+    return id == BUF_FRONTS ? b.fronts : (id == BUF_X ? b.X : b.W);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA tile core: acc += sum_t op(A_t) op(B_t) over nk tiles.
+// sA holds op(A) as [k][i], sB holds op(B) as [k][j] (row stride LDP).
+// ---------------------------------------------------------------------------
+__device__ inline void tile_load_A(double* sA, const double* A, int lda, bool ta, double sgn) {
+    const int tid = threadIdx.x;
+    if (!ta) {
+        const int i = tid & 63;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            int k = (tid >> 6) + 4 * r;
+            sA[k * LDP + i] = sgn * A[i + (int64_t)k * lda];
+        }
+    } else {
+        const int k = tid & 63;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            int i = (tid >> 6) + 4 * r;
+            sA[k * LDP + i] = sgn * A[k + (int64_t)i * lda];
+        }
+    }
+}
+
+__device__ inline void tile_load_B(double* sB, const double* B, int ldb, bool tb) {
+    const int tid = threadIdx.x;
+    if (!tb) {
+        const int k = tid & 63;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            int j = (tid >> 6) + 4 * r;
+            sB[k * LDP + j] = B[k + (int64_t)j * ldb];
+        }
+    } else {
+        const int j = tid & 63;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            int k = (tid >> 6) + 4 * r;
+            sB[k * LDP + j] = B[j + (int64_t)k * ldb];
+        }
+    }
+}
+
+__device__ inline void tile_mma(d4 acc[2][2], const double* sA, const double* sB) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+        const double* ra = sA + (kk + lk) * LDP;
+        const double* rb = sB + (kk + lk) * LDP;
+        double a0 = ra[wr + li], a1 = ra[wr + 16 + li];
+        double b0 = rb[wc + li], b1 = rb[wc + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+__device__ inline void seg_run(d4 acc[2][2], double* sA, double* sB, const double* A, int64_t sa, int lda,
+                               bool ta, double sgn, const double* B, int64_t sb, int ldb, bool tb, int nk) {
+    for (int t = 0; t < nk; t++) {
+        __syncthreads();
+        tile_load_A(sA, A + t * sa, lda, ta, sgn);
+        tile_load_B(sB, B + t * sb, ldb, tb);
+        __syncthreads();
+        tile_mma(acc, sA, sB);
+    }
+}
+
+// Write acc to C (mode: 0 accumulate, 1 overwrite, 2 atomic).  Uses sA as
+// staging for a coalesced column-major store.
+__device__ inline void tile_store(d4 acc[2][2], double* sC, double* C, int ldc, int mode) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                // v_mfma_f64_16x16x4f64 output: lane l, item r -> row l/16 + 4r, column l%16
+                int row = wr + 16 * bi + (lane >> 4) + 4 * r;
+                int col = wc + 16 * bj + (lane & 15);
+                sC[col * LDP + row] = acc[bi][bj][r];
+            }
+    __syncthreads();
+    const int row = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        int col = (threadIdx.x >> 6) + 4 * r;
+        double v = sC[col * LDP + row];
+        double* p = C + row + (int64_t)col * ldc;
+        if (mode == 1) *p = v;
+        else if (mode == 0) *p += v;
+        else atomicAdd(p, v);
+    }
+}
+
+__device__ inline void acc_zero(d4 acc[2][2]) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+__global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
+    __shared__ double sA[TS * LDP];
+    __shared__ double sB[TS * LDP];
+    const int64_t t = blockIdx.x;
+    if (t >= n) return;
+    const GemmTask T = tasks[t];
+    d4 acc[2][2];
+    acc_zero(acc);
+    const int nseg = (T.flags >> 4) & 3;
+    for (int s = 0; s < nseg; s++) {
+        const GemmSeg& S = T.s[s];
+        const double* A = buf_of(bufs, (S.flags >> 8) & 3) + S.a;
+        const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
+        seg_run(acc, sA, sB, A, S.sa, S.lda, S.flags & 1, (S.flags & 4) ? -1.0 : 1.0, B, S.sb, S.ldb,
+                (S.flags & 2) != 0, S.nk);
+    }
+    double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c;
+    int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
+    tile_store(acc, sA, C, T.ldc, mode);
+}
+
+void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gemm_tasks, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal tile: Cholesky of tile (k,k) of each listed front, and the
+// inverse of the factor (kept in X as the diagonal tile of L11^{-1}).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
+                                               int* err) {
+    __shared__ double L[TS * LDP];   // L[i * LDP + j], row-major
+    __shared__ double Xs[TS * LDP];
+    __shared__ int bad;
+    const int f = flist[blockIdx.x];
+    const int m = F.m[f];
+    double* A = bufs.fronts + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    {
+        const int i = tid & 63;
+        for (int r = 0; r < 16; r++) {
+            int j = (tid >> 6) + 4 * r;
+            L[i * LDP + j] = A[i + (int64_t)j * m];
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < TS; j++) {
+        if (tid == 0) {
+            double d = L[j * LDP + j];
+            if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
+            L[j * LDP + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double dj = L[j * LDP + j];
+        if (tid > j && tid < TS) L[tid * LDP + j] /= dj;
+        __syncthreads();
+        for (int idx = tid; idx < TS * TS; idx += 256) {
+            int i = idx >> 6, c = idx & 63;
+            if (c > j && i >= c) L[i * LDP + c] -= L[i * LDP + j] * L[c * LDP + j];
+        }
+        __syncthreads();
+    }
+    // inverse of the lower triangular factor, one column per thread
+    if (tid < TS) {
+        const int j = tid;
+        for (int i = 0; i < j; i++) Xs[i * LDP + j] = 0.0;
+        Xs[j * LDP + j] = 1.0 / L[j * LDP + j];
+        for (int i = j + 1; i < TS; i++) {
+            double s = 0.0;
+            for (int q = j; q < i; q++) s += L[i * LDP + q] * Xs[q * LDP + j];
+            Xs[i * LDP + j] = -s / L[i * LDP + i];
+        }
+    }
+    __syncthreads();
+    double* Xk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
+    const int ldx = F.nvpad[f];
+    {
+        const int i = tid & 63;
+        for (int r = 0; r < 16; r++) {
+            int j = (tid >> 6) + 4 * r;
+            A[i + (int64_t)j * m] = (i >= j) ? L[i * LDP + j] : 0.0;
+            Xk[i + (int64_t)j * ldx] = Xs[i * LDP + j];
+        }
+    }
+    if (tid == 0 && bad) atomicCAS(err, 0, f + 1);
+}
+
+void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(k_potrf, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
+}
+
+// ---------------------------------------------------------------------------
+// Right-looking step k, implicit tasks.
+//   trsm: L_ik = A_ik X_kk^T for row tiles i > k
+//   syrk: A_ij -= L_ik L_jk^T for i >= j > k
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trsm_step(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int k,
+                                                   FrontsDev F, Bufs bufs) {
+    __shared__ double sA[TS * LDP];
+    __shared__ double sB[TS * LDP];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int i = k + 1 + (int)(t - be[e].base);
+    const int m = F.m[f];
+    double* Aik = bufs.fronts + F.off[f] + (int64_t)TS * i + (int64_t)TS * k * m;
+    const double* Xkk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
+    d4 acc[2][2];
+    acc_zero(acc);
+    seg_run(acc, sA, sB, Aik, 0, m, false, 1.0, Xkk, 0, F.nvpad[f], true, 1);
+    tile_store(acc, sA, Aik, m, 1);
+}
+
+__global__ __launch_bounds__(256) void k_syrk_step(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int k,
+                                                   FrontsDev F, Bufs bufs) {
+    __shared__ double sA[TS * LDP];
+    __shared__ double sB[TS * LDP];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    int ii, jj;
+    tri_decode(t - be[e].base, ii, jj);
+    const int i = k + 1 + ii, j = k + 1 + jj;
+    const int m = F.m[f];
+    double* base = bufs.fronts + F.off[f];
+    d4 acc[2][2];
+    acc_zero(acc);
+    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k * m, 0, m, false, -1.0,
+            base + (int64_t)TS * j + (int64_t)TS * k * m, 0, m, true, 1);
+    tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
+}
+
+void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_trsm_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
+}
+void launch_syrk_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_syrk_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
+}
+
+// ---------------------------------------------------------------------------
+// Extend-add: the update block (R x R, lower) of each front is added into
+// its parent at the relative rows.  Sigma gather is the reverse copy of the
+// parent's selected inverse into the child's R x R block (both triangles of
+// diagonal tiles, zeros on padding).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_extend_add(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                    FrontsDev F, Bufs bufs) {
+    __shared__ int32_t rel_i[TS], rel_j[TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    int ti, tj;
+    tri_decode(t - be[e].base, ti, tj);
+    const int p = F.parent[f];
+    const int nr = F.nr[f], nvp = F.nvpad[f], m = F.m[f], mp = F.m[p];
+    const int32_t* rel = F.relmap + F.rptr[f];
+    if (threadIdx.x < TS) {
+        int a = TS * ti + threadIdx.x;
+        rel_i[threadIdx.x] = a < nr ? rel[a] : -1;
+    } else if (threadIdx.x < 2 * TS) {
+        int b = TS * tj + threadIdx.x - TS;
+        rel_j[threadIdx.x - TS] = b < nr ? rel[b] : -1;
+    }
+    __syncthreads();
+    const double* src = bufs.fronts + F.off[f] + nvp + (int64_t)nvp * m;
+    double* dst = bufs.fronts + F.off[p];
+    const int r = threadIdx.x & 63;
+    const int a = TS * ti + r;
+    if (rel_i[r] < 0) return;
+    for (int q = threadIdx.x >> 6; q < TS; q += 4) {
+        const int b = TS * tj + q;
+        if (rel_j[q] < 0 || b > a) continue;
+        atomicAdd(dst + rel_i[r] + (int64_t)rel_j[q] * mp, src[a + (int64_t)b * m]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sigma_gather(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                      FrontsDev F, Bufs bufs) {
+    __shared__ int32_t rel_i[TS], rel_j[TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    int ti, tj;
+    tri_decode(t - be[e].base, ti, tj);
+    const int p = F.parent[f];
+    const int nr = F.nr[f], nvp = F.nvpad[f], m = F.m[f], mp = F.m[p];
+    const int32_t* rel = F.relmap + F.rptr[f];
+    if (threadIdx.x < TS) {
+        int a = TS * ti + threadIdx.x;
+        rel_i[threadIdx.x] = a < nr ? rel[a] : -1;
+    } else if (threadIdx.x < 2 * TS) {
+        int b = TS * tj + threadIdx.x - TS;
+        rel_j[threadIdx.x - TS] = b < nr ? rel[b] : -1;
+    }
+    __syncthreads();
+    double* dst = bufs.fronts + F.off[f] + nvp + (int64_t)nvp * m;
+    const double* src = bufs.fronts + F.off[p];
+    const int r = threadIdx.x & 63;
+    const int a = TS * ti + r;
+    for (int q = threadIdx.x >> 6; q < TS; q += 4) {
+        const int b = TS * tj + q;
+        double v = 0.0;
+        if (rel_i[r] >= 0 && rel_j[q] >= 0) {
+            int ra = rel_i[r], rb = rel_j[q];
+            v = (ra >= rb) ? src[ra + (int64_t)rb * mp] : src[rb + (int64_t)ra * mp];
+        }
+        if (ti == tj) {
+            if (b <= a) { dst[a + (int64_t)b * m] = v; dst[b + (int64_t)a * m] = v; }
+        } else {
+            dst[a + (int64_t)b * m] = v;
+        }
+    }
+}
+
+void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_extend_add, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+}
+void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_sigma_gather, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves with the fronts.  Vectors are in the new node order.
+//   forward : z_V = X y_V ; y_R -= L21 z_V ; y_V = z_V
+//   backward: t_V = y_V - L21^T x_R ; x_V = X^T t_V
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fwd_xv(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                FrontsDev F, Bufs bufs, const double* __restrict__ y,
+                                                double* __restrict__ tout) {
+    __shared__ double v[TS];
+    __shared__ double part[4][TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int i = (int)(t - be[e].base);
+    const int nv = F.nv[f], ldx = F.nvpad[f];
+    const int64_t first = F.first[f];
+    const double* Xb = bufs.X + F.xoff[f];
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    double acc = 0.0;
+    for (int k = 0; k <= i; k++) {
+        __syncthreads();
+        if (threadIdx.x < TS) {
+            int l = TS * k + threadIdx.x;
+            v[threadIdx.x] = l < nv ? y[first + l] : 0.0;
+        }
+        __syncthreads();
+        const double* T = Xb + (int64_t)TS * i + (int64_t)TS * k * ldx;
+#pragma unroll
+        for (int c = 0; c < 16; c++) acc += T[r + (int64_t)(cg * 16 + c) * ldx] * v[cg * 16 + c];
+    }
+    part[cg][r] = acc;
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        int l = TS * i + threadIdx.x;
+        double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+        if (l < nv) tout[first + l] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                               FrontsDev F, Bufs bufs, const double* __restrict__ z,
+                                               double* __restrict__ y) {
+    __shared__ double v[TS];
+    __shared__ double part[4][TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int i = (int)(t - be[e].base);
+    const int nv = F.nv[f], nvp = F.nvpad[f], m = F.m[f], nr = F.nr[f];
+    const int64_t first = F.first[f];
+    const double* base = bufs.fronts + F.off[f];
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    double acc = 0.0;
+    const int P = nvp / TS;
+    for (int k = 0; k < P; k++) {
+        __syncthreads();
+        if (threadIdx.x < TS) {
+            int l = TS * k + threadIdx.x;
+            v[threadIdx.x] = l < nv ? z[first + l] : 0.0;
+        }
+        __syncthreads();
+        const double* T = base + nvp + (int64_t)TS * i + (int64_t)TS * k * m;
+#pragma unroll
+        for (int c = 0; c < 16; c++) acc += T[r + (int64_t)(cg * 16 + c) * m] * v[cg * 16 + c];
+    }
+    part[cg][r] = acc;
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        int a = TS * i + threadIdx.x;
+        double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+        if (a < nr) atomicAdd(y + F.rrows[F.rptr[f] + a], -s);
+    }
+}
+
+__global__ void k_copy_v(const int32_t* __restrict__ flist, FrontsDev F, const double* __restrict__ src,
+                         double* __restrict__ dst) {
+    const int f = flist[blockIdx.x];
+    const int64_t first = F.first[f];
+    for (int l = threadIdx.x; l < F.nv[f]; l += blockDim.x) dst[first + l] = src[first + l];
+}
+
+// transposed tile-vector product through LDS: out[c] += sum_r T[r][c] v[r]
+__device__ inline void tgemv_tile(double* sT, const double* T, int64_t ld, const double* v, double& acc) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    {
+        const int r = tid & 63;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            int c = (tid >> 6) + 4 * q;
+            sT[c * LDP + r] = T[r + (int64_t)c * ld];
+        }
+    }
+    __syncthreads();
+    const int c = tid & 63, rg = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < 16; q++) acc += sT[c * LDP + rg * 16 + q] * v[rg * 16 + q];
+}
+
+__global__ __launch_bounds__(256) void k_bwd_t(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                               FrontsDev F, Bufs bufs, const double* __restrict__ y,
+                                               const double* __restrict__ x, double* __restrict__ tout) {
+    __shared__ double sT[TS * LDP];
+    __shared__ double v[TS];
+    __shared__ double part[4][TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int k = (int)(t - be[e].base);
+    const int nv = F.nv[f], nvp = F.nvpad[f], m = F.m[f], nr = F.nr[f];
+    const int64_t first = F.first[f];
+    const double* base = bufs.fronts + F.off[f];
+    const int32_t* rows = F.rrows + F.rptr[f];
+    const int MR = (nr + TS - 1) / TS;
+    double acc = 0.0;
+    for (int i = 0; i < MR; i++) {
+        __syncthreads();
+        if (threadIdx.x < TS) {
+            int a = TS * i + threadIdx.x;
+            v[threadIdx.x] = a < nr ? x[rows[a]] : 0.0;
+        }
+        tgemv_tile(sT, base + nvp + (int64_t)TS * i + (int64_t)TS * k * m, m, v, acc);
+    }
+    const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    __syncthreads();
+    part[rg][c] = acc;
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        int l = TS * k + threadIdx.x;
+        double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+        if (l < nv) tout[first + l] = y[first + l] - s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_x(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                               FrontsDev F, Bufs bufs, const double* __restrict__ tin,
+                                               double* __restrict__ x) {
+    __shared__ double sT[TS * LDP];
+    __shared__ double v[TS];
+    __shared__ double part[4][TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int k = (int)(t - be[e].base);
+    const int nv = F.nv[f], nvp = F.nvpad[f];
+    const int64_t first = F.first[f];
+    const double* Xb = bufs.X + F.xoff[f];
+    const int P = nvp / TS;
+    double acc = 0.0;
+    for (int i = k; i < P; i++) {
+        __syncthreads();
+        if (threadIdx.x < TS) {
+            int l = TS * i + threadIdx.x;
+            v[threadIdx.x] = l < nv ? tin[first + l] : 0.0;
+        }
+        tgemv_tile(sT, Xb + (int64_t)TS * i + (int64_t)TS * k * nvp, nvp, v, acc);
+    }
+    const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    __syncthreads();
+    part[rg][c] = acc;
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        int l = TS * k + threadIdx.x;
+        double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+        if (l < nv) x[first + l] = s;
+    }
+}
+
+void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                   const double* y, double* t) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_fwd_xv, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, y, t);
+}
+void launch_fwd_r(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* t, double* y) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_fwd_r, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, t, y);
+}
+void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y) {
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(k_copy_v, dim3(nf), dim3(256), 0, st, flist, F, t, y);
+}
+void launch_bwd_t(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* y, const double* x, double* t) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_bwd_t, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, y, x, t);
+}
+void launch_bwd_x(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                  const double* t, double* x) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_bwd_x, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, t, x);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_scatter_set(double* base, const int64_t* dest, const double* val, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        base[dest[i]] = val[i];
+}
+__global__ void k_scatter_const(double* base, const int64_t* dest, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        base[dest[i]] = v;
+}
+__global__ void k_gather_perm(const int32_t* perm, const double* src, double* dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[perm[i]];
+}
+__global__ void k_scatter_perm(const int32_t* perm, const double* src, double* dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[perm[i]] = src[i];
+}
+__global__ void k_diag(const int32_t* perm, const int32_t* snode, FrontsDev F, const double* fronts, double* var,
+                       int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int f = snode[i];
+        int64_t l = i - F.first[f];
+        var[perm[i]] = fronts[F.off[f] + l + l * (int64_t)F.m[f]];
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+void launch_fill(hipStream_t st, double* p, int64_t n, double v) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_scatter_set(hipStream_t st, double* base, const int64_t* dest, const double* val, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_scatter_set, dim3(grid_for(n)), dim3(256), 0, st, base, dest, val, n);
+}
+void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int64_t n, double v) {
+    if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, st, base, dest, n, v);
+}
+void launch_gather_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(n)), dim3(256), 0, st, perm, src, dst, n);
+}
+void launch_scatter_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_scatter_perm, dim3(grid_for(n)), dim3(256), 0, st, perm, src, dst, n);
+}
+void launch_diag(hipStream_t st, const int32_t* perm, const int32_t* snode, FrontsDev F, const double* fronts,
+                 double* var, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_diag, dim3(grid_for(n)), dim3(256), 0, st, perm, snode, F, fronts, var, n);
+}
+
+// ---------------------------------------------------------------------------
+// Line-of-sight linearisation, one wavefront per star.
+//   A_n = sum_t w_t exp(F(s_t)), s_t = o + (t/T)(x_n - o), trapezoid weights
+//   g_n = d ln A_n / d f over the support, c_n = ln A_n - g_n . f
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_los(GridDev g, StarsDev s, const double* __restrict__ f, int cap) {
+    extern __shared__ char smem[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t* snodes = (int32_t*)(smem) + w * cap;
+    double* sg = (double*)(smem + (size_t)4 * cap * sizeof(int32_t)) + w * cap;
+    const int64_t star = (int64_t)blockIdx.x * 4 + w;
+    const bool active = star < s.n;
+    int64_t p0 = 0;
+    int cnt = 0;
+    if (active) {
+        p0 = s.ptr[star];
+        cnt = (int)(s.ptr[star + 1] - p0);
+        for (int k = lane; k < cnt; k += 64) { snodes[k] = s.nodes[p0 + k]; sg[k] = 0.0; }
+    }
+    __syncthreads();
+    double Asum = 0.0;
+    if (active) {
+        const double dx = s.xyz[3 * star] - g.ox, dy = s.xyz[3 * star + 1] - g.oy, dz = s.xyz[3 * star + 2] - g.oz;
+        const int T = s.nsamp[star];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double delta = d / (double)T;
+        const int n = g.n;
+        for (int t = lane; t <= T; t += 64) {
+            const double fr = (double)t / (double)T;
+            double p[3] = {g.ox + fr * dx, g.oy + fr * dy, g.oz + fr * dz};
+            int cc[3];
+            double wv[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                double c = floor(p[a] / g.h);
+                c = c < 0 ? 0 : (c > n - 2 ? n - 2 : c);
+                cc[a] = (int)c;
+                wv[a] = p[a] / g.h - c;
+            }
+            double phi[8];
+            int nd[8];
+            double F = 0.0;
+#pragma unroll
+            for (int c8 = 0; c8 < 8; c8++) {
+                int bi = c8 & 1, bj = (c8 >> 1) & 1, bk = (c8 >> 2) & 1;
+                phi[c8] = (bi ? wv[0] : 1.0 - wv[0]) * (bj ? wv[1] : 1.0 - wv[1]) * (bk ? wv[2] : 1.0 - wv[2]);
+                nd[c8] = (cc[0] + bi) + n * ((cc[1] + bj) + n * (cc[2] + bk));
+                F += phi[c8] * f[nd[c8]];
+            }
+            const double wt = (t == 0 || t == T) ? 0.5 * delta : delta;
+            const double ev = wt * exp(F);
+            Asum += ev;
+#pragma unroll
+            for (int c8 = 0; c8 < 8; c8++) {
+                int lo = 0, hi = cnt - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (snodes[mid] < nd[c8]) lo = mid + 1; else hi = mid;
+                }
+                atomicAdd(&sg[lo], ev * phi[c8]);
+            }
+        }
+    }
+    const double A = wave_sum(Asum);
+    __syncthreads();
+    if (!active) return;
+    const double iA = 1.0 / A;
+    double gf = 0.0;
+    for (int k = lane; k < cnt; k += 64) {
+        double gv = sg[k] * iA;
+        s.g[p0 + k] = gv;
+        gf += gv * f[snodes[k]];
+    }
+    gf = wave_sum(gf);
+    if (lane == 0) {
+        s.lnA[star] = log(A);
+        s.c[star] = log(A) - gf;
+    }
+}
+
+void launch_los(hipStream_t st, GridDev g, StarsDev s, const double* f, int cap) {
+    if (s.n <= 0) return;
+    size_t sh = (size_t)4 * cap * (sizeof(int32_t) + sizeof(double));
+    hipLaunchKernelGGL(k_los, dim3((unsigned)((s.n + 3) / 4)), dim3(256), sh, st, g, s, f, cap);
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of the sites into the fronts: tau_n g_n g_n^T lands in the front
+// of the star's first-eliminated support node (its whole clique is there).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_assemble_stars(StarsDev s, FrontsDev F, double* fronts, int cap) {
+    extern __shared__ char smem[];
+    int32_t* sl = (int32_t*)smem;
+    double* sg = (double*)(smem + ((size_t)cap * sizeof(int32_t) + 15) / 16 * 16);
+    const int64_t star = blockIdx.x;
+    const double tau = s.tau[star];
+    if (tau == 0.0) return;
+    const int64_t p0 = s.ptr[star];
+    const int cnt = (int)(s.ptr[star + 1] - p0);
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        int slot = s.sord[p0 + k];
+        sl[k] = s.loc[p0 + slot];
+        sg[k] = s.g[p0 + slot];
+    }
+    __syncthreads();
+    const int f = s.front[star];
+    double* base = fronts + F.off[f];
+    const int64_t m = F.m[f];
+    const int64_t npair = (int64_t)cnt * (cnt + 1) / 2;
+    for (int64_t q = threadIdx.x; q < npair; q += blockDim.x) {
+        int a, b;
+        tri_decode(q, a, b);
+        atomicAdd(base + sl[a] + (int64_t)sl[b] * m, tau * sg[a] * sg[b]);
+    }
+}
+
+__global__ void k_assemble_b(StarsDev s, double* b) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t star = (int64_t)blockIdx.x * 4 + w;
+    if (star >= s.n) return;
+    const double coef = s.nu[star] - s.tau[star] * s.c[star];
+    if (coef == 0.0) return;
+    const int64_t p0 = s.ptr[star];
+    const int cnt = (int)(s.ptr[star + 1] - p0);
+    for (int k = lane; k < cnt; k += 64) atomicAdd(b + s.nodes[p0 + k], coef * s.g[p0 + k]);
+}
+
+void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int cap) {
+    if (s.n <= 0) return;
+    size_t sh = ((size_t)cap * sizeof(int32_t) + 15) / 16 * 16 + (size_t)cap * sizeof(double);
+    hipLaunchKernelGGL(k_assemble_stars, dim3((unsigned)s.n), dim3(256), sh, st, s, F, fronts, cap);
+}
+void launch_assemble_b(hipStream_t st, StarsDev s, double* b) {
+    if (s.n <= 0) return;
+    hipLaunchKernelGGL(k_assemble_b, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s, b);
+}
+
+// ---------------------------------------------------------------------------
+// Cavity: q-marginal of a_n = c_n + g_n . f: mean c_n + g_n . mu and variance
+// g_n^T Sigma g_n, all pairs read from the star's front (lower triangle).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cavity(StarsDev s, FrontsDev F, const double* __restrict__ fronts,
+                                                const double* __restrict__ mu, int cap) {
+    extern __shared__ char smem[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t* sl = (int32_t*)smem + w * cap;
+    double* sg = (double*)(smem + (size_t)4 * cap * sizeof(int32_t)) + w * cap;
+    const int64_t star = (int64_t)blockIdx.x * 4 + w;
+    const bool active = star < s.n;
+    int64_t p0 = 0;
+    int cnt = 0;
+    double mean = 0.0;
+    if (active) {
+        p0 = s.ptr[star];
+        cnt = (int)(s.ptr[star + 1] - p0);
+        for (int k = lane; k < cnt; k += 64) {
+            int slot = s.sord[p0 + k];
+            sl[k] = s.loc[p0 + slot];
+            double gv = s.g[p0 + slot];
+            sg[k] = gv;
+            mean += gv * mu[s.nodes[p0 + slot]];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const int f = s.front[star];
+    const double* base = fronts + F.off[f];
+    const int64_t m = F.m[f];
+    double acc = 0.0;
+    for (int b = 0; b < cnt; b++) {
+        const double* col = base + (int64_t)sl[b] * m;
+        double part = 0.0;
+        for (int a = b + lane; a < cnt; a += 64) part += (a == b ? 1.0 : 2.0) * sg[a] * col[sl[a]];
+        acc += part * sg[b];
+    }
+    acc = wave_sum(acc);
+    mean = wave_sum(mean);
+    if (lane == 0) {
+        s.cav_mu[star] = s.c[star] + mean;
+        s.cav_var[star] = acc;
+    }
+}
+
+void launch_cavity(hipStream_t st, StarsDev s, FrontsDev F, const double* fronts, const double* mu, int cap) {
+    if (s.n <= 0) return;
+    size_t sh = (size_t)4 * cap * (sizeof(int32_t) + sizeof(double));
+    hipLaunchKernelGGL(k_cavity, dim3((unsigned)((s.n + 3) / 4)), dim3(256), sh, st, s, F, fronts, mu, cap);
+}
+
+// ---------------------------------------------------------------------------
+// Tilted moments of N(a; mu, v) N(A; e^a, s^2), one wavefront per star.
+//
+// The log-integrand l(a) has at most two local maxima: its inflection points
+// solve 2y^2 - A y + s^2/v = 0 (y = e^a) and split the line into pieces
+// where l' is monotone.  Each side of each maximum is cut where l falls
+// 1, 2, 4, 8, 12, ..., 32, 40, 50, 60 below that maximum (one bisection per
+// lane), and every piece gets a 16-point Gauss-Legendre rule; a piece between
+// two maxima ends at the local minimum.
+// ---------------------------------------------------------------------------
+__constant__ double c_glx[16];
+__constant__ double c_glw[16];
+__constant__ double c_depth[13] = {1, 2, 4, 8, 12, 16, 20, 24, 28, 32, 40, 50, 60};
+
+struct TiltP {
+    double mu, v, A, s2;
+};
+__device__ inline double t_ell(const TiltP& t, double a) {
+    double y = exp(a), r = t.A - y;
+    return -(a - t.mu) * (a - t.mu) / (2.0 * t.v) - r * r / (2.0 * t.s2);
+}
+__device__ inline double t_d1(const TiltP& t, double a) {
+    double y = exp(a);
+    return -(a - t.mu) / t.v + (t.A - y) * y / t.s2;
+}
+__device__ inline double t_d2(const TiltP& t, double a) {
+    double y = exp(a);
+    return -1.0 / t.v + (t.A * y - 2.0 * y * y) / t.s2;
+}
+// zero of l' on [lo, hi] (l' changes sign), bisection to full precision
+__device__ inline double t_root(const TiltP& t, double lo, double hi) {
+    double flo = t_d1(t, lo);
+    for (int it = 0; it < 200; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double fm = t_d1(t, mid);
+        if (fm == 0.0) return mid;
+        if ((fm > 0.0) == (flo > 0.0)) { lo = mid; flo = fm; } else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Computes (lnZ, mean, var) with all 64 lanes of the calling wave.
+__device__ void tilted_wave(const TiltP& t, double* sb, double& lnZ, double& mean, double& var) {
+    const int lane = threadIdx.x & 63;
+    double maxima[2] = {t.mu, t.mu};
+    int nmax = 0;
+    double amin = 0.0;
+    bool bimodal = false;
+    const double disc = t.A * t.A - 8.0 * t.s2 / t.v;
+    if (t.A > 0.0 && disc > 0.0) {
+        double y1 = 0.25 * (t.A - sqrt(disc)), y2 = 0.25 * (t.A + sqrt(disc));
+        double a1 = log(y1), a2 = log(y2);
+        double d1a = t_d1(t, a1), d1b = t_d1(t, a2);
+        if (d1a < 0.0) {
+            double step = 1.0, lo = a1 - step;
+            for (int it = 0; it < 200 && !(t_d1(t, lo) > 0.0); it++) { step *= 2.0; lo = a1 - step; }
+            maxima[nmax++] = t_root(t, lo, a1);
+        }
+        if (d1b > 0.0) {
+            double step = 1.0, hi = a2 + step;
+            for (int it = 0; it < 200 && !(t_d1(t, hi) < 0.0); it++) { step *= 2.0; hi = a2 + step; }
+            maxima[nmax++] = t_root(t, a2, hi);
+        }
+        if (d1a < 0.0 && d1b > 0.0) { amin = t_root(t, a1, a2); bimodal = true; }
+    } else {
+        double step = 1.0, lo = t.mu - step, hi = t.mu + step;
+        for (int it = 0; it < 200 && !(t_d1(t, lo) > 0.0); it++) { step *= 2.0; lo = t.mu - step; }
+        step = 1.0;
+        for (int it = 0; it < 200 && !(t_d1(t, hi) < 0.0); it++) { step *= 2.0; hi = t.mu + step; }
+        maxima[nmax++] = t_root(t, lo, hi);
+    }
+    if (nmax == 0) { maxima[0] = t.mu; nmax = 1; }
+    const double l0 = t_ell(t, maxima[0]), l1 = t_ell(t, maxima[nmax - 1]);
+    const double astar = (nmax == 2 && l1 > l0) ? maxima[1] : maxima[0];
+    const double lmax = (nmax == 2 && l1 > l0) ? l1 : l0;
+    // segment ends: outer tails where l drops 60 below the adjacent maximum
+    double sL = 1.0 / sqrt(-t_d2(t, maxima[0]));
+    double sR = 1.0 / sqrt(-t_d2(t, maxima[nmax - 1]));
+    if (!isfinite(sL) || sL <= 0.0) sL = sqrt(t.v);
+    if (!isfinite(sR) || sR <= 0.0) sR = sqrt(t.v);
+    double Lend = maxima[0] - sL, Uend = maxima[nmax - 1] + sR;
+    {
+        double st = sL;
+        for (int it = 0; it < 200 && t_ell(t, Lend) - l0 > -60.0; it++) { st *= 2.0; Lend = maxima[0] - st; }
+        st = sR;
+        for (int it = 0; it < 200 && t_ell(t, Uend) - l1 > -60.0; it++) { st *= 2.0; Uend = maxima[nmax - 1] + st; }
+    }
+    // four segments: (anchor, far end, anchor level); unused ones are empty
+    // 0: left of the first maximum, 1: right of the last maximum,
+    // 2: first maximum -> local minimum, 3: last maximum -> local minimum
+    const int seg = lane / 13, di = lane % 13;
+    if (lane < 52) {
+        double anc, end, lv;
+        bool live = true;
+        if (seg == 0) { anc = maxima[0]; end = Lend; lv = l0; }
+        else if (seg == 1) { anc = maxima[nmax - 1]; end = Uend; lv = l1; }
+        else if (seg == 2) { anc = maxima[0]; end = amin; lv = l0; live = bimodal; }
+        else { anc = maxima[nmax - 1]; end = amin; lv = l1; live = bimodal; }
+        double bpt = anc;
+        if (live) {
+            const double target = lv - c_depth[di];
+            if (di == 12 || !(t_ell(t, end) < target)) {
+                bpt = end;   // the segment ends before this depth
+            } else {
+                double lo = anc, hi = end;   // l(lo) > target >= l(hi)
+                for (int it = 0; it < 200; it++) {
+                    double mid = 0.5 * (lo + hi);
+                    if (mid == lo || mid == hi) break;
+                    if (t_ell(t, mid) > target) lo = mid; else hi = mid;
+                }
+                bpt = 0.5 * (lo + hi);
+            }
+        }
+        sb[lane] = bpt;
+        if (di == 0) sb[64 + seg] = live ? anc : bpt;   // segment start
+    }
+    __syncthreads();
+    // 52 panels x 16 nodes
+    double I0 = 0.0, I1 = 0.0, I2 = 0.0;
+    for (int idx = lane; idx < 52 * 16; idx += 64) {
+        const int pnl = idx >> 4, q = idx & 15;
+        const int sg = pnl / 13, dk = pnl % 13;
+        const double a0 = (dk == 0) ? sb[64 + sg] : sb[sg * 13 + dk - 1];
+        const double a1 = sb[sg * 13 + dk];
+        const double hw = 0.5 * (a1 - a0);
+        if (hw == 0.0) continue;
+        const double a = 0.5 * (a0 + a1) + hw * c_glx[q];
+        const double e = fabs(hw) * c_glw[q] * exp(t_ell(t, a) - lmax);
+        const double u = a - astar;
+        I0 += e;
+        I1 += e * u;
+        I2 += e * u * u;
+    }
+    I0 = wave_sum(I0);
+    I1 = wave_sum(I1);
+    I2 = wave_sum(I2);
+    const double m1 = I1 / I0;
+    mean = astar + m1;
+    var = I2 / I0 - m1 * m1;
+    const double twopi = 6.283185307179586476925286766559;
+    lnZ = lmax + log(I0) - 0.5 * log(twopi * t.v) - 0.5 * log(twopi * t.s2);
+}
+
+__device__ inline void tilted_gauss(const TiltP& t, double& lnZ, double& mean, double& var) {
+    double vh = 1.0 / (1.0 / t.v + 1.0 / t.s2);
+    var = vh;
+    mean = vh * (t.mu / t.v + t.A / t.s2);
+    double tv = t.v + t.s2, r = t.A - t.mu;
+    lnZ = -0.5 * log(6.283185307179586476925286766559 * tv) - 0.5 * r * r / tv;
+}
+
+// Cavity from the q-marginal, tilted moments, damped site update.
+__global__ __launch_bounds__(256) void k_tilted_update(StarsDev s, EpParams P) {
+    __shared__ double sbw[4][72];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t star = (int64_t)blockIdx.x * 4 + w;
+    const bool active = star < s.n;
+    double tau = 0.0, nu = 0.0, tau_c = 1.0, nu_c = 0.0, mu_c = 0.0, v_c = 1.0;
+    bool skip = !active;
+    TiltP tp{0.0, 1.0, 1.0, 1.0};   // benign stand-in for idle waves
+    if (active) {
+        const double qm = s.cav_mu[star], qv = s.cav_var[star];
+        tau = s.tau[star];
+        nu = s.nu[star];
+        tau_c = 1.0 / qv - tau;
+        nu_c = qm / qv - nu;
+        if (!(tau_c > 0.0)) {
+            skip = true;
+        } else {
+            v_c = 1.0 / tau_c;
+            if (v_c < P.vfloor) v_c = P.vfloor;
+            mu_c = nu_c / tau_c;
+            tau_c = 1.0 / v_c;
+            nu_c = mu_c / v_c;
+            const double sig = s.sigma[star];
+            tp = TiltP{mu_c, v_c, s.A[star], sig * sig};
+        }
+    }
+    double lnZ, mh, vh;
+    if (P.mode == 1) tilted_gauss(tp, lnZ, mh, vh);
+    else tilted_wave(tp, sbw[w], lnZ, mh, vh);   // every wave reaches the block barrier inside
+    if (!active || lane != 0) return;
+    if (skip) {
+        s.status[star] = 1;
+        s.dtau[star] = 0.0;
+        return;
+    }
+    s.cav_mu[star] = mu_c;
+    s.cav_var[star] = v_c;
+    s.lnZ[star] = lnZ;
+    s.tmean[star] = mh;
+    s.tvar[star] = vh;
+    const double tn = 1.0 / vh - tau_c;
+    const double nn = mh / vh - nu_c;
+    if (!(tn >= 0.0) || !isfinite(tn) || !isfinite(nn)) {
+        s.status[star] = 2;
+        s.dtau[star] = 0.0;
+    } else {
+        const double d = P.damping;
+        const double t2 = (1.0 - d) * tau + d * tn;
+        s.status[star] = 0;
+        s.dtau[star] = fabs(t2 - tau);
+        s.tau[star] = t2;
+        s.nu[star] = (1.0 - d) * nu + d * nn;
+    }
+}
+
+void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p) {
+    if (s.n <= 0) return;
+    hipLaunchKernelGGL(k_tilted_update, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s, p);
+}
+
+__global__ __launch_bounds__(256) void k_tilted_batch(int mode, int64_t n, const double* mu, const double* v,
+                                                      const double* A, const double* sig, double* lnZ,
+                                                      double* mean, double* var) {
+    __shared__ double sbw[4][72];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    const bool active = i < n;
+    TiltP tp{0.0, 1.0, 1.0, 1.0};
+    if (active) tp = TiltP{mu[i], v[i], A[i], sig[i] * sig[i]};
+    double a, b, c;
+    if (mode == 1) tilted_gauss(tp, a, b, c);
+    else tilted_wave(tp, sbw[w], a, b, c);
+    if (active && lane == 0) { lnZ[i] = a; mean[i] = b; var[i] = c; }
+}
+
+void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
+                         const double* sig, double* lnZ, double* mean, double* var) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tilted_batch, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, mode, n, mu, v, A, sig,
+                       lnZ, mean, var);
+}
+
+// Gauss-Legendre 16-point nodes and weights from Newton's iteration on the
+// Legendre recurrence (computed on the host, copied to constant memory).
+void set_gauss_legendre(hipStream_t st) {
+    const int n = 16;
+    double x[16], wgt[16];
+    for (int i = 0; i < n; i++) {
+        double z = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = z;
+        wgt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, st);
+    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), wgt, sizeof(wgt), 0, hipMemcpyHostToDevice, st);
+    hipStreamSynchronize(st);
+}
+
+}  // namespace ep

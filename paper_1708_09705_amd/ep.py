@@ -1,0 +1,288 @@
+"""Python binding of the C ABI in include/ep.h (argument marshalling only).
+
+Every step of the EP sweep runs in the HIP library ``libep.so`` built in this
+directory for gfx950.  Loading fails loudly when the library is missing.
+
+Functions keep the C names (``ep_init``, ``ep_sweep``, ``ep_posterior_mean``,
+``ep_marginal_var``, ...); the ``EP`` class bundles them around one context.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Mapping
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libep.so")
+
+EP_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "NOT_PD", -4: "DEVICE", -5: "STATE", -6: "NUMERIC"}
+LIKELIHOOD = {"extinction": 0, "gauss_linear": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+MOMENTS = {"quadrature": 0, "surrogate": 1}
+
+
+class EPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class ep_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("box_pc", ctypes.c_double),
+        ("observer_pc", ctypes.c_double * 3),
+        ("prior_mean", ctypes.c_double),
+        ("prior_var", ctypes.c_double),
+        ("outer_scale_pc", ctypes.c_double),
+        ("support_pc", ctypes.c_double),
+        ("vecchia_radius_pc", ctypes.c_double),
+        ("los_step_pc", ctypes.c_double),
+        ("likelihood", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("moments", ctypes.c_int32),
+        ("damping", ctypes.c_double),
+        ("cavity_var_floor", ctypes.c_double),
+        ("relinearize", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("leaf_size", ctypes.c_int32),
+        ("hbm_cap_bytes", ctypes.c_int64),
+    ]
+
+
+class ep_sweep_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve",
+                                                "ms_selinv", "ms_star", "ms_total")] + \
+               [(k, ctypes.c_int64) for k in ("updated", "skipped_cavity", "skipped_negsite")] + \
+               [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu")]
+
+
+class ep_structure_stats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_stars", ctypes.c_int64), ("nnz_g", ctypes.c_int64),
+                ("n_fronts", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("front_elems", ctypes.c_int64),
+                ("max_front", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("selinv_flops", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_free",
+           "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
+           "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure")
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libep.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(p)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    cfgp = ctypes.POINTER(ep_config)
+    L.ep_config_default.argtypes = [cfgp]
+    L.ep_config_default.restype = None
+    L.ep_init.argtypes = [cfgp, i64, vp, vp, vp, ctypes.POINTER(vp)]
+    L.ep_sweep.argtypes = [vp, ctypes.POINTER(ep_sweep_stats)]
+    L.ep_posterior_mean.argtypes = [vp, vp]
+    L.ep_marginal_var.argtypes = [vp, vp]
+    L.ep_free.argtypes = [vp]
+    L.ep_free.restype = None
+    L.ep_last_error.argtypes = [vp]
+    L.ep_last_error.restype = ctypes.c_char_p
+    L.ep_get_sites.argtypes = [vp, vp, vp]
+    L.ep_set_sites.argtypes = [vp, vp, vp]
+    L.ep_get_linpoint.argtypes = [vp, vp]
+    L.ep_set_linpoint.argtypes = [vp, vp]
+    L.ep_star_state.argtypes = [vp] * 7
+    L.ep_tilted_moments.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, i32]
+    L.ep_simulate.argtypes = [cfgp, i64, vp, vp, vp, vp, vp, vp]
+    L.ep_structure.argtypes = [vp, ctypes.POINTER(ep_structure_stats)]
+    for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
+                 "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
+                 "ep_tilted_moments", "ep_simulate", "ep_structure"):
+        getattr(L, name).restype = ctypes.c_int
+    if path is None:
+        _lib = L
+    return L
+
+
+def _arr(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_config(fields: Mapping | None = None, lib=None, **kw) -> ep_config:
+    """An ep_config from defaults plus a mapping of field values (the same
+    keys as the C struct; likelihood/precision/moments may be strings)."""
+    L = lib or load()
+    c = ep_config()
+    L.ep_config_default(ctypes.byref(c))
+    vals = dict(fields or {})
+    vals.update(kw)
+    for k, v in vals.items():
+        if k == "likelihood" and isinstance(v, str):
+            v = LIKELIHOOD[v]
+        elif k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        elif k == "moments" and isinstance(v, str):
+            v = MOMENTS[v]
+        elif k == "relinearize":
+            v = int(bool(v))
+        if k == "observer_pc":
+            c.observer_pc = (ctypes.c_double * 3)(*v)
+        elif k == "stream":
+            c.stream = ctypes.c_void_p(int(v) if v else None)
+        elif hasattr(c, k):
+            setattr(c, k, v)
+        else:
+            raise KeyError(f"unknown config field {k}")
+    return c
+
+
+def _check(L, rc: int, ctx=None):
+    if rc != EP_OK:
+        msg = L.ep_last_error(ctx).decode()
+        raise EPError(rc, msg)
+
+
+# ---- C names -----------------------------------------------------------------
+def ep_init(cfg: ep_config, xyz, A_obs, sigma, lib=None):
+    L = lib or load()
+    xyz = _arr(xyz).reshape(-1, 3)
+    S = xyz.shape[0]
+    A_obs, sigma = _arr(A_obs, S), _arr(sigma, S)
+    out = ctypes.c_void_p()
+    _check(L, L.ep_init(ctypes.byref(cfg), S, _ptr(xyz), _ptr(A_obs), _ptr(sigma), ctypes.byref(out)))
+    return out
+
+
+def ep_sweep(ctx, lib=None) -> dict:
+    L = lib or load()
+    st = ep_sweep_stats()
+    _check(L, L.ep_sweep(ctx, ctypes.byref(st)), ctx)
+    return {k: getattr(st, k) for k, _ in ep_sweep_stats._fields_}
+
+
+def ep_posterior_mean(ctx, N: int, lib=None) -> np.ndarray:
+    L = lib or load()
+    out = np.empty(N)
+    _check(L, L.ep_posterior_mean(ctx, _ptr(out)), ctx)
+    return out
+
+
+def ep_marginal_var(ctx, N: int, lib=None) -> np.ndarray:
+    L = lib or load()
+    out = np.empty(N)
+    _check(L, L.ep_marginal_var(ctx, _ptr(out)), ctx)
+    return out
+
+
+def ep_free(ctx, lib=None) -> None:
+    L = lib or load()
+    L.ep_free(ctx)
+
+
+def ep_tilted_moments(mode, mu_c, v_c, A, sigma, device: int = 0, lib=None):
+    L = lib or load()
+    mu_c = _arr(mu_c)
+    n = mu_c.size
+    v_c, A, sigma = _arr(v_c, n), _arr(A, n), _arr(sigma, n)
+    lnZ, m, v = np.empty(n), np.empty(n), np.empty(n)
+    mode = LIKELIHOOD.get(mode, mode) if isinstance(mode, str) else int(mode)
+    _check(L, L.ep_tilted_moments(mode, n, _ptr(mu_c), _ptr(v_c), _ptr(A), _ptr(sigma), _ptr(lnZ), _ptr(m),
+                                  _ptr(v), device))
+    return lnZ, m, v
+
+
+def ep_simulate(cfg: ep_config, xyz, sigma, eps, xi, lib=None):
+    """(f_true, A_obs) from raw deviates with the library's own arithmetic."""
+    L = lib or load()
+    xyz = _arr(xyz).reshape(-1, 3)
+    S = xyz.shape[0]
+    N = cfg.n ** 3
+    sigma, eps, xi = _arr(sigma, S), _arr(eps, S), _arr(xi, N)
+    f = np.empty(N)
+    A = np.empty(S)
+    _check(L, L.ep_simulate(ctypes.byref(cfg), S, _ptr(xyz), _ptr(sigma), _ptr(eps), _ptr(xi), _ptr(f), _ptr(A)))
+    return f, A
+
+
+# ---- convenience wrapper -----------------------------------------------------
+class EP:
+    """One EP context on the GPU."""
+
+    def __init__(self, cfg: Mapping | ep_config, xyz, A_obs, sigma, lib=None):
+        self.L = lib or load()
+        self.cfg = cfg if isinstance(cfg, ep_config) else make_config(cfg, lib=self.L)
+        self.N = self.cfg.n ** 3
+        self.S = int(np.asarray(xyz).reshape(-1, 3).shape[0])
+        self.ctx = ep_init(self.cfg, xyz, A_obs, sigma, lib=self.L)
+
+    def sweep(self) -> dict:
+        return ep_sweep(self.ctx, lib=self.L)
+
+    def posterior_mean(self) -> np.ndarray:
+        return ep_posterior_mean(self.ctx, self.N, lib=self.L)
+
+    def marginal_var(self) -> np.ndarray:
+        return ep_marginal_var(self.ctx, self.N, lib=self.L)
+
+    def sites(self):
+        tau, nu = np.empty(self.S), np.empty(self.S)
+        _check(self.L, self.L.ep_get_sites(self.ctx, _ptr(tau), _ptr(nu)), self.ctx)
+        return tau, nu
+
+    def set_sites(self, tau, nu) -> None:
+        tau, nu = _arr(tau, self.S), _arr(nu, self.S)
+        _check(self.L, self.L.ep_set_sites(self.ctx, _ptr(tau), _ptr(nu)), self.ctx)
+
+    def linpoint(self) -> np.ndarray:
+        f = np.empty(self.N)
+        _check(self.L, self.L.ep_get_linpoint(self.ctx, _ptr(f)), self.ctx)
+        return f
+
+    def set_linpoint(self, f) -> None:
+        f = _arr(f, self.N)
+        _check(self.L, self.L.ep_set_linpoint(self.ctx, _ptr(f)), self.ctx)
+
+    def star_state(self) -> dict:
+        keys = ("lnA", "cav_mu", "cav_var", "lnZ", "tilted_mean", "tilted_var")
+        arrs = [np.empty(self.S) for _ in keys]
+        _check(self.L, self.L.ep_star_state(self.ctx, *[_ptr(a) for a in arrs]), self.ctx)
+        return dict(zip(keys, arrs))
+
+    def structure(self) -> dict:
+        st = ep_structure_stats()
+        _check(self.L, self.L.ep_structure(self.ctx, ctypes.byref(st)), self.ctx)
+        return {k: getattr(st, k) for k, _ in ep_structure_stats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            ep_free(self.ctx, lib=self.L)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
