@@ -1,0 +1,157 @@
+"""Benchmark: EP star-updates per second on one MI355X.
+
+One step = one full parallel EP sweep (line-of-sight linearisation, assembly,
+multifrontal Cholesky, solves, selected inversion, cavity, tilted moments and
+site update for every star) of the 64^3-grid / 100,000-star workload (4 kpc
+cube, disc-distributed stars, sigma ~ U[0.05, 0.2] mag), FP64 throughout.
+
+value = stars x steps / wall time of the timed steps (whole sweeps; inputs
+resident on the device).  The JSON line also carries the per-phase times,
+the dense-front MFMA roofline and the oracle's CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(preset_id: int, n_sample: int) -> dict:
+    """The oracle (plain FP64 C + numpy, unchanged) performing first-sweep star
+    updates for a sample of the same workload: line-of-sight linearisation at
+    the prior mean, cavity variance g^T Q0^{-1} g by Vecchia back-substitution,
+    adaptive Gauss-Kronrod tilted moments and the site update."""
+    from oracle import epo
+    from synth import draw, preset
+    w = preset(preset_id)
+    cfg = w.ep_fields()
+    raw = draw(w)
+    t0 = time.perf_counter()
+    vec = epo.Vecchia(cfg)
+    f_true = vec.draw(cfg["prior_mean"], raw["xi"])
+    t_prior = time.perf_counter() - t0
+    idx = np.arange(n_sample)
+    sl = epo.Sightlines(cfg, raw["xyz"][idx])
+    _, lnA_true, _ = sl.linearise(f_true)
+    A = np.exp(lnA_true) + raw["sigma"][idx] * raw["eps"][idx]
+    t0 = time.perf_counter()
+    gval, lnA, c = sl.linearise(np.full(sl.grid.N, cfg["prior_mean"]))
+    v = vec.prior_quadform(sl.ptr, sl.nodes, gval)
+    m = lnA
+    lnZ, mh, vh = epo.tilted(0, m, v, A, raw["sigma"][idx])
+    tau = 1 / vh - 1 / v
+    nu = mh / vh - m / v
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(tau)) and np.all(np.isfinite(nu))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_sample / dt, "unit": "star-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"first-sweep star updates of {n_sample} stars of the same 64^3/100k workload "
+                      f"(LOS linearisation, g^T Q0^-1 g by Vecchia back-substitution, adaptive "
+                      f"Gauss-Kronrod tilted moments, site update); {dt:.1f} s; prior set-up "
+                      f"{t_prior:.1f} s not counted"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--preset", type=int, default=2)
+    ap.add_argument("--stars", type=int, default=0, help="override the star count (testing)")
+    ap.add_argument("--leaf", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=100000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
+              f"design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_1708_09705_amd import ep as E
+    from synth import draw, preset
+
+    w = preset(args.preset) if not args.stars else preset(args.preset, n_stars=args.stars)
+    raw = draw(w)
+    cfg = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1)
+    t0 = time.perf_counter()
+    f_true, A = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+    log(f"simulated {w.name}: {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    g = E.EP(cfg, raw["xyz"], A, raw["sigma"])
+    st = g.structure()
+    log(f"init {time.perf_counter() - t0:.1f} s; structure {st}")
+    for i in range(args.warmup):
+        s = g.sweep()
+        log(f"warmup {i}: {s['ms_total']:.1f} ms")
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s = g.sweep()
+        stats.append(s)
+        log(f"step {i}: {json.dumps({k: round(v, 3) if isinstance(v, float) else v for k, v in s.items()})}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    S = g.S
+    value = S * args.steps / wall
+    ph = {k: float(np.mean([s[k] for s in stats])) for k in
+          ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")}
+    # Dominant kernel family: the FP64 MFMA tile kernels (trailing/inner
+    # updates, column solves, triangular inverse, selected inversion).  Their
+    # launches are timed with HIP events on the library's stream; the work
+    # counted is the algorithmic (unpadded) flop count of the partial
+    # Cholesky and the selected inversion of every front.
+    mfma_ms = float(np.mean([s["mfma_ms"] for s in stats]))
+    launches = int(stats[0]["mfma_launches"])
+    flops = st["factor_flops"] + st["selinv_flops"]
+    achieved = flops / (mfma_ms * 1e-3) / 1e12
+    line = {
+        "metric": "EP star-updates/sec (full sweep, plain FP64)",
+        "value": value,
+        "unit": "star-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded draws; exact Vecchia-prior field; library forward model)",
+        "config": {"workload": w.name, "grid": f"{w.n}^3", "box_pc": w.box_pc, "stars": S,
+                   "precision": "fp64", "moments": "quadrature", "parallelism": "single GPU"},
+        "phases_ms": ph,
+        "star_phase_updates_per_s": S / (ph["ms_star"] * 1e-3),
+        "structure": {k: st[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front", "factor_flops",
+                                         "selinv_flops", "device_bytes")},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "FP64 MFMA tile kernels (k_syrk_trail, k_syrk_inner, k_trsm_step, k_gemm_tasks)",
+                     "launches_per_step": launches, "kernel_ms_per_step": mfma_ms,
+                     "avg_launch_ms": mfma_ms / max(launches, 1),
+                     "algorithmic_flop_per_step": flops},
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.preset, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,6 +83,7 @@ typedef struct ep_config {
     void *stream;              /* hipStream_t to run on; NULL = library-owned stream */
     int32_t leaf_size;         /* ordering: largest dissection leaf (0 = 512) */
     int64_t hbm_cap_bytes;     /* refuse to allocate more than this (0 = no cap) */
+    int32_t profile_kernels;   /* 1: time every MFMA tile-kernel launch with HIP events */
 } ep_config;
 
 typedef struct ep_sweep_stats {
@@ -98,6 +99,8 @@ typedef struct ep_sweep_stats {
     int64_t skipped_negsite;   /* new site precision < 0 or non-finite */
     double max_dtau;           /* max |change of site precision| */
     double max_dmu;            /* max |posterior mean - previous linearisation point| */
+    double mfma_ms;            /* summed duration of the MFMA tile-kernel launches (profile_kernels) */
+    int64_t mfma_launches;     /* number of those launches */
 } ep_sweep_stats;
 
 typedef struct ep_structure_stats {

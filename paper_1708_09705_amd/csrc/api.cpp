@@ -40,8 +40,8 @@ struct TaskRange {
     int64_t n = 0;
 };
 struct LevelPlan {
-    std::vector<FList> potrf;   // per right-looking step
-    std::vector<Launch> trsm, syrk;
+    std::vector<FList> potrf;   // per pivot step
+    std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k
     Launch extend;              // also the Sigma-gather enumeration
     Launch fwd_xv, fwd_r, bwd_t, bwd_x;
     FList fronts;
@@ -92,6 +92,8 @@ struct ep_ctx {
     std::vector<LevelPlan> levels;
     std::vector<TaskRange> trtri1, trtri2;   // per doubling stage
     bool linearised = false;                 // g, c valid for the current fhat (frozen modes)
+    std::vector<hipEvent_t> kt_ev;           // per-launch timing events (profile_kernels)
+    size_t kt_used = 0;
 
     FrontsDev F{};
     StarsDev SD{};
@@ -207,21 +209,34 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         LevelPlan& P = ctx->levels[l];
         int Pmax = 0;
         for (int f : lv[l]) Pmax = std::max(Pmax, P_of(f));
+        // Blocked right-looking partial Cholesky, panels of PW tiles:
+        //   step k: diagonal tile, column below it, update of the rest of
+        //   k's panel (K = 1); after a panel's last step, the trailing
+        //   update of every later column with K = panel width.
         for (int k = 0; k < Pmax; k++) {
             FList fl;
             fl.off = (int64_t)flists.size();
-            std::vector<std::pair<int, int64_t>> tr, sy;
+            std::vector<std::pair<int, int64_t>> tr, in, tl;
+            const int g = k / PW;
             for (int f : lv[l]) {
-                if (P_of(f) <= k) continue;
+                const int Pf = P_of(f), M = M_of(f);
+                if (Pf <= k) continue;
                 flists.push_back(f);
-                int64_t T = M_of(f) - k - 1;
-                tr.emplace_back(f, T);
-                sy.emplace_back(f, T * (T + 1) / 2);
+                tr.emplace_back(f, (int64_t)(M - k - 1));
+                const int gend = std::min(PW * (g + 1), Pf);
+                int64_t cnt = 0;
+                for (int j = k + 1; j < gend; j++) cnt += M - j;
+                in.emplace_back(f, cnt);
+                if (gend - 1 == k) {
+                    int64_t T = M - gend;
+                    tl.emplace_back(f, T * (T + 1) / 2);
+                }
             }
             fl.n = (int)((int64_t)flists.size() - fl.off);
             P.potrf.push_back(fl);
             P.trsm.push_back(mk_launch(tr));
-            P.syrk.push_back(mk_launch(sy));
+            P.inner.push_back(mk_launch(in));
+            P.trail.push_back(mk_launch(tl));
         }
         std::vector<std::pair<int, int64_t>> ea, fx, fr;
         for (int f : lv[l]) {
@@ -639,6 +654,23 @@ static void enqueue_assemble(ep_ctx* ctx) {
     launch_gather_perm(st, ctx->d_perm, ctx->d_borig, ctx->d_y, ctx->g.N());
 }
 
+// Optional per-launch timing of the MFMA tile kernels (cfg.profile_kernels).
+static void kt_begin(ep_ctx* ctx, int64_t ntasks) {
+    if (!ctx->cfg.profile_kernels || ntasks <= 0) return;
+    if (ctx->kt_used + 2 > ctx->kt_ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        ctx->kt_ev.push_back(a);
+        ctx->kt_ev.push_back(b);
+    }
+    (void)hipEventRecord(ctx->kt_ev[ctx->kt_used], ctx->stream);
+}
+static void kt_end(ep_ctx* ctx, int64_t ntasks) {
+    if (!ctx->cfg.profile_kernels || ntasks <= 0 || ctx->kt_used + 2 > ctx->kt_ev.size()) return;
+    (void)hipEventRecord(ctx->kt_ev[ctx->kt_used + 1], ctx->stream);
+    ctx->kt_used += 2;
+}
+
 static void enqueue_factor(ep_ctx* ctx) {
     hipStream_t st = ctx->stream;
     Bufs b = bufs(ctx);
@@ -646,16 +678,28 @@ static void enqueue_factor(ep_ctx* ctx) {
         for (size_t k = 0; k < P.potrf.size(); k++) {
             launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
             const Launch& t = P.trsm[k];
+            kt_begin(ctx, t.ntasks);
             launch_trsm_step(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
-            const Launch& s = P.syrk[k];
-            launch_syrk_step(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
+            kt_end(ctx, t.ntasks);
+            const Launch& s = P.inner[k];
+            kt_begin(ctx, s.ntasks);
+            launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
+            kt_end(ctx, s.ntasks);
+            const Launch& r = P.trail[k];
+            kt_begin(ctx, r.ntasks);
+            launch_syrk_trail(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
+            kt_end(ctx, r.ntasks);
         }
         const Launch& e = P.extend;
         launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
     }
     for (size_t s = 0; s < ctx->trtri1.size(); s++) {
+        kt_begin(ctx, ctx->trtri1[s].n);
         launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri1[s].off, ctx->trtri1[s].n, b);
+        kt_end(ctx, ctx->trtri1[s].n);
+        kt_begin(ctx, ctx->trtri2[s].n);
         launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri2[s].off, ctx->trtri2[s].n, b);
+        kt_end(ctx, ctx->trtri2[s].n);
     }
 }
 
@@ -685,9 +729,11 @@ static void enqueue_selinv(ep_ctx* ctx) {
     for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
         auto& P = ctx->levels[l];
         launch_sigma_gather(st, ctx->d_batches + P.extend.be_off, P.extend.nbe, P.extend.ntasks, ctx->F, b);
-        launch_gemm_tasks(st, ctx->d_tasks + P.selW.off, P.selW.n, b);
-        launch_gemm_tasks(st, ctx->d_tasks + P.selS21.off, P.selS21.n, b);
-        launch_gemm_tasks(st, ctx->d_tasks + P.selS11.off, P.selS11.n, b);
+        for (const TaskRange* r : {&P.selW, &P.selS21, &P.selS11}) {
+            kt_begin(ctx, r->n);
+            launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b);
+            kt_end(ctx, r->n);
+        }
     }
 }
 
@@ -732,6 +778,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         hipEvent_t* e;
         ~EvGuard() { for (int i = 0; i < 8; i++) hipEventDestroy(e[i]); }
     } guard{ev};
+    ctx->kt_used = 0;
     TRY(run_factor(ctx, ev));
     enqueue_solve(ctx);
     HIPCHK(hipEventRecord(ev[4], st));
@@ -793,6 +840,9 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
             stats->max_dtau = std::max(stats->max_dtau, dtau[s]);
         }
         stats->max_dmu = dmu;
+        stats->mfma_ms = 0;
+        stats->mfma_launches = (int64_t)(ctx->kt_used / 2);
+        for (size_t i = 0; i + 1 < ctx->kt_used; i += 2) stats->mfma_ms += ev_ms(ctx->kt_ev[i], ctx->kt_ev[i + 1]);
     }
     return EP_OK;
 }
@@ -826,12 +876,14 @@ void ep_config_default(ep_config* c) {
     c->stream = nullptr;
     c->leaf_size = 0;
     c->hbm_cap_bytes = 0;
+    c->profile_kernels = 0;
 }
 
 void ep_free(ep_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    for (void* p : ctx->allocs) hipFree(p);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    for (hipEvent_t e : ctx->kt_ev) (void)hipEventDestroy(e);
     if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
     delete ctx;
 }

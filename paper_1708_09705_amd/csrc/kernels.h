@@ -7,6 +7,7 @@
 namespace ep {
 
 constexpr int TS = 64;   // dense tile edge (doubles)
+constexpr int PW = 8;    // factorization panel width in tiles
 
 // Base buffers a tile task may address.
 enum Buf : int { BUF_FRONTS = 0, BUF_X = 1, BUF_W = 2 };
@@ -61,7 +62,8 @@ void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int
 void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b);
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
-void launch_syrk_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
+void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
+void launch_syrk_trail(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b);
 void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 

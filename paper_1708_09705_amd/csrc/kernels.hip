@@ -22,13 +22,13 @@ constexpr int LDP = TS + 1;   // padded LDS row (doubles)
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-__device__ inline int64_t batch_find(const BatchEnt* be, int nbe, int64_t t) {
+__device__ __forceinline__ int64_t batch_find(const BatchEnt* be, int nbe, int64_t t) {
     int lo = 0, hi = nbe - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -38,7 +38,7 @@ __device__ inline int64_t batch_find(const BatchEnt* be, int nbe, int64_t t) {
 }
 
 // t -> (i, j) with i >= j >= 0, row-major over the lower triangle
-__device__ inline void tri_decode(int64_t t, int& i, int& j) {
+__device__ __forceinline__ void tri_decode(int64_t t, int& i, int& j) {
     int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= t) r++;
     while (r * (r + 1) / 2 > t) r--;
@@ -46,7 +46,7 @@ __device__ inline void tri_decode(int64_t t, int& i, int& j) {
     j = (int)(t - r * (r + 1) / 2);
 }
 
-__device__ inline double* buf_of(const Bufs& b, int id) {
+__device__ __forceinline__ double* buf_of(const Bufs& b, int id) {
     return id == BUF_FRONTS ? b.fronts : (id == BUF_X ? b.X : b.W);
 }
 
@@ -54,45 +54,50 @@ __device__ inline double* buf_of(const Bufs& b, int id) {
 // MFMA tile core: acc += sum_t op(A_t) op(B_t) over nk tiles.
 // sA holds op(A) as [k][i], sB holds op(B) as [k][j] (row stride LDP).
 // ---------------------------------------------------------------------------
-__device__ inline void tile_load_A(double* sA, const double* A, int lda, bool ta, double sgn) {
-    const int tid = threadIdx.x;
+// Register staging of one A tile and one B tile (16 + 16 doubles per thread),
+// so the global loads of the next K tile overlap the MFMAs of the current one.
+struct Stage {
+    double a[16], b[16];
+};
+
+__device__ __forceinline__ void stage_load(Stage& p, const double* A, int lda, bool ta, const double* B, int ldb, bool tb) {
+    const int tid = threadIdx.x, lo = tid & 63, hi = tid >> 6;
     if (!ta) {
-        const int i = tid & 63;
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            int k = (tid >> 6) + 4 * r;
-            sA[k * LDP + i] = sgn * A[i + (int64_t)k * lda];
-        }
+        for (int r = 0; r < 16; r++) p.a[r] = A[lo + (int64_t)(hi + 4 * r) * lda];        // A[i=lo][k=hi+4r]
     } else {
-        const int k = tid & 63;
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            int i = (tid >> 6) + 4 * r;
-            sA[k * LDP + i] = sgn * A[k + (int64_t)i * lda];
-        }
+        for (int r = 0; r < 16; r++) p.a[r] = A[lo + (int64_t)(hi + 4 * r) * lda];        // A^T: k=lo, i=hi+4r
     }
-}
-
-__device__ inline void tile_load_B(double* sB, const double* B, int ldb, bool tb) {
-    const int tid = threadIdx.x;
     if (!tb) {
-        const int k = tid & 63;
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            int j = (tid >> 6) + 4 * r;
-            sB[k * LDP + j] = B[k + (int64_t)j * ldb];
-        }
+        for (int r = 0; r < 16; r++) p.b[r] = B[lo + (int64_t)(hi + 4 * r) * ldb];        // B[k=lo][j=hi+4r]
     } else {
-        const int j = tid & 63;
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            int k = (tid >> 6) + 4 * r;
-            sB[k * LDP + j] = B[j + (int64_t)k * ldb];
-        }
+        for (int r = 0; r < 16; r++) p.b[r] = B[lo + (int64_t)(hi + 4 * r) * ldb];        // B^T: j=lo, k=hi+4r
     }
 }
 
-__device__ inline void tile_mma(d4 acc[2][2], const double* sA, const double* sB) {
+// sA holds op(A) as [k][i], sB holds op(B) as [k][j] (row stride LDP)
+__device__ __forceinline__ void stage_store(const Stage& p, double* sA, double* sB, bool ta, bool tb, double sgn) {
+    const int tid = threadIdx.x, lo = tid & 63, hi = tid >> 6;
+    if (!ta) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sA[(hi + 4 * r) * LDP + lo] = sgn * p.a[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sA[lo * LDP + hi + 4 * r] = sgn * p.a[r];
+    }
+    if (!tb) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sB[lo * LDP + hi + 4 * r] = p.b[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sB[(hi + 4 * r) * LDP + lo] = p.b[r];
+    }
+}
+
+__device__ __forceinline__ void tile_mma(d4 acc[2][2], const double* sA, const double* sB) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
@@ -109,20 +114,23 @@ __device__ inline void tile_mma(d4 acc[2][2], const double* sA, const double* sB
     }
 }
 
-__device__ inline void seg_run(d4 acc[2][2], double* sA, double* sB, const double* A, int64_t sa, int lda,
+__device__ __forceinline__ void seg_run(d4 acc[2][2], double* sA, double* sB, const double* A, int64_t sa, int lda,
                                bool ta, double sgn, const double* B, int64_t sb, int ldb, bool tb, int nk) {
+    if (nk <= 0) return;
+    Stage p;
+    stage_load(p, A, lda, ta, B, ldb, tb);
     for (int t = 0; t < nk; t++) {
         __syncthreads();
-        tile_load_A(sA, A + t * sa, lda, ta, sgn);
-        tile_load_B(sB, B + t * sb, ldb, tb);
+        stage_store(p, sA, sB, ta, tb, sgn);
         __syncthreads();
+        if (t + 1 < nk) stage_load(p, A + (t + 1) * sa, lda, ta, B + (t + 1) * sb, ldb, tb);
         tile_mma(acc, sA, sB);
     }
 }
 
 // Write acc to C (mode: 0 accumulate, 1 overwrite, 2 atomic).  Uses sA as
 // staging for a coalesced column-major store.
-__device__ inline void tile_store(d4 acc[2][2], double* sC, double* C, int ldc, int mode) {
+__device__ __forceinline__ void tile_store(d4 acc[2][2], double* sC, double* C, int ldc, int mode) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     __syncthreads();
@@ -150,29 +158,44 @@ __device__ inline void tile_store(d4 acc[2][2], double* sC, double* C, int ldc, 
     }
 }
 
-__device__ inline void acc_zero(d4 acc[2][2]) {
+__device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
+__device__ __forceinline__ void seg_apply(d4 acc[2][2], double* sA, double* sB, const Bufs& bufs, const GemmSeg& S) {
+    const double* A = buf_of(bufs, (S.flags >> 8) & 3) + S.a;
+    const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
+    seg_run(acc, sA, sB, A, S.sa, S.lda, S.flags & 1, (S.flags & 4) ? -1.0 : 1.0, B, S.sb, S.ldb, (S.flags & 2) != 0,
+            S.nk);
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of tasks instead, so neighbouring tasks (which share operand tiles)
+// meet in the same L2.
+__device__ __forceinline__ int64_t xcd_task(int64_t n) {
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    const int64_t per = (G + 7) / 8;
+    const int64_t x = b % 8, q = b / 8;
+    const int64_t full = G % 8 == 0 ? 8 : G % 8;   // XCDs that own 'per' blocks
+    const int64_t t = x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
+    (void)n;
+    return t;
+}
+
 __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
     __shared__ double sA[TS * LDP];
     __shared__ double sB[TS * LDP];
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_task(n);
     if (t >= n) return;
-    const GemmTask T = tasks[t];
+    const GemmTask& T = tasks[t];
     d4 acc[2][2];
     acc_zero(acc);
     const int nseg = (T.flags >> 4) & 3;
-    for (int s = 0; s < nseg; s++) {
-        const GemmSeg& S = T.s[s];
-        const double* A = buf_of(bufs, (S.flags >> 8) & 3) + S.a;
-        const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
-        seg_run(acc, sA, sB, A, S.sa, S.lda, S.flags & 1, (S.flags & 4) ? -1.0 : 1.0, B, S.sb, S.ldb,
-                (S.flags & 2) != 0, S.nk);
-    }
+    if (nseg > 0) seg_apply(acc, sA, sB, bufs, T.s[0]);
+    if (nseg > 1) seg_apply(acc, sA, sB, bufs, T.s[1]);
     double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c;
     int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
     tile_store(acc, sA, C, T.ldc, mode);
@@ -274,23 +297,50 @@ __global__ __launch_bounds__(256) void k_trsm_step(const BatchEnt* __restrict__ 
     tile_store(acc, sA, Aik, m, 1);
 }
 
-__global__ __launch_bounds__(256) void k_syrk_step(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int k,
-                                                   FrontsDev F, Bufs bufs) {
+// inner update at pivot step kk: columns j in (kk, end of kk's panel), rows i >= j
+__global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int kk,
+                                                    FrontsDev F, Bufs bufs) {
     __shared__ double sA[TS * LDP];
     __shared__ double sB[TS * LDP];
     const int64_t t = blockIdx.x;
     if (t >= ntasks) return;
     const int e = (int)batch_find(be, nbe, t);
     const int f = be[e].front;
-    int ii, jj;
-    tri_decode(t - be[e].base, ii, jj);
-    const int i = k + 1 + ii, j = k + 1 + jj;
-    const int m = F.m[f];
+    const int m = F.m[f], M = m / TS;
+    int j = kk + 1;
+    int64_t r = t - be[e].base;
+    while (r >= M - j) { r -= M - j; j++; }
+    const int i = j + (int)r;
     double* base = bufs.fronts + F.off[f];
     d4 acc[2][2];
     acc_zero(acc);
-    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k * m, 0, m, false, -1.0,
-            base + (int64_t)TS * j + (int64_t)TS * k * m, 0, m, true, 1);
+    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * kk * m, 0, m, false, -1.0,
+            base + (int64_t)TS * j + (int64_t)TS * kk * m, 0, m, true, 1);
+    tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
+}
+
+// trailing update after panel g: columns j >= gend, rows i >= j,
+//   C_ij -= sum_{kk = k0}^{gend-1} L_{i,kk} L_{j,kk}^T
+__global__ __launch_bounds__(256) void k_syrk_trail(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int g,
+                                                    FrontsDev F, Bufs bufs) {
+    __shared__ double sA[TS * LDP];
+    __shared__ double sB[TS * LDP];
+    const int64_t t = xcd_task(ntasks);
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int m = F.m[f];
+    const int P = F.nvpad[f] / TS;
+    const int k0 = PW * g;
+    const int gend = min(k0 + PW, P);
+    int ii, jj;
+    tri_decode(t - be[e].base, ii, jj);
+    const int i = gend + ii, j = gend + jj;
+    double* base = bufs.fronts + F.off[f];
+    d4 acc[2][2];
+    acc_zero(acc);
+    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0,
+            base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, gend - k0);
     tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
 }
 
@@ -298,9 +348,13 @@ void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntask
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_trsm_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
 }
-void launch_syrk_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
+void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_syrk_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
+    hipLaunchKernelGGL(k_syrk_inner, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b);
+}
+void launch_syrk_trail(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_syrk_trail, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, g, F, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -473,7 +527,7 @@ __global__ void k_copy_v(const int32_t* __restrict__ flist, FrontsDev F, const d
 }
 
 // transposed tile-vector product through LDS: out[c] += sum_r T[r][c] v[r]
-__device__ inline void tgemv_tile(double* sT, const double* T, int64_t ld, const double* v, double& acc) {
+__device__ __forceinline__ void tgemv_tile(double* sT, const double* T, int64_t ld, const double* v, double& acc) {
     const int tid = threadIdx.x;
     __syncthreads();
     {
@@ -850,20 +904,20 @@ __constant__ double c_depth[13] = {1, 2, 4, 8, 12, 16, 20, 24, 28, 32, 40, 50, 6
 struct TiltP {
     double mu, v, A, s2;
 };
-__device__ inline double t_ell(const TiltP& t, double a) {
+__device__ __forceinline__ double t_ell(const TiltP& t, double a) {
     double y = exp(a), r = t.A - y;
     return -(a - t.mu) * (a - t.mu) / (2.0 * t.v) - r * r / (2.0 * t.s2);
 }
-__device__ inline double t_d1(const TiltP& t, double a) {
+__device__ __forceinline__ double t_d1(const TiltP& t, double a) {
     double y = exp(a);
     return -(a - t.mu) / t.v + (t.A - y) * y / t.s2;
 }
-__device__ inline double t_d2(const TiltP& t, double a) {
+__device__ __forceinline__ double t_d2(const TiltP& t, double a) {
     double y = exp(a);
     return -1.0 / t.v + (t.A * y - 2.0 * y * y) / t.s2;
 }
 // zero of l' on [lo, hi] (l' changes sign), bisection to full precision
-__device__ inline double t_root(const TiltP& t, double lo, double hi) {
+__device__ __forceinline__ double t_root(const TiltP& t, double lo, double hi) {
     double flo = t_d1(t, lo);
     for (int it = 0; it < 200; it++) {
         double mid = 0.5 * (lo + hi);
@@ -977,7 +1031,7 @@ __device__ void tilted_wave(const TiltP& t, double* sb, double& lnZ, double& mea
     lnZ = lmax + log(I0) - 0.5 * log(twopi * t.v) - 0.5 * log(twopi * t.s2);
 }
 
-__device__ inline void tilted_gauss(const TiltP& t, double& lnZ, double& mean, double& var) {
+__device__ __forceinline__ void tilted_gauss(const TiltP& t, double& lnZ, double& mean, double& var) {
     double vh = 1.0 / (1.0 / t.v + 1.0 / t.s2);
     var = vh;
     mean = vh * (t.mu / t.v + t.A / t.s2);

@@ -52,6 +52,7 @@ class ep_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("leaf_size", ctypes.c_int32),
         ("hbm_cap_bytes", ctypes.c_int64),
+        ("profile_kernels", ctypes.c_int32),
     ]
 
 
@@ -59,7 +60,8 @@ class ep_sweep_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve",
                                                 "ms_selinv", "ms_star", "ms_total")] + \
                [(k, ctypes.c_int64) for k in ("updated", "skipped_cavity", "skipped_negsite")] + \
-               [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu")]
+               [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu", "mfma_ms")] + \
+               [("mfma_launches", ctypes.c_int64)]
 
 
 class ep_structure_stats(ctypes.Structure):
