@@ -6,21 +6,21 @@
  * extinction mapping" (arXiv:1708.09705).
  *
  * Model.  The unknown is the log extinction pseudo-density
- * f(x) = ln(rho kappa)(x) (Sec. 4: dA/ds = rho kappa) on a regular n^3 grid.
+ * f(x) = ln(rho kappa)(x) (Sec. 5: dA/ds = rho kappa) on a regular n^3 grid.
  * Its prior is a Gaussian process (Sec. 2) with a turbulence-shaped
  * covariance (Sec. 1: Kolmogorov spectrum truncated at the outer scale, here
  * a Matern nu = 1/3 kernel with length scale equal to the outer scale)
  * tapered to a compact support and made sparse by a Vecchia
  * (inverse-Cholesky) precision Q0.  Each star n at a known distance
- * (Sec. 3, simplified case) has extinction A_n = integral of exp(f) along
+ * (Sec. 4.1, simplified case) has extinction A_n = integral of exp(f) along
  * its sightline; its likelihood is N(A_obs_n | A_n, sigma_n^2).
  *
- * Inference is parallel expectation propagation (Sec. 3.1; App. A): one
+ * Inference is parallel expectation propagation (Sec. 4.1; App. A.2): one
  * Gaussian site per star in a_n = ln A_n, cavity -> tilted -> moment
  * matching, every site updated from the same posterior in a sweep.  The
  * posterior precision Q = Q0 + sum_n tau_n g_n g_n^T is factored by a
  * multifrontal Cholesky on the GPU; the posterior mean comes from the
- * triangular solves and the marginal variances (Sec. 4: maps of marginal
+ * triangular solves and the marginal variances (Sec. 5: maps of marginal
  * posterior mean and variance) from selected inversion.
  *
  * Conventions
@@ -75,7 +75,7 @@ typedef struct ep_config {
     int32_t moments;           /* ep_moments */
     /* EP controls */
     double damping;            /* delta in (0, 1]: site <- (1-delta) old + delta new */
-    double cavity_var_floor;   /* cavity variance floor (Sec. 4), 0 = none */
+    double cavity_var_floor;   /* cavity variance floor (Sec. 5), 0 = none */
     int32_t relinearize;       /* 1: relinearise each sweep at the posterior mean;
                                   0: freeze g_n, c_n at the prior mean */
     /* device */
@@ -127,17 +127,17 @@ void ep_config_default(ep_config *cfg);
  * nested-dissection ordering and the front layout (host), upload the
  * structure, and set every site to zero and the linearisation point to the
  * prior mean.  xyz: n_stars x 3 positions (pc, cube frame) at known
- * distances (Sec. 3); A_obs: observed extinction (mag; in the
+ * distances (Sec. 4.1); A_obs: observed extinction (mag; in the
  * gauss_linear mode the observed log-extinction); sigma: 1-sigma noise
  * (> 0).  Errors: INVALID_ARG (bad config, non-finite input, star outside
  * the cube), OOM, DEVICE. */
 int ep_init(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *A_obs,
             const double *sigma, ep_ctx **out);
 
-/* One parallel EP sweep (App. A, parallel procedure): linearise every
+/* One parallel EP sweep (App. A.2, parallel procedure): linearise every
  * sightline at the current point, assemble and factor the posterior
  * precision, posterior mean and selected inverse, then for every star the
- * cavity, the tilted moments (Sec. 3.1) and the damped site update; finally
+ * cavity, the tilted moments (Sec. 4.1) and the damped site update; finally
  * move the linearisation point to the posterior mean.  stats may be NULL.
  * On NOT_PD or NUMERIC the sites and the linearisation point are left as
  * they were before the call. */
@@ -173,7 +173,7 @@ int ep_set_linpoint(ep_ctx *ctx, const double *f);
 int ep_star_state(ep_ctx *ctx, double *lnA, double *cav_mu, double *cav_var, double *lnZ,
                   double *tmean, double *tvar);
 
-/* Batch tilted moments (the per-star moment matching of Sec. 3.1), without
+/* Batch tilted moments (the per-star moment matching of Sec. 4.1), without
  * a context.  mode: ep_likelihood.  Inputs and outputs: n doubles each,
  * host memory. */
 int ep_tilted_moments(int32_t mode, int64_t n, const double *mu_c, const double *v_c,

@@ -144,7 +144,7 @@ static int gk_adapt(epo_vfun f, const void *ctx, int nf, const double *bp, int n
 
 /* ------------------------------------------------------------------------ */
 /* Covariance: Matern nu=1/3 (the 3-D Kolmogorov spectrum truncated at the   */
-/* outer scale, Sec. 1 / Sec. 3) times a compactly supported Wendland taper. */
+/* outer scale, Sec. 1) times a compactly supported Wendland taper. */
 /* ------------------------------------------------------------------------ */
 typedef struct { double nu, x; } kv_ctx;
 static void kv_integrand(double t, const void *c, double *out) {
@@ -369,7 +369,7 @@ double epo_prior_quadform(int64_t N, const int64_t *rowptr, const int32_t *col, 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Line-of-sight operator (pseudo-density f = ln(rho kappa), Sec. 4).        */
+/* Line-of-sight operator (pseudo-density f = ln(rho kappa), Sec. 5).        */
 /* A_n = sum_t w_t exp(F(s_t)),  F = trilinear interpolation of f,           */
 /* g_n = d ln A_n / d f,  c_n = ln A_n - g_n . f                              */
 /* Samples: T = max(1, ceil(d/step)) equal steps from the observer.           */
@@ -489,7 +489,7 @@ void epo_los_eval(const epo_grid *g, const double *xs, const double *f, int m, c
 }
 
 /* ------------------------------------------------------------------------ */
-/* Tilted moments of one star (Sec. 3.1 tilted distribution; App. A moment  */
+/* Tilted moments of one star (Sec. 4.1 tilted distribution; App. A.2 moment*/
 /* matching): cavity N(a; mu, v) times the likelihood N(A_obs; e^a, s^2).    */
 /* Returns ln Z, the mean and the variance of the normalised tilted.         */
 /* mode 0: extinction likelihood N(A_obs | e^a, s^2) (plain integral)         */

@@ -7,16 +7,16 @@ library; the two meet only at the seeded raw draws of ``synth``.
 What it computes (Sale & Magorrian, arXiv:1708.09705):
 
 * prior: a Gaussian process on the log pseudo-density f = ln(rho kappa)
-  (Sec. 4, dA/ds = rho kappa) on a regular grid, Matern nu = 1/3 (the 3-D
+  (Sec. 5, dA/ds = rho kappa) on a regular grid, Matern nu = 1/3 (the 3-D
   Kolmogorov spectrum truncated at the outer scale, Sec. 1) tapered to a
   compact support, made sparse by a Vecchia (inverse-Cholesky) precision
   Q0 = (I - B)^T D^{-1} (I - B);
 * likelihood: one factor per star on a_n = ln A_n, A_n the line-of-sight
   integral of exp(f); linearised at the current posterior mean each sweep;
-* EP: Gaussian sites in a_n, parallel updates (App. A, parallel procedure),
-  cavity -> tilted -> moment matching (Sec. 3.1 and App. A);
+* EP: Gaussian sites in a_n, parallel updates (App. A.2, parallel procedure),
+  cavity -> tilted -> moment matching (Sec. 4.1 and App. A.2);
 * outputs: posterior mean and marginal variance of f at the grid nodes
-  (Sec. 4, maps of marginal posterior mean and variance).
+  (Sec. 5, maps of marginal posterior mean and variance).
 
 The linear algebra is the plain definition (dense numpy Cholesky/inverse);
 use it on small grids only.

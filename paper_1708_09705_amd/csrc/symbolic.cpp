@@ -3,7 +3,7 @@
 // the sightline cliques, and the multifrontal layout of the Cholesky factor.
 //
 // Why the ordering is special.  Every star contributes the rank-one term
-// tau_n g_n g_n^T (the Gaussian site of the per-star EP factor, Sec. 3.1),
+// tau_n g_n g_n^T (the Gaussian site of the per-star EP factor, Sec. 4.1),
 // so all nodes on one sightline form a clique, and every sightline starts
 // at the observer.  A separator must therefore avoid cutting sightlines:
 // planes through the observer never do, whatever their orientation, while

@@ -1,12 +1,12 @@
 """Workload presets and seeded raw draws.
 
 The paper's own test catalogue (simulated Gaia stars in a thin anticentre
-letter-box, Sec. 4) is not available; these synthetic workloads stand in for it.
+letter-box, Sec. 5) is not available; these synthetic workloads stand in for it.
 Each preset fixes a grid, a prior and a star sample:
 
 * stars either uniform in the cube, or from an exponential disc seen from an
   observer at the centre of the y = 0 face looking along +y (the anticentre
-  direction, as in Sec. 4): density proportional to
+  direction, as in Sec. 5): density proportional to
   exp(-y / 2.6 kpc - |z - L/2| / 0.3 kpc), restricted to |b| <= 10 degrees
   (sin b = (z - L/2) / d) and d <= d_max, by rejection to an exact count;
 * per-star noise scales sigma (1-sigma, in mag) from the preset's law;

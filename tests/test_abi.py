@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports every function include/ep.h declares;
+argument validation fails cleanly before any device work (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ep.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(ep_\w+)\s*\(", src, re.M)))
+
+
+def _lib():
+    from paper_1708_09705_amd import ep as E
+    so = E.LIB_PATH
+    if not os.path.exists(so):
+        from paper_1708_09705_amd import build
+        build.build()
+    return E, E.load()
+
+
+def test_every_declared_symbol_is_exported():
+    E, L = _lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(E.EXPORTS) <= set(names)
+
+
+def test_config_default_and_struct_size():
+    E, L = _lib()
+    c = E.make_config()
+    assert c.n == 16 and c.box_pc == 1000.0 and c.prior_mean == -7.0
+    assert tuple(c.observer_pc) == (500.0, 0.0, 500.0)
+    assert c.damping == 1.0 and c.relinearize == 1 and c.los_step_pc == 2.0
+
+
+def test_invalid_inputs_rejected_before_device_work():
+    E, L = _lib()
+    xyz = np.array([[100.0, 200.0, 300.0], [400.0, 500.0, 600.0]])
+    A = np.array([0.3, 0.4])
+    s = np.array([0.05, 0.05])
+    cfg = E.make_config()
+    for bad in (dict(A=np.array([math.nan, 0.4])), dict(s=np.array([0.05, 0.0])),
+                dict(xyz=np.array([[100.0, 200.0, 300.0], [400.0, 500.0, 1200.0]]))):
+        with pytest.raises(E.EPError) as ei:
+            E.ep_init(cfg, bad.get("xyz", xyz), bad.get("A", A), bad.get("s", s))
+        assert ei.value.code == -1
+    for field, val in (("n", 1), ("damping", 0.0), ("box_pc", -1.0), ("precision", 7)):
+        c = E.make_config(**{field: val})
+        with pytest.raises(E.EPError) as ei:
+            E.ep_init(c, xyz, A, s)
+        assert ei.value.code == -1
+    with pytest.raises(E.EPError) as ei:
+        E.ep_tilted_moments(0, [0.0], [-1.0], [0.3], [0.05])
+    assert ei.value.code == -1
+    assert b"no error" != L.ep_last_error(None)

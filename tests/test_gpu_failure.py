@@ -1,0 +1,67 @@
+"""Failure handling and checkpoint/resume on the GPU, forced from the host."""
+import numpy as np
+import pytest
+
+from gpu_common import relerr, small_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _E():
+    from paper_1708_09705_amd import ep as E
+    return E
+
+
+def test_not_pd_leaves_state_unchanged():
+    E = _E()
+    cfg, gcfg, raw, f, A, sl = small_case(n=8, L=500.0, stars=60, leaf=32)
+    g = E.EP(gcfg, raw["xyz"], A, raw["sigma"])
+    g.sweep()
+    tau, nu = g.sites()
+    bad = tau.copy()
+    bad[:5] = -1e7          # makes the posterior precision indefinite
+    g.set_sites(bad, nu)
+    f0 = g.linpoint()
+    with pytest.raises(E.EPError) as ei:
+        g.sweep()
+    assert ei.value.name == "NOT_PD"
+    t2, n2 = g.sites()
+    assert np.array_equal(t2, bad) and np.array_equal(n2, nu)
+    assert np.array_equal(g.linpoint(), f0)
+    g.set_sites(tau, nu)     # recovers
+    g.sweep()
+    g.close()
+
+
+def test_allocation_cap_gives_oom():
+    E = _E()
+    cfg, gcfg, raw, f, A, sl = small_case(n=8, L=500.0, stars=60, leaf=32)
+    with pytest.raises(E.EPError) as ei:
+        E.EP(dict(gcfg, hbm_cap_bytes=1 << 20), raw["xyz"], A, raw["sigma"])
+    assert ei.value.name == "OOM"
+
+
+def test_checkpoint_resume_reproduces_the_next_sweep():
+    E = _E()
+    cfg, gcfg, raw, f, A, sl = small_case(n=10, L=600.0, stars=150, leaf=48)
+    a = E.EP(gcfg, raw["xyz"], A, raw["sigma"])
+    a.sweep()
+    a.sweep()
+    tau, nu = a.sites()
+    fh = a.linpoint()
+    b = E.EP(gcfg, raw["xyz"], A, raw["sigma"])
+    b.set_sites(tau, nu)
+    b.set_linpoint(fh)
+    a.sweep()
+    b.sweep()
+    ta, na = a.sites()
+    tb, nb = b.sites()
+    assert relerr(tb, ta) < 1e-12 and np.allclose(nb, na, rtol=1e-12, atol=1e-12)
+    assert relerr(b.posterior_mean(), a.posterior_mean()) < 1e-12
+
+
+def test_tiny_noise_gives_finite_degenerate_moments():
+    E = _E()
+    lnZ, m, v = E.ep_tilted_moments(0, [-0.5, -2.0], [0.3, 1.0], [0.6, 0.2], [1e-9, 1e-9])
+    assert np.all(np.isfinite(lnZ)) and np.all(v > 0)
+    assert np.allclose(m, np.log([0.6, 0.2]), atol=1e-12)

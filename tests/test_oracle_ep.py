@@ -1,4 +1,4 @@
-"""Pins for the oracle's parallel EP (Sec. 3.1 steps; App. A parallel
+"""Pins for the oracle's parallel EP (Sec. 4.1 steps; App. A.2 parallel
 procedure and moment matching)."""
 import math
 
@@ -99,7 +99,7 @@ def test_moment_matching_invariant_at_convergence():
 
 def test_calibration_of_posterior_on_true_field():
     """z-scores of the true field under the EP posterior are roughly standard
-    normal where the data constrain it (cf. the residual histograms of Sec. 4)."""
+    normal where the data constrain it (cf. the residual histograms of Sec. 5)."""
     w, cfg = _small(n=10, L=660.0, stars=400)
     raw = draw(w)
     f_true, A_obs, sl = epo.simulate(cfg, raw)

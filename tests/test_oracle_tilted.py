@@ -1,6 +1,6 @@
 """Pins for the oracle's tilted moments: cavity N(a; mu, v) times the
 extinction likelihood N(A | e^a, s^2) (the per-star tilted distribution and
-its first two moments, Sec. 3.1 and App. A)."""
+its first two moments, Sec. 4.1 and App. A.2)."""
 import math
 
 import numpy as np
