@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--leaf", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the mixed-precision run (FP32 factor + FP64 refinement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -92,23 +94,31 @@ def main():
     t0 = time.perf_counter()
     f_true, A = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
     log(f"simulated {w.name}: {time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    g = E.EP(cfg, raw["xyz"], A, raw["sigma"])
-    st = g.structure()
-    log(f"init {time.perf_counter() - t0:.1f} s; structure {st}")
-    for i in range(args.warmup):
-        s = g.sweep()
-        log(f"warmup {i}: {s['ms_total']:.1f} ms")
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s = g.sweep()
-        stats.append(s)
-        log(f"step {i}: {json.dumps({k: round(v, 3) if isinstance(v, float) else v for k, v in s.items()})}")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    S = g.S
+
+    def run(prec):
+        c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec)
+        t0 = time.perf_counter()
+        g = E.EP(c, raw["xyz"], A, raw["sigma"])
+        st = g.structure()
+        log(f"[{prec}] init {time.perf_counter() - t0:.1f} s; structure {st}")
+        for i in range(args.warmup):
+            s = g.sweep()
+            log(f"[{prec}] warmup {i}: {s['ms_total']:.1f} ms")
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            s = g.sweep()
+            stats.append(s)
+            log(f"[{prec}] step {i}: {json.dumps({k: round(v, 3) if isinstance(v, float) else v for k, v in s.items()})}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        mean, var = (g.posterior_mean(), g.marginal_var()) if args.mixed else (None, None)
+        g.close()
+        return st, stats, wall, mean, var
+
+    st, stats, wall, mean64, var64 = run("fp64")
+    S = w.n_stars
     value = S * args.steps / wall
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
           ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")}
@@ -147,7 +157,18 @@ def main():
                      "avg_launch_ms": mfma_ms / max(launches, 1),
                      "algorithmic_flop_per_step": flops},
     }
-    g.close()
+    if args.mixed:
+        st32, stats32, wall32, mean32, var32 = run("mixed")
+        line["mixed"] = {
+            "value": S * args.steps / wall32, "unit": "star-updates/s", "ms_per_step": wall32 / args.steps * 1e3,
+            "phases_ms": {k: float(np.mean([s[k] for s in stats32])) for k in ph},
+            "refine_iters": int(stats32[-1]["refine_iters"]),
+            "refine_residual": float(stats32[-1]["refine_residual"]),
+            "rel_err_vs_fp64": {
+                "posterior_mean": float(np.max(np.abs(mean32 - mean64) / np.abs(mean64))),
+                "marginal_var": float(np.max(np.abs(var32 - var64) / np.abs(var64)))},
+            "note": "same warm-up and step count as the FP64 run; errors after the same sweeps",
+        }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.preset, args.cpu_sample)
     print(json.dumps(line), flush=True)

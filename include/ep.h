@@ -71,7 +71,9 @@ typedef struct ep_config {
     double los_step_pc;        /* trapezoid steps are d/T <= this, T = ceil(d/step) */
     /* modes */
     int32_t likelihood;        /* ep_likelihood */
-    int32_t precision;         /* ep_precision */
+    int32_t precision;         /* ep_precision: FP64, or MIXED = FP32 factor on FP32 MFMA
+                                  with FP64 diagonal pivots, FP64 refinement of the
+                                  mean and FP64 selected inversion */
     int32_t moments;           /* ep_moments */
     /* EP controls */
     double damping;            /* delta in (0, 1]: site <- (1-delta) old + delta new */
@@ -84,6 +86,8 @@ typedef struct ep_config {
     int32_t leaf_size;         /* ordering: largest dissection leaf (0 = 512) */
     int64_t hbm_cap_bytes;     /* refuse to allocate more than this (0 = no cap) */
     int32_t profile_kernels;   /* 1: time every MFMA tile-kernel launch with HIP events */
+    int32_t mixed_fp64_levels; /* mixed precision: factor the top k levels of the
+                                  dissection tree in FP64 (0 = all levels FP32) */
 } ep_config;
 
 typedef struct ep_sweep_stats {
@@ -101,6 +105,8 @@ typedef struct ep_sweep_stats {
     double max_dmu;            /* max |posterior mean - previous linearisation point| */
     double mfma_ms;            /* summed duration of the MFMA tile-kernel launches (profile_kernels) */
     int64_t mfma_launches;     /* number of those launches */
+    int32_t refine_iters;      /* mixed precision: FP64 refinement rounds of the mean */
+    double refine_residual;    /* mixed precision: final ||b - Q mu|| / ||b|| */
 } ep_sweep_stats;
 
 typedef struct ep_structure_stats {

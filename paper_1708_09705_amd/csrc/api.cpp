@@ -38,11 +38,13 @@ struct FList {
 struct TaskRange {
     int64_t off = 0;
     int64_t n = 0;
+    bool a32 = false;   // some task reads its A operand from the FP32 factor copy
 };
 struct LevelPlan {
     std::vector<FList> potrf;   // per pivot step
     std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k
     Launch extend;              // also the Sigma-gather enumeration
+    Launch conv;                // FP64 -> FP32 copy of the level's fronts (mixed precision)
     Launch fwd_xv, fwd_r, bwd_t, bwd_x;
     FList fronts;
     TaskRange selW, selS21, selS11;
@@ -88,6 +90,13 @@ struct ep_ctx {
     int32_t* d_status = nullptr;
     double *d_fhat = nullptr, *d_b0 = nullptr, *d_borig = nullptr, *d_y = nullptr, *d_x = nullptr, *d_t = nullptr;
     double *d_mu = nullptr, *d_var = nullptr;
+    // mixed precision: FP32 copy of the fronts, prior factor for the residual
+    float* d_f32 = nullptr;
+    int64_t *d_brp = nullptr;
+    int32_t* d_bcol = nullptr;
+    double *d_bval = nullptr, *d_bd = nullptr, *d_u = nullptr, *d_w = nullptr, *d_r = nullptr, *d_dx = nullptr;
+    int ir_iters = 0;
+    double ir_res = 0;
 
     std::vector<LevelPlan> levels;
     std::vector<TaskRange> trtri1, trtri2;   // per doubling stage
@@ -149,6 +158,10 @@ static int32_t front_local(const Symbolic& sym, const Front& f, int64_t newidx) 
     return f.nvpad + (int32_t)(it - b);
 }
 
+static bool is_f32_level(const ep_ctx* ctx, int level) {
+    return ctx->cfg.precision == EP_PREC_MIXED && level < ctx->sym.nlevels - ctx->cfg.mixed_fp64_levels;
+}
+
 static GemmSeg mkseg(int bufA, int64_t a, int64_t sa, int lda, bool ta, bool neg, int bufB, int64_t b, int64_t sb,
                      int ldb, bool tb, int nk) {
     GemmSeg s{};
@@ -174,6 +187,9 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
     const Symbolic& sym = ctx->sym;
     const int64_t nf = (int64_t)sym.fronts.size();
     const int L = sym.nlevels;
+    // where each front's factor lives: FP32 copy in mixed precision, except
+    // in the top mixed_fp64_levels levels of the dissection tree
+    auto Lbuf_of = [&](int f) { return is_f32_level(ctx, sym.fronts[f].level) ? (int)BUF_F32 : (int)BUF_FRONTS; };
     // X layout
     ctx->xoff.assign(nf, 0);
     int64_t xo = 0;
@@ -246,6 +262,9 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             fr.emplace_back(f, MR);
         }
         P.extend = mk_launch(ea);
+        std::vector<std::pair<int, int64_t>> cv;
+        for (int f : lv[l]) cv.emplace_back(f, M_of(f));
+        P.conv = mk_launch(cv);
         P.fwd_xv = mk_launch(fx);
         P.fwd_r = mk_launch(fr);
         P.bwd_t = mk_launch(fx);
@@ -278,12 +297,13 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                     t.ldc = (int32_t)ldw;
                     t.flags = 1 | (1 << 4) | (BUF_W << 8);
                     // sum_{j=k}^{P-1} L(R_i, j) X(j, k)
-                    t.s[0] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
+                    t.s[0] = mkseg(Lbuf_of(f), Fr.off + nvp + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
                                    xb + TS * k + TS * k * nvp, TS, (int)nvp, false, Pf - k);
                     tasks.push_back(t);
                 }
         }
         P.selW.n = (int64_t)tasks.size() - P.selW.off;
+        P.selW.a32 = is_f32_level(ctx, l);
         P.selS21.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
@@ -368,12 +388,13 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                     t.ldc = (int32_t)ldt;
                     t.flags = 1 | (1 << 4) | (BUF_W << 8);
                     // sum_{j=k}^{b0-1} L(i, j) X(j, k)
-                    t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
+                    t.s[0] = mkseg(Lbuf_of(f), Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
                                    xb + TS * k + TS * k * nvp, TS, (int)nvp, false, b0 - k);
                     tasks.push_back(t);
                 }
         }
         r1.n = (int64_t)tasks.size() - r1.off;
+        for (int64_t q = r1.off; q < r1.off + r1.n; q++) r1.a32 |= ((tasks[q].s[0].flags >> 8) & 3) == BUF_F32;
         r2.off = (int64_t)tasks.size();
         for (auto& pr : pairs) {
             int f, t0, b0, b1;
@@ -419,7 +440,8 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
         err = "unknown likelihood";
         return EP_ERR_INVALID_ARG;
     }
-    if (c->precision != EP_PREC_FP64) { err = "only the FP64 precision mode is available"; return EP_ERR_INVALID_ARG; }
+    if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED) { err = "unknown precision"; return EP_ERR_INVALID_ARG; }
+    if (c->mixed_fp64_levels < 0) { err = "mixed_fp64_levels must be >= 0"; return EP_ERR_INVALID_ARG; }
     if (c->moments != EP_MOM_QUADRATURE) { err = "only quadrature moments are available"; return EP_ERR_INVALID_ARG; }
     for (int a = 0; a < 3; a++)
         if (!(c->observer_pc[a] >= 0 && c->observer_pc[a] <= c->box_pc)) {
@@ -576,6 +598,12 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     TRY(dev_alloc(ctx, &ctx->d_X, ctx->X_elems));
     TRY(dev_alloc(ctx, &ctx->d_W, ctx->W_elems));
     TRY(dev_alloc(ctx, &ctx->d_err, 1));
+    if (c.precision == EP_PREC_MIXED) TRY(dev_alloc(ctx, &ctx->d_f32, sym.total_elems));
+    TRY(upload(ctx, &ctx->d_brp, ctx->vec.rowptr));
+    TRY(upload(ctx, &ctx->d_bcol, ctx->vec.col));
+    TRY(upload(ctx, &ctx->d_bval, ctx->vec.val));
+    TRY(upload(ctx, &ctx->d_bd, ctx->vec.d));
+    for (double** p : {&ctx->d_u, &ctx->d_w, &ctx->d_r, &ctx->d_dx}) TRY(dev_alloc(ctx, p, N));
     // stars
     std::vector<double> vx(xyz, xyz + 3 * S), vA(A, A + S), vs(sig, sig + S);
     TRY(upload(ctx, &ctx->d_xyz, vx));
@@ -619,13 +647,20 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     // free host-side bulk no longer needed
     std::vector<double>().swap(ctx->vec.val);
     std::vector<int32_t>().swap(ctx->vec.col);
+    std::vector<int64_t>().swap(ctx->vec.rowptr);
     return EP_OK;
 }
 
 // ---------------------------------------------------------------------------
 // sweep pieces
 // ---------------------------------------------------------------------------
-static Bufs bufs(ep_ctx* ctx) { return Bufs{ctx->d_fronts, ctx->d_X, ctx->d_W}; }
+static Bufs bufs(ep_ctx* ctx) { return Bufs{ctx->d_fronts, ctx->d_X, ctx->d_W, ctx->d_f32}; }
+// buffers for the solves of one level: the FP32 factor copy only where that level was factored in FP32
+static Bufs level_bufs(ep_ctx* ctx, int lvl) {
+    Bufs b = bufs(ctx);
+    if (!is_f32_level(ctx, lvl)) b.F32 = nullptr;
+    return b;
+}
 
 static bool frozen(const ep_ctx* ctx) {
     return ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR || ctx->cfg.relinearize == 0;
@@ -651,7 +686,6 @@ static void enqueue_assemble(ep_ctx* ctx) {
     launch_assemble_stars(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->max_support);
     hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st);
     launch_assemble_b(st, ctx->SD, ctx->d_borig);
-    launch_gather_perm(st, ctx->d_perm, ctx->d_borig, ctx->d_y, ctx->g.N());
 }
 
 // Optional per-launch timing of the MFMA tile kernels (cfg.profile_kernels).
@@ -674,7 +708,29 @@ static void kt_end(ep_ctx* ctx, int64_t ntasks) {
 static void enqueue_factor(ep_ctx* ctx) {
     hipStream_t st = ctx->stream;
     Bufs b = bufs(ctx);
-    for (auto& P : ctx->levels) {
+    for (int lvl = 0; lvl < (int)ctx->levels.size(); lvl++) {
+        auto& P = ctx->levels[lvl];
+        if (is_f32_level(ctx, lvl)) {
+            launch_to_f32(st, ctx->d_batches + P.conv.be_off, P.conv.nbe, P.conv.ntasks, ctx->F, b);
+            for (size_t k = 0; k < P.potrf.size(); k++) {
+                launch_potrf32(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
+                const Launch& t = P.trsm[k];
+                kt_begin(ctx, t.ntasks);
+                launch_trsm32(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
+                kt_end(ctx, t.ntasks);
+                const Launch& s = P.inner[k];
+                kt_begin(ctx, s.ntasks);
+                launch_syrk_inner32(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
+                kt_end(ctx, s.ntasks);
+                const Launch& r = P.trail[k];
+                kt_begin(ctx, r.ntasks);
+                launch_syrk_trail32(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
+                kt_end(ctx, r.ntasks);
+            }
+            const Launch& e = P.extend;
+            launch_extend_add32(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
+            continue;
+        }
         for (size_t k = 0; k < P.potrf.size(); k++) {
             launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
             const Launch& t = P.trsm[k];
@@ -695,18 +751,20 @@ static void enqueue_factor(ep_ctx* ctx) {
     }
     for (size_t s = 0; s < ctx->trtri1.size(); s++) {
         kt_begin(ctx, ctx->trtri1[s].n);
-        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri1[s].off, ctx->trtri1[s].n, b);
+        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri1[s].off, ctx->trtri1[s].n, b, ctx->trtri1[s].a32);
         kt_end(ctx, ctx->trtri1[s].n);
         kt_begin(ctx, ctx->trtri2[s].n);
-        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri2[s].off, ctx->trtri2[s].n, b);
+        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri2[s].off, ctx->trtri2[s].n, b, false);
         kt_end(ctx, ctx->trtri2[s].n);
     }
 }
 
-static void enqueue_solve(ep_ctx* ctx) {
+// L L^T x = y for y (elimination order) in d_y, consumed; x to out (node order)
+static void enqueue_tri_solve(ep_ctx* ctx, double* out) {
     hipStream_t st = ctx->stream;
-    Bufs b = bufs(ctx);
-    for (auto& P : ctx->levels) {
+    for (int lvl = 0; lvl < (int)ctx->levels.size(); lvl++) {
+        auto& P = ctx->levels[lvl];
+        Bufs b = level_bufs(ctx, lvl);
         launch_fwd_xv(st, ctx->d_batches + P.fwd_xv.be_off, P.fwd_xv.nbe, P.fwd_xv.ntasks, ctx->F, b, ctx->d_y,
                       ctx->d_t);
         launch_fwd_r(st, ctx->d_batches + P.fwd_r.be_off, P.fwd_r.nbe, P.fwd_r.ntasks, ctx->F, b, ctx->d_t,
@@ -715,12 +773,49 @@ static void enqueue_solve(ep_ctx* ctx) {
     }
     for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
         auto& P = ctx->levels[l];
+        Bufs b = level_bufs(ctx, l);
         launch_bwd_t(st, ctx->d_batches + P.bwd_t.be_off, P.bwd_t.nbe, P.bwd_t.ntasks, ctx->F, b, ctx->d_y, ctx->d_x,
                      ctx->d_t);
         launch_bwd_x(st, ctx->d_batches + P.bwd_x.be_off, P.bwd_x.nbe, P.bwd_x.ntasks, ctx->F, b, ctx->d_t,
                      ctx->d_x);
     }
-    launch_scatter_perm(st, ctx->d_perm, ctx->d_x, ctx->d_mu, ctx->g.N());
+    launch_scatter_perm(st, ctx->d_perm, ctx->d_x, out, ctx->g.N());
+}
+
+static double host_norm(const std::vector<double>& v) {
+    double s = 0;
+    for (double x : v) s += x * x;
+    return std::sqrt(s);
+}
+
+// Posterior mean mu = Q^{-1} b into d_mu.  With the FP32 factor (mixed
+// precision) the FP64 residual r = b - Q mu is solved again with the factor
+// and added back until ||r|| <= 1e-12 ||b|| (at most 10 rounds).
+static int run_solve(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->g.N();
+    launch_gather_perm(st, ctx->d_perm, ctx->d_borig, ctx->d_y, N);
+    enqueue_tri_solve(ctx, ctx->d_mu);
+    ctx->ir_iters = 0;
+    ctx->ir_res = 0;
+    if (ctx->cfg.precision != EP_PREC_MIXED) return EP_OK;
+    std::vector<double> hb(N), hr(N);
+    HIPCHK(hipMemcpyAsync(hb.data(), ctx->d_borig, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double bn = std::max(host_norm(hb), 1e-300);
+    for (int it = 0; it <= 10; it++) {
+        launch_residual(st, N, ctx->d_brp, ctx->d_bcol, ctx->d_bval, ctx->d_bd, ctx->SD, ctx->d_borig, ctx->d_mu,
+                        ctx->d_u, ctx->d_w, ctx->d_r);
+        HIPCHK(hipMemcpyAsync(hr.data(), ctx->d_r, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->ir_res = host_norm(hr) / bn;
+        if (!(ctx->ir_res > 1e-12) || it == 10) break;
+        launch_gather_perm(st, ctx->d_perm, ctx->d_r, ctx->d_y, N);
+        enqueue_tri_solve(ctx, ctx->d_dx);
+        launch_add(st, N, ctx->d_mu, ctx->d_dx);
+        ctx->ir_iters = it + 1;
+    }
+    return EP_OK;
 }
 
 static void enqueue_selinv(ep_ctx* ctx) {
@@ -731,7 +826,7 @@ static void enqueue_selinv(ep_ctx* ctx) {
         launch_sigma_gather(st, ctx->d_batches + P.extend.be_off, P.extend.nbe, P.extend.ntasks, ctx->F, b);
         for (const TaskRange* r : {&P.selW, &P.selS21, &P.selS11}) {
             kt_begin(ctx, r->n);
-            launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b);
+            launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b, r->a32);
             kt_end(ctx, r->n);
         }
     }
@@ -780,7 +875,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     } guard{ev};
     ctx->kt_used = 0;
     TRY(run_factor(ctx, ev));
-    enqueue_solve(ctx);
+    TRY(run_solve(ctx));
     HIPCHK(hipEventRecord(ev[4], st));
     enqueue_selinv(ctx);
     HIPCHK(hipEventRecord(ev[5], st));
@@ -842,6 +937,8 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         stats->max_dmu = dmu;
         stats->mfma_ms = 0;
         stats->mfma_launches = (int64_t)(ctx->kt_used / 2);
+        stats->refine_iters = ctx->ir_iters;
+        stats->refine_residual = ctx->ir_res;
         for (size_t i = 0; i + 1 < ctx->kt_used; i += 2) stats->mfma_ms += ev_ms(ctx->kt_ev[i], ctx->kt_ev[i + 1]);
     }
     return EP_OK;
@@ -877,6 +974,7 @@ void ep_config_default(ep_config* c) {
     c->leaf_size = 0;
     c->hbm_cap_bytes = 0;
     c->profile_kernels = 0;
+    c->mixed_fp64_levels = 0;
 }
 
 void ep_free(ep_ctx* ctx) {
@@ -923,7 +1021,7 @@ int ep_posterior_mean(ep_ctx* ctx, double* out) {
     if (!ctx || !out) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
     TRY(run_factor(ctx, nullptr));
-    enqueue_solve(ctx);
+    TRY(run_solve(ctx));
     HIPCHK(hipMemcpyAsync(out, ctx->d_mu, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());

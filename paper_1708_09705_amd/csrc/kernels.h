@@ -10,7 +10,7 @@ constexpr int TS = 64;   // dense tile edge (doubles)
 constexpr int PW = 8;    // factorization panel width in tiles
 
 // Base buffers a tile task may address.
-enum Buf : int { BUF_FRONTS = 0, BUF_X = 1, BUF_W = 2 };
+enum Buf : int { BUF_FRONTS = 0, BUF_X = 1, BUF_W = 2, BUF_F32 = 3 };
 
 // One K-segment of a tile product: sum_t op(A_t) op(B_t), A_t = A + t*sa.
 struct GemmSeg {
@@ -49,9 +49,10 @@ struct BatchEnt {
 };
 
 struct Bufs {
-    double* fronts;
-    double* X;
-    double* W;
+    double* fronts;   // FP64 fronts: assembly, FP64 factor, selected inverse
+    double* X;        // L11^{-1} of every front
+    double* W;        // scratch
+    float* F32;       // FP32 copy of the fronts for the mixed-precision factor (or null)
 };
 
 // ---- launch wrappers (all asynchronous on 'st') ----
@@ -59,7 +60,7 @@ void launch_fill(hipStream_t st, double* p, int64_t n, double v);
 void launch_scatter_set(hipStream_t st, double* base, const int64_t* dest, const double* val, int64_t n);
 void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int64_t n, double v);
 
-void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b);
+void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, bool a32);
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
@@ -126,6 +127,18 @@ void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p);
 void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
                          const double* sig, double* lnZ, double* mean, double* var);
 void set_gauss_legendre(hipStream_t st);
+
+// mixed precision factor (FP32 storage and MFMA, FP64 diagonal pivots)
+void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+void launch_potrf32(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
+void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
+void launch_syrk_inner32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
+void launch_syrk_trail32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b);
+void launch_extend_add32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+// r = b - Q x in FP64 (Q = Vecchia prior precision + star sites), for refinement
+void launch_residual(hipStream_t st, int64_t N, const int64_t* rp, const int32_t* col, const double* val,
+                     const double* d, StarsDev s, const double* b, const double* x, double* u, double* w, double* r);
+void launch_add(hipStream_t st, int64_t n, double* x, const double* dx);
 void launch_maxabs_diff(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
 
 }  // namespace ep

@@ -60,22 +60,16 @@ struct Stage {
     double a[16], b[16];
 };
 
-__device__ __forceinline__ void stage_load(Stage& p, const double* A, int lda, bool ta, const double* B, int ldb, bool tb) {
+// Thread (lo = tid % 64, hi = tid / 64) reads element lo + (hi + 4r) ld of a
+// column-major tile: row lo of column hi + 4r.  Whether that is A[i][k] or
+// A[k][i] (transposed operand) is decided when it is written to LDS.
+template <typename TA, typename TB>
+__device__ __forceinline__ void stage_load(Stage& p, const TA* A, int lda, const TB* B, int ldb) {
     const int tid = threadIdx.x, lo = tid & 63, hi = tid >> 6;
-    if (!ta) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) p.a[r] = A[lo + (int64_t)(hi + 4 * r) * lda];        // A[i=lo][k=hi+4r]
-    } else {
+    for (int r = 0; r < 16; r++) p.a[r] = (double)A[lo + (int64_t)(hi + 4 * r) * lda];
 #pragma unroll
-        for (int r = 0; r < 16; r++) p.a[r] = A[lo + (int64_t)(hi + 4 * r) * lda];        // A^T: k=lo, i=hi+4r
-    }
-    if (!tb) {
-#pragma unroll
-        for (int r = 0; r < 16; r++) p.b[r] = B[lo + (int64_t)(hi + 4 * r) * ldb];        // B[k=lo][j=hi+4r]
-    } else {
-#pragma unroll
-        for (int r = 0; r < 16; r++) p.b[r] = B[lo + (int64_t)(hi + 4 * r) * ldb];        // B^T: j=lo, k=hi+4r
-    }
+    for (int r = 0; r < 16; r++) p.b[r] = (double)B[lo + (int64_t)(hi + 4 * r) * ldb];
 }
 
 // sA holds op(A) as [k][i], sB holds op(B) as [k][j] (row stride LDP)
@@ -114,16 +108,17 @@ __device__ __forceinline__ void tile_mma(d4 acc[2][2], const double* sA, const d
     }
 }
 
-__device__ __forceinline__ void seg_run(d4 acc[2][2], double* sA, double* sB, const double* A, int64_t sa, int lda,
-                               bool ta, double sgn, const double* B, int64_t sb, int ldb, bool tb, int nk) {
+template <typename TA, typename TB>
+__device__ __forceinline__ void seg_run(d4 acc[2][2], double* sA, double* sB, const TA* A, int64_t sa, int lda,
+                                        bool ta, double sgn, const TB* B, int64_t sb, int ldb, bool tb, int nk) {
     if (nk <= 0) return;
     Stage p;
-    stage_load(p, A, lda, ta, B, ldb, tb);
+    stage_load(p, A, lda, B, ldb);
     for (int t = 0; t < nk; t++) {
         __syncthreads();
         stage_store(p, sA, sB, ta, tb, sgn);
         __syncthreads();
-        if (t + 1 < nk) stage_load(p, A + (t + 1) * sa, lda, ta, B + (t + 1) * sb, ldb, tb);
+        if (t + 1 < nk) stage_load(p, A + (t + 1) * sa, lda, B + (t + 1) * sb, ldb);
         tile_mma(acc, sA, sB);
     }
 }
@@ -165,11 +160,19 @@ __device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
         for (int b = 0; b < 2; b++) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
+// A32: the task list may hold A operands in the FP32 copy of the factor
+// (mixed precision), upcast on load.  A separate instance keeps the all-FP64
+// kernel within the register budget of two waves per SIMD.
+template <bool A32>
 __device__ __forceinline__ void seg_apply(d4 acc[2][2], double* sA, double* sB, const Bufs& bufs, const GemmSeg& S) {
-    const double* A = buf_of(bufs, (S.flags >> 8) & 3) + S.a;
+    const int ba = (S.flags >> 8) & 3;
     const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
-    seg_run(acc, sA, sB, A, S.sa, S.lda, S.flags & 1, (S.flags & 4) ? -1.0 : 1.0, B, S.sb, S.ldb, (S.flags & 2) != 0,
-            S.nk);
+    const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
+    const double sgn = (S.flags & 4) ? -1.0 : 1.0;
+    if (A32 && ba == BUF_F32)
+        seg_run(acc, sA, sB, bufs.F32 + S.a, S.sa, S.lda, ta, sgn, B, S.sb, S.ldb, tb, S.nk);
+    else
+        seg_run(acc, sA, sB, buf_of(bufs, ba) + S.a, S.sa, S.lda, ta, sgn, B, S.sb, S.ldb, tb, S.nk);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
@@ -185,6 +188,7 @@ __device__ __forceinline__ int64_t xcd_task(int64_t n) {
     return t;
 }
 
+template <bool A32>
 __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
     __shared__ double sA[TS * LDP];
     __shared__ double sB[TS * LDP];
@@ -194,16 +198,19 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask* __restrict__
     d4 acc[2][2];
     acc_zero(acc);
     const int nseg = (T.flags >> 4) & 3;
-    if (nseg > 0) seg_apply(acc, sA, sB, bufs, T.s[0]);
-    if (nseg > 1) seg_apply(acc, sA, sB, bufs, T.s[1]);
+    if (nseg > 0) seg_apply<A32>(acc, sA, sB, bufs, T.s[0]);
+    if (nseg > 1) seg_apply<A32>(acc, sA, sB, bufs, T.s[1]);
     double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c;
     int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
     tile_store(acc, sA, C, T.ldc, mode);
 }
 
-void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b) {
+void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, bool a32) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_gemm_tasks, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
+    if (a32)
+        hipLaunchKernelGGL(k_gemm_tasks<true>, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
+    else
+        hipLaunchKernelGGL(k_gemm_tasks<false>, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,8 +490,9 @@ __global__ __launch_bounds__(256) void k_fwd_xv(const BatchEnt* __restrict__ be,
     }
 }
 
+template <typename LT>
 __global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
-                                               FrontsDev F, Bufs bufs, const double* __restrict__ z,
+                                               FrontsDev F, const LT* __restrict__ Lbuf, const double* __restrict__ z,
                                                double* __restrict__ y) {
     __shared__ double v[TS];
     __shared__ double part[4][TS];
@@ -495,7 +503,7 @@ __global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, 
     const int i = (int)(t - be[e].base);
     const int nv = F.nv[f], nvp = F.nvpad[f], m = F.m[f], nr = F.nr[f];
     const int64_t first = F.first[f];
-    const double* base = bufs.fronts + F.off[f];
+    const LT* base = Lbuf + F.off[f];
     const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
     double acc = 0.0;
     const int P = nvp / TS;
@@ -506,9 +514,9 @@ __global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, 
             v[threadIdx.x] = l < nv ? z[first + l] : 0.0;
         }
         __syncthreads();
-        const double* T = base + nvp + (int64_t)TS * i + (int64_t)TS * k * m;
+        const LT* T = base + nvp + (int64_t)TS * i + (int64_t)TS * k * m;
 #pragma unroll
-        for (int c = 0; c < 16; c++) acc += T[r + (int64_t)(cg * 16 + c) * m] * v[cg * 16 + c];
+        for (int c = 0; c < 16; c++) acc += (double)T[r + (int64_t)(cg * 16 + c) * m] * v[cg * 16 + c];
     }
     part[cg][r] = acc;
     __syncthreads();
@@ -527,7 +535,8 @@ __global__ void k_copy_v(const int32_t* __restrict__ flist, FrontsDev F, const d
 }
 
 // transposed tile-vector product through LDS: out[c] += sum_r T[r][c] v[r]
-__device__ __forceinline__ void tgemv_tile(double* sT, const double* T, int64_t ld, const double* v, double& acc) {
+template <typename LT>
+__device__ __forceinline__ void tgemv_tile(double* sT, const LT* T, int64_t ld, const double* v, double& acc) {
     const int tid = threadIdx.x;
     __syncthreads();
     {
@@ -535,7 +544,7 @@ __device__ __forceinline__ void tgemv_tile(double* sT, const double* T, int64_t 
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             int c = (tid >> 6) + 4 * q;
-            sT[c * LDP + r] = T[r + (int64_t)c * ld];
+            sT[c * LDP + r] = (double)T[r + (int64_t)c * ld];
         }
     }
     __syncthreads();
@@ -544,8 +553,9 @@ __device__ __forceinline__ void tgemv_tile(double* sT, const double* T, int64_t 
     for (int q = 0; q < 16; q++) acc += sT[c * LDP + rg * 16 + q] * v[rg * 16 + q];
 }
 
+template <typename LT>
 __global__ __launch_bounds__(256) void k_bwd_t(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
-                                               FrontsDev F, Bufs bufs, const double* __restrict__ y,
+                                               FrontsDev F, const LT* __restrict__ Lbuf, const double* __restrict__ y,
                                                const double* __restrict__ x, double* __restrict__ tout) {
     __shared__ double sT[TS * LDP];
     __shared__ double v[TS];
@@ -557,7 +567,7 @@ __global__ __launch_bounds__(256) void k_bwd_t(const BatchEnt* __restrict__ be, 
     const int k = (int)(t - be[e].base);
     const int nv = F.nv[f], nvp = F.nvpad[f], m = F.m[f], nr = F.nr[f];
     const int64_t first = F.first[f];
-    const double* base = bufs.fronts + F.off[f];
+    const LT* base = Lbuf + F.off[f];
     const int32_t* rows = F.rrows + F.rptr[f];
     const int MR = (nr + TS - 1) / TS;
     double acc = 0.0;
@@ -623,7 +633,12 @@ void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
 void launch_fwd_r(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                   const double* t, double* y) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_fwd_r, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, t, y);
+    if (b.F32)
+        hipLaunchKernelGGL(k_fwd_r<float>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
+                           (const float*)b.F32, t, y);
+    else
+        hipLaunchKernelGGL(k_fwd_r<double>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
+                           (const double*)b.fronts, t, y);
 }
 void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y) {
     if (nf <= 0) return;
@@ -632,7 +647,12 @@ void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, co
 void launch_bwd_t(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                   const double* y, const double* x, double* t) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_bwd_t, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, y, x, t);
+    if (b.F32)
+        hipLaunchKernelGGL(k_bwd_t<float>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
+                           (const float*)b.F32, y, x, t);
+    else
+        hipLaunchKernelGGL(k_bwd_t<double>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
+                           (const double*)b.fronts, y, x, t);
 }
 void launch_bwd_x(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                   const double* t, double* x) {
@@ -1157,6 +1177,368 @@ void set_gauss_legendre(hipStream_t st) {
     hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, st);
     hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), wgt, sizeof(wgt), 0, hipMemcpyHostToDevice, st);
     hipStreamSynchronize(st);
+}
+
+// ===========================================================================
+// Mixed precision: the partial Cholesky of every front in FP32 storage with
+// FP32 MFMA (v_mfma_f32_16x16x4f32) for the column solves and the updates;
+// the diagonal tiles are factored (and inverted) in FP64 from their FP32
+// values.  Extend-add goes back into the FP64 fronts, which each level
+// converts to FP32 before it is factored.
+// ===========================================================================
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int LDF = TS + 4;   // padded LDS row (floats)
+
+struct Stage32 {
+    float a[16], b[16];
+};
+
+template <typename TA, typename TB>
+__device__ __forceinline__ void stage32_load(Stage32& p, const TA* A, int lda, const TB* B, int ldb) {
+    const int tid = threadIdx.x, lo = tid & 63, hi = tid >> 6;
+#pragma unroll
+    for (int r = 0; r < 16; r++) p.a[r] = (float)A[lo + (int64_t)(hi + 4 * r) * lda];
+#pragma unroll
+    for (int r = 0; r < 16; r++) p.b[r] = (float)B[lo + (int64_t)(hi + 4 * r) * ldb];
+}
+
+__device__ __forceinline__ void stage32_store(const Stage32& p, float* sA, float* sB, bool ta, bool tb, float sgn) {
+    const int tid = threadIdx.x, lo = tid & 63, hi = tid >> 6;
+    if (!ta) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sA[(hi + 4 * r) * LDF + lo] = sgn * p.a[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sA[lo * LDF + hi + 4 * r] = sgn * p.a[r];
+    }
+    if (!tb) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sB[lo * LDF + hi + 4 * r] = p.b[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) sB[(hi + 4 * r) * LDF + lo] = p.b[r];
+    }
+}
+
+__device__ __forceinline__ void tile_mma32(f4 acc[2][2], const float* sA, const float* sB) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+        const float* ra = sA + (kk + lk) * LDF;
+        const float* rb = sB + (kk + lk) * LDF;
+        float a0 = ra[wr + li], a1 = ra[wr + 16 + li];
+        float b0 = rb[wc + li], b1 = rb[wc + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+template <typename TA, typename TB>
+__device__ __forceinline__ void seg_run32(f4 acc[2][2], float* sA, float* sB, const TA* A, int64_t sa, int lda,
+                                          bool ta, float sgn, const TB* B, int64_t sb, int ldb, bool tb, int nk) {
+    if (nk <= 0) return;
+    Stage32 p;
+    stage32_load(p, A, lda, B, ldb);
+    for (int t = 0; t < nk; t++) {
+        __syncthreads();
+        stage32_store(p, sA, sB, ta, tb, sgn);
+        __syncthreads();
+        if (t + 1 < nk) stage32_load(p, A + (t + 1) * sa, lda, B + (t + 1) * sb, ldb);
+        tile_mma32(acc, sA, sB);
+    }
+}
+
+// mode 0 accumulate, 1 overwrite
+__device__ __forceinline__ void tile_store32(f4 acc[2][2], float* sC, float* C, int ldc, int mode) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                // v_mfma_f32_16x16x4f32 output: lane l, item r -> row 4(l/16) + r, column l%16
+                int row = wr + 16 * bi + 4 * (lane >> 4) + r;
+                int col = wc + 16 * bj + (lane & 15);
+                sC[col * LDF + row] = acc[bi][bj][r];
+            }
+    __syncthreads();
+    const int row = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        int col = (threadIdx.x >> 6) + 4 * r;
+        float v = sC[col * LDF + row];
+        float* p = C + row + (int64_t)col * ldc;
+        if (mode == 1) *p = v;
+        else *p += v;
+    }
+}
+
+__device__ __forceinline__ void acc32_zero(f4 acc[2][2]) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// FP64 -> FP32 copy of every front of a level; task = (front, 64-column tile)
+__global__ __launch_bounds__(256) void k_to_f32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, FrontsDev F,
+                                                Bufs bufs) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int j0 = TS * (int)(t - be[e].base);
+    const int64_t m = F.m[f];
+    const double* src = bufs.fronts + F.off[f] + j0 * m;
+    float* dst = bufs.F32 + F.off[f] + j0 * m;
+    for (int64_t q = threadIdx.x; q < (int64_t)TS * m; q += 256) dst[q] = (float)src[q];
+}
+
+__global__ __launch_bounds__(256) void k_potrf32(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
+                                                 int* err) {
+    __shared__ double L[TS * LDP];
+    __shared__ double Xs[TS * LDP];
+    __shared__ int bad;
+    const int f = flist[blockIdx.x];
+    const int m = F.m[f];
+    float* A = bufs.F32 + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    {
+        const int i = tid & 63;
+        for (int r = 0; r < 16; r++) {
+            int j = (tid >> 6) + 4 * r;
+            L[i * LDP + j] = (double)A[i + (int64_t)j * m];
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < TS; j++) {
+        if (tid == 0) {
+            double d = L[j * LDP + j];
+            if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
+            L[j * LDP + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double dj = L[j * LDP + j];
+        if (tid > j && tid < TS) L[tid * LDP + j] /= dj;
+        __syncthreads();
+        for (int idx = tid; idx < TS * TS; idx += 256) {
+            int i = idx >> 6, c = idx & 63;
+            if (c > j && i >= c) L[i * LDP + c] -= L[i * LDP + j] * L[c * LDP + j];
+        }
+        __syncthreads();
+    }
+    if (tid < TS) {
+        const int j = tid;
+        for (int i = 0; i < j; i++) Xs[i * LDP + j] = 0.0;
+        Xs[j * LDP + j] = 1.0 / L[j * LDP + j];
+        for (int i = j + 1; i < TS; i++) {
+            double s = 0.0;
+            for (int q = j; q < i; q++) s += L[i * LDP + q] * Xs[q * LDP + j];
+            Xs[i * LDP + j] = -s / L[i * LDP + i];
+        }
+    }
+    __syncthreads();
+    double* Xk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
+    const int ldx = F.nvpad[f];
+    {
+        const int i = tid & 63;
+        for (int r = 0; r < 16; r++) {
+            int j = (tid >> 6) + 4 * r;
+            A[i + (int64_t)j * m] = (i >= j) ? (float)L[i * LDP + j] : 0.0f;
+            Xk[i + (int64_t)j * ldx] = Xs[i * LDP + j];
+        }
+    }
+    if (tid == 0 && bad) atomicCAS(err, 0, f + 1);
+}
+
+__global__ __launch_bounds__(256) void k_trsm32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int k,
+                                                FrontsDev F, Bufs bufs) {
+    __shared__ float sA[TS * LDF];
+    __shared__ float sB[TS * LDF];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int i = k + 1 + (int)(t - be[e].base);
+    const int m = F.m[f];
+    float* Aik = bufs.F32 + F.off[f] + (int64_t)TS * i + (int64_t)TS * k * m;
+    const double* Xkk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
+    f4 acc[2][2];
+    acc32_zero(acc);
+    seg_run32(acc, sA, sB, Aik, 0, m, false, 1.0f, Xkk, 0, F.nvpad[f], true, 1);
+    tile_store32(acc, sA, Aik, m, 1);
+}
+
+__global__ __launch_bounds__(256) void k_syrk_inner32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                      int kk, FrontsDev F, Bufs bufs) {
+    __shared__ float sA[TS * LDF];
+    __shared__ float sB[TS * LDF];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int m = F.m[f], M = m / TS;
+    int j = kk + 1;
+    int64_t r = t - be[e].base;
+    while (r >= M - j) { r -= M - j; j++; }
+    const int i = j + (int)r;
+    float* base = bufs.F32 + F.off[f];
+    f4 acc[2][2];
+    acc32_zero(acc);
+    seg_run32(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * kk * m, 0, m, false, -1.0f,
+              base + (int64_t)TS * j + (int64_t)TS * kk * m, 0, m, true, 1);
+    tile_store32(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
+}
+
+__global__ __launch_bounds__(256) void k_syrk_trail32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int g,
+                                                      FrontsDev F, Bufs bufs) {
+    __shared__ float sA[TS * LDF];
+    __shared__ float sB[TS * LDF];
+    const int64_t t = xcd_task(ntasks);
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    const int m = F.m[f];
+    const int P = F.nvpad[f] / TS;
+    const int k0 = PW * g;
+    const int gend = min(k0 + PW, P);
+    int ii, jj;
+    tri_decode(t - be[e].base, ii, jj);
+    const int i = gend + ii, j = gend + jj;
+    float* base = bufs.F32 + F.off[f];
+    f4 acc[2][2];
+    acc32_zero(acc);
+    seg_run32(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0f,
+              base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, gend - k0);
+    tile_store32(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
+}
+
+// update block of the FP32 front added into the FP64 parent
+__global__ __launch_bounds__(256) void k_extend_add32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                      FrontsDev F, Bufs bufs) {
+    __shared__ int32_t rel_i[TS], rel_j[TS];
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    int ti, tj;
+    tri_decode(t - be[e].base, ti, tj);
+    const int p = F.parent[f];
+    const int nr = F.nr[f], nvp = F.nvpad[f], m = F.m[f], mp = F.m[p];
+    const int32_t* rel = F.relmap + F.rptr[f];
+    if (threadIdx.x < TS) {
+        int a = TS * ti + threadIdx.x;
+        rel_i[threadIdx.x] = a < nr ? rel[a] : -1;
+    } else if (threadIdx.x < 2 * TS) {
+        int b = TS * tj + threadIdx.x - TS;
+        rel_j[threadIdx.x - TS] = b < nr ? rel[b] : -1;
+    }
+    __syncthreads();
+    const float* src = bufs.F32 + F.off[f] + nvp + (int64_t)nvp * m;
+    double* dst = bufs.fronts + F.off[p];
+    const int r = threadIdx.x & 63;
+    const int a = TS * ti + r;
+    if (rel_i[r] < 0) return;
+    for (int q = threadIdx.x >> 6; q < TS; q += 4) {
+        const int b = TS * tj + q;
+        if (rel_j[q] < 0 || b > a) continue;
+        atomicAdd(dst + rel_i[r] + (int64_t)rel_j[q] * mp, (double)src[a + (int64_t)b * m]);
+    }
+}
+
+void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+}
+void launch_potrf32(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(k_potrf32, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
+}
+void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_trsm32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
+}
+void launch_syrk_inner32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_syrk_inner32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b);
+}
+void launch_syrk_trail32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_syrk_trail32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, g, F, b);
+}
+void launch_extend_add32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_extend_add32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+}
+
+// ===========================================================================
+// FP64 residual of the posterior system for iterative refinement:
+//   r = b - Q x,  Q x = (I-B)^T D^{-1} (I-B) x + sum_n tau_n g_n (g_n . x)
+// ===========================================================================
+// u = D^{-1} (I - B) x  (rows of B)
+__global__ void k_q0_rows(int64_t N, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const double* __restrict__ val, const double* __restrict__ d, const double* __restrict__ x,
+                          double* __restrict__ u) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        double s = x[p];
+        for (int64_t e = rp[p]; e < rp[p + 1]; e++) s -= val[e] * x[col[e]];
+        u[p] = s / d[p];
+    }
+}
+// w = u - B^T u  (w initialised to u by the caller)
+__global__ void k_q0_cols(int64_t N, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const double* __restrict__ val, const double* __restrict__ u, double* __restrict__ w) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        const double up = u[p];
+        if (up == 0.0) continue;
+        for (int64_t e = rp[p]; e < rp[p + 1]; e++) atomicAdd(w + col[e], -val[e] * up);
+    }
+}
+// w += sum_n tau_n g_n (g_n . x), one wavefront per star
+__global__ __launch_bounds__(256) void k_gtg(StarsDev s, const double* __restrict__ x, double* __restrict__ w) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t star = (int64_t)blockIdx.x * 4 + wv;
+    if (star >= s.n) return;
+    const double tau = s.tau[star];
+    if (tau == 0.0) return;
+    const int64_t p0 = s.ptr[star];
+    const int cnt = (int)(s.ptr[star + 1] - p0);
+    double dot = 0.0;
+    for (int k = lane; k < cnt; k += 64) dot += s.g[p0 + k] * x[s.nodes[p0 + k]];
+    dot = wave_sum(dot);
+    const double c = tau * dot;
+    for (int k = lane; k < cnt; k += 64) atomicAdd(w + s.nodes[p0 + k], c * s.g[p0 + k]);
+}
+// r = b - w
+__global__ void k_sub(int64_t n, const double* __restrict__ b, const double* __restrict__ w, double* __restrict__ r) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = b[i] - w[i];
+}
+// x += dx
+__global__ void k_add(int64_t n, double* __restrict__ x, const double* __restrict__ dx) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += dx[i];
+}
+
+void launch_residual(hipStream_t st, int64_t N, const int64_t* rp, const int32_t* col, const double* val,
+                     const double* d, StarsDev s, const double* b, const double* x, double* u, double* w, double* r) {
+    unsigned g = grid_for(N);
+    hipLaunchKernelGGL(k_q0_rows, dim3(g), dim3(256), 0, st, N, rp, col, val, d, x, u);
+    (void)hipMemcpyAsync(w, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_q0_cols, dim3(g), dim3(256), 0, st, N, rp, col, val, u, w);
+    if (s.n > 0) hipLaunchKernelGGL(k_gtg, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s, x, w);
+    hipLaunchKernelGGL(k_sub, dim3(g), dim3(256), 0, st, N, b, w, r);
+}
+void launch_add(hipStream_t st, int64_t n, double* x, const double* dx) {
+    if (n > 0) hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, st, n, x, dx);
 }
 
 }  // namespace ep

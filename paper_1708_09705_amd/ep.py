@@ -53,6 +53,7 @@ class ep_config(ctypes.Structure):
         ("leaf_size", ctypes.c_int32),
         ("hbm_cap_bytes", ctypes.c_int64),
         ("profile_kernels", ctypes.c_int32),
+        ("mixed_fp64_levels", ctypes.c_int32),
     ]
 
 
@@ -61,7 +62,8 @@ class ep_sweep_stats(ctypes.Structure):
                                                 "ms_selinv", "ms_star", "ms_total")] + \
                [(k, ctypes.c_int64) for k in ("updated", "skipped_cavity", "skipped_negsite")] + \
                [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu", "mfma_ms")] + \
-               [("mfma_launches", ctypes.c_int64)]
+               [("mfma_launches", ctypes.c_int64), ("refine_iters", ctypes.c_int32),
+                ("refine_residual", ctypes.c_double)]
 
 
 class ep_structure_stats(ctypes.Structure):
