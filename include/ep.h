@@ -74,7 +74,8 @@ typedef struct ep_config {
     int32_t precision;         /* ep_precision: FP64, or MIXED = FP32 factor on FP32 MFMA
                                   with FP64 diagonal pivots, FP64 refinement of the
                                   mean and FP64 selected inversion */
-    int32_t moments;           /* ep_moments */
+    int32_t moments;           /* ep_moments: QUADRATURE, or SURROGATE = gated network
+                                  with quadrature fallback (needs ep_mlp_load) */
     /* EP controls */
     double damping;            /* delta in (0, 1]: site <- (1-delta) old + delta new */
     double cavity_var_floor;   /* cavity variance floor (Sec. 5), 0 = none */
@@ -88,6 +89,8 @@ typedef struct ep_config {
     int32_t profile_kernels;   /* 1: time every MFMA tile-kernel launch with HIP events */
     int32_t mixed_fp64_levels; /* mixed precision: factor the top k levels of the
                                   dissection tree in FP64 (0 = all levels FP32) */
+    double surrogate_tol;      /* surrogate moments: accept a star when the network's
+                                  moments and the Gauss-Hermite check agree to this */
 } ep_config;
 
 typedef struct ep_sweep_stats {
@@ -107,6 +110,7 @@ typedef struct ep_sweep_stats {
     int64_t mfma_launches;     /* number of those launches */
     int32_t refine_iters;      /* mixed precision: FP64 refinement rounds of the mean */
     double refine_residual;    /* mixed precision: final ||b - Q mu|| / ||b|| */
+    int64_t surrogate_fallbacks; /* surrogate moments: stars sent to the quadrature */
 } ep_sweep_stats;
 
 typedef struct ep_structure_stats {
@@ -194,6 +198,55 @@ int ep_tilted_moments(int32_t mode, int64_t n, const double *mu_c, const double 
  * f_true (n^3) and A_obs (n_stars), either may be NULL. */
 int ep_simulate(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *sigma,
                 const double *eps, const double *xi, double *f_true, double *A_obs);
+
+/* ---- Tilted-moment surrogate (the per-star moment matching of Sec. 4.1) ----
+ * A 4-128-128-128-3 SiLU network predicts corrections to a Gaussian baseline
+ * of the tilted distribution (the likelihood linearised in a = ln A at
+ * ln max(A, sigma), times the cavity).  Weights: EP_MLP_NPARAM floats, in
+ * the order W1 (4x128) b1 W2 (128x128) b2 W3 b3 W4 (128x3) b4, then the
+ * feature mean and std (4 + 4) and the target mean and std (3 + 3).
+ * Inference runs with BF16 operands on MFMA.  The gate: a 20-node
+ * Gauss-Hermite rule centred at the prediction computes the moments of the
+ * true integrand, a 32-node rule re-centred at those moments checks them, and
+ * the star is accepted when the passes agree to surrogate_tol (relative in
+ * var and in mean on the scale max(|mean|, sd), absolute in ln Z) with an
+ * analytic bound on the tails beyond 8 sd added, and the predicted variance
+ * is within a factor 4; accepted stars take the second
+ * pass's moments, the others fall back to the quadrature. */
+#define EP_MLP_NPARAM 34065
+
+typedef struct ep_mlp_hyper {
+    int32_t epochs;            /* passes over the data */
+    int32_t batch;             /* samples per Adam step */
+    double lr;                 /* peak learning rate (cosine decay to 0) */
+    uint64_t seed;             /* initialisation and shuffling */
+} ep_mlp_hyper;
+
+/* Train on n tuples.  inputs: n x 4 (cavity mean mu_c, cavity variance v_c,
+ * observed A, noise sigma); targets: n x 3 (ln Z, mean, variance of the
+ * tilted distribution).  Mean squared error on the standardised baseline
+ * corrections; Adam.  weights_out: EP_MLP_NPARAM floats; loss_per_epoch:
+ * epochs doubles (may be NULL). */
+int ep_mlp_train(const ep_mlp_hyper *hp, int64_t n, const double *inputs, const double *targets,
+                 float *weights_out, double *loss_per_epoch, int32_t device);
+
+/* Gated surrogate moments for n tuples (inputs as above).  out3: n x 3
+ * (ln Z, mean, var), the Gauss-Hermite moments where accepted and the
+ * network's otherwise; errest: the gate's error estimate; accepted: 1/0.
+ * errest and accepted may be NULL.  weights == NULL centres the gate at the
+ * analytic baseline instead of the network (what the network is measured
+ * against). */
+int ep_mlp_predict(const float *weights, int64_t n, const double *inputs, double tol, double *out3,
+                   double *errest, int32_t *accepted, int32_t device);
+
+/* One forward and backward pass on already standardised features (n x 4)
+ * and targets (n x 3): the loss (mean over samples of the summed squared
+ * error) and its gradient for the trainable prefix of the weights. */
+int ep_mlp_loss_grad(const float *weights, int64_t n, const float *xstd, const float *ystd, double *loss,
+                     float *grad, int32_t device);
+
+/* Give a context the network used when cfg.moments = EP_MOM_SURROGATE. */
+int ep_mlp_load(ep_ctx *ctx, const float *weights);
 
 /* Structure and memory figures of a context. */
 int ep_structure(const ep_ctx *ctx, ep_structure_stats *out);

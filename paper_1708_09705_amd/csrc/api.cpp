@@ -18,11 +18,15 @@
 #include "../../include/ep.h"
 #include "kernels.h"
 #include "prior.h"
+#include "surrogate.h"
 #include "symbolic.h"
 
 using namespace ep;
 
 static thread_local std::string g_tls_err = "no error";
+namespace ep {
+void set_last_error(const std::string& m) { g_tls_err = m; }
+}
 
 namespace {
 
@@ -97,6 +101,12 @@ struct ep_ctx {
     double *d_bval = nullptr, *d_bd = nullptr, *d_u = nullptr, *d_w = nullptr, *d_r = nullptr, *d_dx = nullptr;
     int ir_iters = 0;
     double ir_res = 0;
+    // tilted-moment surrogate
+    float* d_mlp_P = nullptr;
+    short* d_mlp_bf = nullptr;
+    int32_t *d_fb_list = nullptr, *d_fb_count = nullptr;
+    bool mlp_loaded = false;
+    int64_t fallbacks = 0;
 
     std::vector<LevelPlan> levels;
     std::vector<TaskRange> trtri1, trtri2;   // per doubling stage
@@ -442,7 +452,8 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
     }
     if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED) { err = "unknown precision"; return EP_ERR_INVALID_ARG; }
     if (c->mixed_fp64_levels < 0) { err = "mixed_fp64_levels must be >= 0"; return EP_ERR_INVALID_ARG; }
-    if (c->moments != EP_MOM_QUADRATURE) { err = "only quadrature moments are available"; return EP_ERR_INVALID_ARG; }
+    if (c->moments != EP_MOM_QUADRATURE && c->moments != EP_MOM_SURROGATE) { err = "unknown moments mode"; return EP_ERR_INVALID_ARG; }
+    if (c->moments == EP_MOM_SURROGATE && !(c->surrogate_tol > 0)) { err = "surrogate_tol must be > 0"; return EP_ERR_INVALID_ARG; }
     for (int a = 0; a < 3; a++)
         if (!(c->observer_pc[a] >= 0 && c->observer_pc[a] <= c->box_pc)) {
             err = "observer must lie in the cube";
@@ -629,6 +640,11 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     for (auto p : varr) TRY(dev_alloc(ctx, p, N));
     launch_fill(ctx->stream, ctx->d_fhat, N, ctx->pp.mean);
     set_gauss_legendre(ctx->stream);
+    set_gauss_hermite(ctx->stream);
+    TRY(dev_alloc(ctx, &ctx->d_mlp_P, MLP_NPARAM));
+    TRY(dev_alloc(ctx, &ctx->d_mlp_bf, 2 * 128 * 128));
+    TRY(dev_alloc(ctx, &ctx->d_fb_list, S));
+    TRY(dev_alloc(ctx, &ctx->d_fb_count, 1));
 
     FrontsDev& F = ctx->F;
     F.off = ctx->d_off; F.m = ctx->d_m; F.nv = ctx->d_nv; F.nvpad = ctx->d_nvpad; F.nr = ctx->d_nr;
@@ -866,6 +882,10 @@ static double ev_ms(hipEvent_t a, hipEvent_t b) {
 
 static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     hipStream_t st = ctx->stream;
+    if (ctx->cfg.moments == EP_MOM_SURROGATE && !ctx->mlp_loaded) {
+        ctx->err = "surrogate moments need network weights (ep_mlp_load)";
+        return EP_ERR_STATE;
+    }
     const int64_t N = ctx->g.N(), S = ctx->S;
     hipEvent_t ev[8];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -898,7 +918,20 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     HIPCHK(hipEventRecord(ev[6], st));
     launch_cavity(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->d_mu, ctx->max_support);
     EpParams p{ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR ? 1 : 0, ctx->cfg.damping, ctx->cfg.cavity_var_floor};
-    launch_tilted_update(st, ctx->SD, p);
+    ctx->fallbacks = 0;
+    if (ctx->cfg.moments == EP_MOM_SURROGATE && p.mode == 0) {
+        // gated surrogate for every star, quadrature for the rejected ones
+        HIPCHK(hipMemsetAsync(ctx->d_fb_count, 0, sizeof(int32_t), st));
+        launch_mlp_tilted(st, ctx->SD, p, ctx->d_mlp_P, ctx->d_mlp_bf, ctx->cfg.surrogate_tol, ctx->d_fb_list,
+                          ctx->d_fb_count, nullptr, nullptr, nullptr);
+        int32_t nfb = 0;
+        HIPCHK(hipMemcpyAsync(&nfb, ctx->d_fb_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->fallbacks = nfb;
+        launch_tilted_update(st, ctx->SD, p, ctx->d_fb_list, nfb);
+    } else {
+        launch_tilted_update(st, ctx->SD, p);
+    }
     HIPCHK(hipEventRecord(ev[7], st));
     HIPCHK(hipGetLastError());
     std::vector<int32_t> status(S);
@@ -939,6 +972,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         stats->mfma_launches = (int64_t)(ctx->kt_used / 2);
         stats->refine_iters = ctx->ir_iters;
         stats->refine_residual = ctx->ir_res;
+        stats->surrogate_fallbacks = ctx->fallbacks;
         for (size_t i = 0; i + 1 < ctx->kt_used; i += 2) stats->mfma_ms += ev_ms(ctx->kt_ev[i], ctx->kt_ev[i + 1]);
     }
     return EP_OK;
@@ -975,6 +1009,7 @@ void ep_config_default(ep_config* c) {
     c->hbm_cap_bytes = 0;
     c->profile_kernels = 0;
     c->mixed_fp64_levels = 0;
+    c->surrogate_tol = 1e-4;
 }
 
 void ep_free(ep_ctx* ctx) {
@@ -1091,6 +1126,24 @@ int ep_star_state(ep_ctx* ctx, double* lnA, double* cav_mu, double* cav_var, dou
     if (tmean) HIPCHK(hipMemcpyAsync(tmean, ctx->d_tmean, b, hipMemcpyDeviceToHost, st));
     if (tvar) HIPCHK(hipMemcpyAsync(tvar, ctx->d_tvar, b, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    return EP_OK;
+}
+
+int ep_mlp_load(ep_ctx* ctx, const float* weights) {
+    if (!ctx || !weights) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    for (int i = 0; i < MLP_NPARAM; i++)
+        if (!std::isfinite(weights[i])) { ctx->err = "network weights must be finite"; return EP_ERR_INVALID_ARG; }
+    for (int k = 0; k < 7; k++)
+        if (!(weights[MLP_NTRAIN + 4 + (k < 4 ? k : k + 3)] > 0)) {
+            ctx->err = "standardisation scales must be > 0";
+            return EP_ERR_INVALID_ARG;
+        }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    HIPCHK(hipMemcpyAsync(ctx->d_mlp_P, weights, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, ctx->stream));
+    mlp_make_bf16(ctx->stream, ctx->d_mlp_P, ctx->d_mlp_bf);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    ctx->mlp_loaded = true;
     return EP_OK;
 }
 

@@ -123,7 +123,8 @@ struct EpParams {
     double damping;
     double vfloor;
 };
-void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p);
+// list: optional subset of stars (nlist entries)
+void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p, const int32_t* list = nullptr, int64_t nlist = 0);
 void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
                          const double* sig, double* lnZ, double* mean, double* var);
 void set_gauss_legendre(hipStream_t st);

@@ -1060,11 +1060,12 @@ __device__ __forceinline__ void tilted_gauss(const TiltP& t, double& lnZ, double
 }
 
 // Cavity from the q-marginal, tilted moments, damped site update.
-__global__ __launch_bounds__(256) void k_tilted_update(StarsDev s, EpParams P) {
+__global__ __launch_bounds__(256) void k_tilted_update(StarsDev s, EpParams P, const int32_t* list, int64_t nlist) {
     __shared__ double sbw[4][72];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t star = (int64_t)blockIdx.x * 4 + w;
-    const bool active = star < s.n;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    const bool active = list ? i < nlist : i < s.n;
+    const int64_t star = list ? (active ? (int64_t)list[i] : 0) : i;
     double tau = 0.0, nu = 0.0, tau_c = 1.0, nu_c = 0.0, mu_c = 0.0, v_c = 1.0;
     bool skip = !active;
     TiltP tp{0.0, 1.0, 1.0, 1.0};   // benign stand-in for idle waves
@@ -1115,9 +1116,10 @@ __global__ __launch_bounds__(256) void k_tilted_update(StarsDev s, EpParams P) {
     }
 }
 
-void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p) {
-    if (s.n <= 0) return;
-    hipLaunchKernelGGL(k_tilted_update, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s, p);
+void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p, const int32_t* list, int64_t nlist) {
+    const int64_t n = list ? nlist : s.n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tilted_update, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, s, p, list, nlist);
 }
 
 __global__ __launch_bounds__(256) void k_tilted_batch(int mode, int64_t n, const double* mu, const double* v,

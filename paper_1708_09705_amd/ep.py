@@ -54,6 +54,7 @@ class ep_config(ctypes.Structure):
         ("hbm_cap_bytes", ctypes.c_int64),
         ("profile_kernels", ctypes.c_int32),
         ("mixed_fp64_levels", ctypes.c_int32),
+        ("surrogate_tol", ctypes.c_double),
     ]
 
 
@@ -63,7 +64,7 @@ class ep_sweep_stats(ctypes.Structure):
                [(k, ctypes.c_int64) for k in ("updated", "skipped_cavity", "skipped_negsite")] + \
                [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu", "mfma_ms")] + \
                [("mfma_launches", ctypes.c_int64), ("refine_iters", ctypes.c_int32),
-                ("refine_residual", ctypes.c_double)]
+                ("refine_residual", ctypes.c_double), ("surrogate_fallbacks", ctypes.c_int64)]
 
 
 class ep_structure_stats(ctypes.Structure):
@@ -75,7 +76,14 @@ class ep_structure_stats(ctypes.Structure):
 
 EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_free",
            "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
-           "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure")
+           "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
+           "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load")
+MLP_NPARAM = 34065
+
+
+class ep_mlp_hyper(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 _lib = None
 
@@ -109,9 +117,14 @@ def load(path: str | None = None):
     L.ep_tilted_moments.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, i32]
     L.ep_simulate.argtypes = [cfgp, i64, vp, vp, vp, vp, vp, vp]
     L.ep_structure.argtypes = [vp, ctypes.POINTER(ep_structure_stats)]
+    L.ep_mlp_train.argtypes = [ctypes.POINTER(ep_mlp_hyper), i64, vp, vp, vp, vp, i32]
+    L.ep_mlp_predict.argtypes = [vp, i64, vp, ctypes.c_double, vp, vp, vp, i32]
+    L.ep_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, i32]
+    L.ep_mlp_load.argtypes = [vp, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
-                 "ep_tilted_moments", "ep_simulate", "ep_structure"):
+                 "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
+                 "ep_mlp_loss_grad", "ep_mlp_load"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -225,6 +238,46 @@ def ep_simulate(cfg: ep_config, xyz, sigma, eps, xi, lib=None):
     return f, A
 
 
+def ep_mlp_train(inputs, targets, epochs=20, batch=4096, lr=1e-3, seed=1, device=0, lib=None):
+    """Train the tilted-moment surrogate.  inputs (n, 4): mu_c, v_c, A, sigma;
+    targets (n, 3): ln Z, mean, var.  Returns (weights float32, loss per epoch)."""
+    L = lib or load()
+    X = _arr(inputs).reshape(-1, 4)
+    Y = _arr(targets).reshape(-1, 3)
+    if X.shape[0] != Y.shape[0]:
+        raise ValueError("inputs and targets differ in length")
+    w = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = np.zeros(epochs)
+    hp = ep_mlp_hyper(epochs, batch, lr, seed)
+    _check(L, L.ep_mlp_train(ctypes.byref(hp), X.shape[0], _ptr(X), _ptr(Y), _ptr(w), _ptr(loss), device))
+    return w, loss
+
+
+def ep_mlp_predict(weights, inputs, tol=1e-4, device=0, lib=None):
+    """Gated surrogate moments: (out (n,3), error estimate (n,), accepted (n,))."""
+    L = lib or load()
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    X = _arr(inputs).reshape(-1, 4)
+    n = X.shape[0]
+    out = np.zeros((n, 3))
+    err = np.zeros(n)
+    acc = np.zeros(n, dtype=np.int32)
+    _check(L, L.ep_mlp_predict(None if w is None else _ptr(w), n, _ptr(X), tol, _ptr(out), _ptr(err), _ptr(acc),
+                               device))
+    return out, err, acc.astype(bool)
+
+
+def ep_mlp_loss_grad(weights, xstd, ystd, device=0, lib=None):
+    L = lib or load()
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    X = np.ascontiguousarray(xstd, dtype=np.float32).reshape(-1, 4)
+    Y = np.ascontiguousarray(ystd, dtype=np.float32).reshape(-1, 3)
+    loss = np.zeros(1)
+    g = np.zeros(MLP_NPARAM, dtype=np.float32)
+    _check(L, L.ep_mlp_loss_grad(_ptr(w), X.shape[0], _ptr(X), _ptr(Y), _ptr(loss), _ptr(g), device))
+    return float(loss[0]), g
+
+
 # ---- convenience wrapper -----------------------------------------------------
 class EP:
     """One EP context on the GPU."""
@@ -268,6 +321,12 @@ class EP:
         arrs = [np.empty(self.S) for _ in keys]
         _check(self.L, self.L.ep_star_state(self.ctx, *[_ptr(a) for a in arrs]), self.ctx)
         return dict(zip(keys, arrs))
+
+    def load_surrogate(self, weights) -> None:
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} weights")
+        _check(self.L, self.L.ep_mlp_load(self.ctx, _ptr(w)), self.ctx)
 
     def structure(self) -> dict:
         st = ep_structure_stats()
