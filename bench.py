@@ -6,8 +6,11 @@ site update for every star) of the 64^3-grid / 100,000-star workload (4 kpc
 cube, disc-distributed stars, sigma ~ U[0.05, 0.2] mag), FP64 throughout.
 
 value = stars x steps / wall time of the timed steps (whole sweeps; inputs
-resident on the device).  The JSON line also carries the per-phase times,
-the dense-front MFMA roofline and the oracle's CPU baseline.
+resident on the device).  The JSON line also carries the per-star-phase rate
+(stars / time of cavity + tilted moments + site update), the per-phase
+times, the dense-front MFMA roofline, the surrogate + mixed-precision form
+of the same sweeps with its error against the FP64 run, and the oracle's CPU
+baseline.
 """
 from __future__ import annotations
 
@@ -24,6 +27,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per step of the dominant kernel from the rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters, scaled by the copy-kernel calibration (None until
+# counters are taken for the current kernel).
+TRAFFIC_GEMM_TASKS = None
 
 
 def log(*a):
@@ -65,6 +72,20 @@ def cpu_baseline(preset_id: int, n_sample: int) -> dict:
                       f"{t_prior:.1f} s not counted"}
 
 
+def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "ms_per_copy": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,8 +97,17 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
-                    help="skip the mixed-precision run (FP32 factor + FP64 refinement)")
+                    help="skip the surrogate + mixed-precision run (FP32 factor + FP64 refinement, "
+                         "network moments with quadrature fallback)")
+    ap.add_argument("--mixed-quadrature", action="store_true",
+                    help="also run mixed precision with quadrature moments")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the reference kernel that "
+                         "scales the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
               f"design note, not a measured path", file=sys.stderr)
@@ -95,10 +125,16 @@ def main():
     f_true, A = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
     log(f"simulated {w.name}: {time.perf_counter() - t0:.1f} s")
 
-    def run(prec):
-        c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec)
+    weights = np.load(os.path.join(ROOT, "paper_1708_09705_amd", "surrogate_64cube.npy"))
+
+    def run(prec, moments="quadrature"):
+        c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec,
+                          moments=moments)
         t0 = time.perf_counter()
         g = E.EP(c, raw["xyz"], A, raw["sigma"])
+        if moments == "surrogate":
+            g.load_surrogate(weights)
+        prec = f"{prec}/{moments}"
         st = g.structure()
         log(f"[{prec}] init {time.perf_counter() - t0:.1f} s; structure {st}")
         for i in range(args.warmup):
@@ -122,15 +158,18 @@ def main():
     value = S * args.steps / wall
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
           ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")}
-    # Dominant kernel family: the FP64 MFMA tile kernels (trailing/inner
-    # updates, column solves, triangular inverse, selected inversion).  Their
-    # launches are timed with HIP events on the library's stream; the work
-    # counted is the algorithmic (unpadded) flop count of the partial
-    # Cholesky and the selected inversion of every front.
+    # Dominant kernel: k_gemm_tasks, the FP64 MFMA task-list GEMM that forms
+    # the diagonal-block inverses and the selected-inversion products of
+    # every front.  Each launch is timed with HIP events on the library's
+    # stream; the work counted is the algorithmic (unpadded) flop count of
+    # the selected inversion, inverses included.
+    gemm_ms = float(np.mean([s["kernel_ms"]["gemm"] for s in stats]))
+    launches = int(stats[0]["kernel_launches"]["gemm"])
+    flops = st["selinv_flops"]
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    trail_ms = float(np.mean([s["kernel_ms"]["trail"] for s in stats]))
     mfma_ms = float(np.mean([s["mfma_ms"] for s in stats]))
-    launches = int(stats[0]["mfma_launches"])
-    flops = st["factor_flops"] + st["selinv_flops"]
-    achieved = flops / (mfma_ms * 1e-3) / 1e12
+    all_flops = st["factor_flops"] + st["selinv_flops"]
     line = {
         "metric": "EP star-updates/sec (full sweep, plain FP64)",
         "value": value,
@@ -149,26 +188,39 @@ def main():
         "phases_ms": ph,
         "star_phase_updates_per_s": S / (ph["ms_star"] * 1e-3),
         "structure": {k: st[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front", "factor_flops",
-                                         "selinv_flops", "device_bytes")},
+                                         "selinv_flops", "trail_flops", "device_bytes")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "FP64 MFMA tile kernels (k_syrk_trail, k_syrk_inner, k_trsm_step, k_gemm_tasks)",
-                     "launches_per_step": launches, "kernel_ms_per_step": mfma_ms,
-                     "avg_launch_ms": mfma_ms / max(launches, 1),
-                     "algorithmic_flop_per_step": flops},
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": TRAFFIC_GEMM_TASKS,
+                     "kernel": "k_gemm_tasks<false> (FP64 MFMA: diagonal-block inverses + selected inversion)",
+                     "launches_per_step": launches, "kernel_ms_per_step": gemm_ms,
+                     "avg_launch_ms": gemm_ms / max(launches, 1),
+                     "algorithmic_flop_per_step": flops,
+                     "others": {
+                         "k_syrk_trail": {"ms_per_step": trail_ms, "algorithmic_flop_per_step": st["trail_flops"],
+                                          "tflops": st["trail_flops"] / (trail_ms * 1e-3) / 1e12},
+                         "all_mfma_tile_kernels": {"ms_per_step": mfma_ms, "algorithmic_flop_per_step": all_flops,
+                                                   "tflops": all_flops / (mfma_ms * 1e-3) / 1e12}}},
     }
-    if args.mixed:
-        st32, stats32, wall32, mean32, var32 = run("mixed")
-        line["mixed"] = {
+    def leg(prec, moments):
+        st32, stats32, wall32, mean32, var32 = run(prec, moments)
+        ph32 = {k: float(np.mean([s[k] for s in stats32])) for k in ph}
+        return {
             "value": S * args.steps / wall32, "unit": "star-updates/s", "ms_per_step": wall32 / args.steps * 1e3,
-            "phases_ms": {k: float(np.mean([s[k] for s in stats32])) for k in ph},
+            "star_phase_updates_per_s": S / (ph32["ms_star"] * 1e-3),
+            "phases_ms": ph32,
             "refine_iters": int(stats32[-1]["refine_iters"]),
             "refine_residual": float(stats32[-1]["refine_residual"]),
+            "surrogate_fallbacks": int(stats32[-1]["surrogate_fallbacks"]),
             "rel_err_vs_fp64": {
                 "posterior_mean": float(np.max(np.abs(mean32 - mean64) / np.abs(mean64))),
                 "marginal_var": float(np.max(np.abs(var32 - var64) / np.abs(var64)))},
             "note": "same warm-up and step count as the FP64 run; errors after the same sweeps",
         }
+
+    if args.mixed:
+        line["surrogate_mixed"] = leg("mixed", "surrogate")
+        if args.mixed_quadrature:
+            line["mixed_quadrature"] = leg("mixed", "quadrature")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.preset, args.cpu_sample)
     print(json.dumps(line), flush=True)

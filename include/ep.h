@@ -93,6 +93,18 @@ typedef struct ep_config {
                                   moments and the Gauss-Hermite check agree to this */
 } ep_config;
 
+/* Kinds of timed MFMA tile-kernel launches (ep_sweep_stats.kernel_ms):
+ * column-panel triangular solves, in-panel rank updates, trailing updates
+ * after each panel, and the task-list GEMM kernel (diagonal-block inverses
+ * and the selected-inversion products). */
+enum {
+    EP_KK_TRSM = 0,
+    EP_KK_INNER = 1,
+    EP_KK_TRAIL = 2,
+    EP_KK_GEMM = 3,
+    EP_KK_COUNT = 4
+};
+
 typedef struct ep_sweep_stats {
     double ms_linearise;       /* line-of-sight linearisation */
     double ms_assemble;        /* Q and b assembly */
@@ -111,6 +123,8 @@ typedef struct ep_sweep_stats {
     int32_t refine_iters;      /* mixed precision: FP64 refinement rounds of the mean */
     double refine_residual;    /* mixed precision: final ||b - Q mu|| / ||b|| */
     int64_t surrogate_fallbacks; /* surrogate moments: stars sent to the quadrature */
+    double kernel_ms[EP_KK_COUNT];        /* mfma_ms split by kind (EP_KK_*) */
+    int64_t kernel_launches[EP_KK_COUNT]; /* mfma_launches split by kind */
 } ep_sweep_stats;
 
 typedef struct ep_structure_stats {
@@ -122,7 +136,10 @@ typedef struct ep_structure_stats {
     int64_t front_elems;       /* sum of m^2 over fronts (factor / Sigma storage) */
     int64_t max_front;         /* largest front order */
     double factor_flops;       /* partial Cholesky flops of all fronts */
-    double selinv_flops;       /* selected-inversion flops */
+    double selinv_flops;       /* selected-inversion flops, diagonal-block
+                                  inverses included (the EP_KK_GEMM work) */
+    double trail_flops;        /* trailing-update share of factor_flops
+                                  (the EP_KK_TRAIL work) */
     int64_t device_bytes;      /* bytes the context holds on the device */
 } ep_structure_stats;
 

@@ -109,10 +109,11 @@ struct ep_ctx {
     int64_t fallbacks = 0;
 
     std::vector<LevelPlan> levels;
-    std::vector<TaskRange> trtri1, trtri2;   // per doubling stage
+    std::vector<TaskRange> trtri1, trtri1f, trtri2;   // per doubling stage (1f: FP32 factor copy)
     bool linearised = false;                 // g, c valid for the current fhat (frozen modes)
     std::vector<hipEvent_t> kt_ev;           // per-launch timing events (profile_kernels)
     size_t kt_used = 0;
+    std::vector<int> kt_kind;                // EP_KK_* of each timed launch
 
     FrontsDev F{};
     StarsDev SD{};
@@ -184,6 +185,42 @@ static GemmSeg mkseg(int bufA, int64_t a, int64_t sa, int lda, bool ta, bool neg
     s.nk = nk;
     s.flags = (ta ? 1 : 0) | (tb ? 2 : 0) | (neg ? 4 : 0) | (bufA << 8) | (bufB << 10);
     return s;
+}
+
+// Reorder the tasks of one launch for the XCD-contiguous block mapping (the
+// k_gemm_tasks blocks of XCD x run tasks [x per, (x + 1) per) in order): cut
+// the emission order, which keeps operand-sharing tasks together, into eight
+// contiguous pieces of equal work, put each piece longest task first, and pad
+// the pieces to equal length with empty tasks.
+static void balance_range(std::vector<GemmTask>& tasks, TaskRange& r) {
+    if (r.n <= 0) return;
+    auto work = [](const GemmTask& t) {
+        int64_t w = 1;
+        for (int q = 0; q < ((t.flags >> 4) & 3); q++) w += t.s[q].nk;
+        return w;
+    };
+    std::vector<GemmTask> src(tasks.begin() + r.off, tasks.begin() + r.off + r.n);
+    int64_t total = 0;
+    for (const GemmTask& t : src) total += work(t);
+    std::vector<int64_t> cut(9, (int64_t)src.size());
+    cut[0] = 0;
+    int64_t acc = 0;
+    int c = 1;
+    for (int64_t i = 0; i < (int64_t)src.size() && c < 8; i++) {
+        acc += work(src[i]);
+        while (c < 8 && acc * 8 >= total * c) cut[c++] = i + 1;
+    }
+    int64_t per = 0;
+    for (int x = 0; x < 8; x++) per = std::max(per, cut[x + 1] - cut[x]);
+    std::vector<GemmTask> out((size_t)(8 * per), GemmTask{});
+    for (int x = 0; x < 8; x++) {
+        std::stable_sort(src.begin() + cut[x], src.begin() + cut[x + 1],
+                         [&](const GemmTask& a, const GemmTask& b) { return work(a) > work(b); });
+        std::copy(src.begin() + cut[x], src.begin() + cut[x + 1], out.begin() + x * per);
+    }
+    tasks.resize((size_t)r.off);
+    tasks.insert(tasks.end(), out.begin(), out.end());
+    r.n = 8 * per;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,18 +331,25 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             wb += (int64_t)TS * MR_of(lv[l][q]) * (int64_t)sym.fronts[lv[l][q]].nvpad;
         }
         Wmax = std::max(Wmax, wb);
+        // Tasks are 128 x 128 blocks: tile pairs (2p, 2p+1) of rows and of
+        // columns.  Where a pair's second tile lies in the upper triangle of
+        // a lower-triangular operand, that operand is zero there (X holds
+        // zeros above its diagonal), so a pair shares its first tile's K range.
+        auto pair_flags = [](bool rows2, bool cols2, bool noupper) {
+            return (rows2 ? GT_ROWS2 : 0) | (cols2 ? GT_COLS2 : 0) | (noupper ? GT_NOUPPER : 0);
+        };
         P.selW.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int i = 0; i < MR; i++)
-                for (int k = 0; k < Pf; k++) {
+            for (int i = 0; i < MR; i += 2)
+                for (int k = 0; k < Pf; k += 2) {
                     GemmTask t{};
                     t.c = wbase[q] + TS * i + TS * k * ldw;
                     t.ldc = (int32_t)ldw;
-                    t.flags = 1 | (1 << 4) | (BUF_W << 8);
+                    t.flags = 1 | (1 << 4) | (BUF_W << 8) | pair_flags(i + 1 < MR, k + 1 < Pf, false);
                     // sum_{j=k}^{P-1} L(R_i, j) X(j, k)
                     t.s[0] = mkseg(Lbuf_of(f), Fr.off + nvp + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
                                    xb + TS * k + TS * k * nvp, TS, (int)nvp, false, Pf - k);
@@ -314,39 +358,42 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         }
         P.selW.n = (int64_t)tasks.size() - P.selW.off;
         P.selW.a32 = is_f32_level(ctx, l);
+        balance_range(tasks, P.selW);
         P.selS21.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, nvp = Fr.nvpad;
-            for (int i = 0; i < MR; i++)
-                for (int k = 0; k < Pf; k++) {
+            for (int i = 0; i < MR; i += 2)
+                for (int k = 0; k < Pf; k += 2) {
                     GemmTask t{};
                     t.c = Fr.off + nvp + TS * i + TS * k * m;
                     t.ldc = (int32_t)m;
                     int nseg = 0;
-                    // l <= i: S22 tile (i, l) as stored
+                    // l <= i: S22 tiles (i, l), (i+1, l) as stored
                     t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * i + nvp * m, TS * m, (int)m, false, true, BUF_W,
                                         wbase[q] + TS * k * ldw, TS, (int)ldw, false, i + 1);
-                    // l > i: S22 tile (l, i) transposed
+                    // l > i: S22 tiles (l, i), (l, i+1) transposed; at l = i+1
+                    // the second is the (symmetric, fully stored) diagonal tile
                     if (i + 1 < MR)
                         t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * (i + 1) + (nvp + TS * i) * m, TS, (int)m,
                                             true, true, BUF_W, wbase[q] + TS * (i + 1) + TS * k * ldw, TS, (int)ldw,
                                             false, MR - i - 1);
-                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) | pair_flags(i + 1 < MR, k + 1 < Pf, false);
                     tasks.push_back(t);
                 }
         }
         P.selS21.n = (int64_t)tasks.size() - P.selS21.off;
+        balance_range(tasks, P.selS21);
         P.selS11.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int k = 0; k < Pf; k++)
-                for (int j = 0; j <= k; j++) {
+            for (int k = 0; k < Pf; k += 2)
+                for (int j = 0; j <= k; j += 2) {
                     GemmTask t{};
                     t.c = Fr.off + TS * k + TS * j * m;
                     t.ldc = (int32_t)m;
@@ -358,11 +405,12 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                     if (MR > 0)
                         t.s[nseg++] = mkseg(BUF_W, wbase[q] + TS * k * ldw, TS, (int)ldw, true, true, BUF_FRONTS,
                                             Fr.off + nvp + TS * j * m, TS, (int)m, false, MR);
-                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) | pair_flags(k + 1 < Pf, j + 1 < Pf, j == k);
                     tasks.push_back(t);
                 }
         }
         P.selS11.n = (int64_t)tasks.size() - P.selS11.off;
+        balance_range(tasks, P.selS11);
     }
     // ---- inverse of each L11 by doubling over all fronts ----
     // blocks [t0, b0) (top, inverted) and [b0, b1) (bottom, inverted):
@@ -383,28 +431,36 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             }
         }
         Tmax = std::max(Tmax, tb);
-        TaskRange r1, r2;
-        r1.off = (int64_t)tasks.size();
-        for (auto& pr : pairs) {
-            int f, t0, b0, b1;
-            int64_t tbase;
-            std::tie(f, t0, b0, b1, tbase) = pr;
-            const Front& Fr = sym.fronts[f];
-            const int64_t ldt = (int64_t)TS * (b1 - b0), m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int i = b0; i < b1; i++)
-                for (int k = t0; k < b0; k++) {
-                    GemmTask t{};
-                    t.c = tbase + TS * (i - b0) + TS * (k - t0) * ldt;
-                    t.ldc = (int32_t)ldt;
-                    t.flags = 1 | (1 << 4) | (BUF_W << 8);
-                    // sum_{j=k}^{b0-1} L(i, j) X(j, k)
-                    t.s[0] = mkseg(Lbuf_of(f), Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
-                                   xb + TS * k + TS * k * nvp, TS, (int)nvp, false, b0 - k);
-                    tasks.push_back(t);
-                }
+        TaskRange r1, r1f, r2;
+        // T = L(bot, top) X(top, top): FP64 and FP32 factor copies in
+        // separate launches
+        for (int pass = 0; pass < 2; pass++) {
+            TaskRange& rr = pass == 0 ? r1 : r1f;
+            rr.off = (int64_t)tasks.size();
+            rr.a32 = pass == 1;
+            for (auto& pr : pairs) {
+                int f, t0, b0, b1;
+                int64_t tbase;
+                std::tie(f, t0, b0, b1, tbase) = pr;
+                if ((Lbuf_of(f) == BUF_F32) != (pass == 1)) continue;
+                const Front& Fr = sym.fronts[f];
+                const int64_t ldt = (int64_t)TS * (b1 - b0), m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
+                for (int i = b0; i < b1; i += 2)
+                    for (int k = t0; k < b0; k += 2) {
+                        GemmTask t{};
+                        t.c = tbase + TS * (i - b0) + TS * (k - t0) * ldt;
+                        t.ldc = (int32_t)ldt;
+                        t.flags = 1 | (1 << 4) | (BUF_W << 8) | (i + 1 < b1 ? GT_ROWS2 : 0) |
+                                  (k + 1 < b0 ? GT_COLS2 : 0);
+                        // sum_{j=k}^{b0-1} L(i, j) X(j, k)
+                        t.s[0] = mkseg(Lbuf_of(f), Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
+                                       xb + TS * k + TS * k * nvp, TS, (int)nvp, false, b0 - k);
+                        tasks.push_back(t);
+                    }
+            }
+            rr.n = (int64_t)tasks.size() - rr.off;
+            balance_range(tasks, rr);
         }
-        r1.n = (int64_t)tasks.size() - r1.off;
-        for (int64_t q = r1.off; q < r1.off + r1.n; q++) r1.a32 |= ((tasks[q].s[0].flags >> 8) & 3) == BUF_F32;
         r2.off = (int64_t)tasks.size();
         for (auto& pr : pairs) {
             int f, t0, b0, b1;
@@ -412,19 +468,22 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             std::tie(f, t0, b0, b1, tbase) = pr;
             const Front& Fr = sym.fronts[f];
             const int64_t ldt = (int64_t)TS * (b1 - b0), xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int i = b0; i < b1; i++)
-                for (int k = t0; k < b0; k++) {
+            for (int i = b0; i < b1; i += 2)
+                for (int k = t0; k < b0; k += 2) {
+                    const bool rows2 = i + 1 < b1;
                     GemmTask t{};
                     t.c = xb + TS * i + TS * k * nvp;
                     t.ldc = (int32_t)nvp;
-                    t.flags = 1 | (1 << 4) | (BUF_X << 8);
-                    // - sum_{j=b0}^{i} X(i, j) T(j, k)
+                    t.flags = 1 | (1 << 4) | (BUF_X << 8) | (rows2 ? GT_ROWS2 : 0) | (k + 1 < b0 ? GT_COLS2 : 0);
+                    // - sum_{j=b0}^{i or i+1} X(i, j) T(j, k)
                     t.s[0] = mkseg(BUF_X, xb + TS * i + TS * b0 * nvp, TS * nvp, (int)nvp, false, true, BUF_W,
-                                   tbase + TS * (k - t0) * ldt, TS, (int)ldt, false, i - b0 + 1);
+                                   tbase + TS * (k - t0) * ldt, TS, (int)ldt, false, (rows2 ? i + 1 : i) - b0 + 1);
                     tasks.push_back(t);
                 }
         }
         r2.n = (int64_t)tasks.size() - r2.off;
+        balance_range(tasks, r2);
+        ctx->trtri1f.push_back(r1f);
         ctx->trtri1.push_back(r1);
         ctx->trtri2.push_back(r2);
     }
@@ -518,6 +577,7 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     opt.leaf_size = c.leaf_size > 0 ? c.leaf_size : 512;
     opt.sep_halfwidth = ctx->pp.rho * (1.0 + 1e-9);
     opt.tile = TS;
+    opt.panel_tiles = PW;
     int rc = analyse(g, ctx->st, ctx->sup, opt, ctx->sym);
     if (rc != 0) {
         ctx->err = "symbolic analysis failed (" + std::to_string(rc) + ")";
@@ -607,6 +667,9 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     TRY(upload(ctx, &ctx->d_tasks, tasks));
     TRY(dev_alloc(ctx, &ctx->d_fronts, sym.total_elems));
     TRY(dev_alloc(ctx, &ctx->d_X, ctx->X_elems));
+    // X tiles above the diagonal are never written and must read as zero
+    // (the 128 x 128 tasks run a tile pair over its first tile's K range)
+    launch_fill(ctx->stream, ctx->d_X, ctx->X_elems, 0.0);
     TRY(dev_alloc(ctx, &ctx->d_W, ctx->W_elems));
     TRY(dev_alloc(ctx, &ctx->d_err, 1));
     if (c.precision == EP_PREC_MIXED) TRY(dev_alloc(ctx, &ctx->d_f32, sym.total_elems));
@@ -712,12 +775,14 @@ static void kt_begin(ep_ctx* ctx, int64_t ntasks) {
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
         ctx->kt_ev.push_back(a);
         ctx->kt_ev.push_back(b);
+        ctx->kt_kind.push_back(0);
     }
     (void)hipEventRecord(ctx->kt_ev[ctx->kt_used], ctx->stream);
 }
-static void kt_end(ep_ctx* ctx, int64_t ntasks) {
+static void kt_end(ep_ctx* ctx, int64_t ntasks, int kind) {
     if (!ctx->cfg.profile_kernels || ntasks <= 0 || ctx->kt_used + 2 > ctx->kt_ev.size()) return;
     (void)hipEventRecord(ctx->kt_ev[ctx->kt_used + 1], ctx->stream);
+    ctx->kt_kind[ctx->kt_used / 2] = kind;
     ctx->kt_used += 2;
 }
 
@@ -733,15 +798,15 @@ static void enqueue_factor(ep_ctx* ctx) {
                 const Launch& t = P.trsm[k];
                 kt_begin(ctx, t.ntasks);
                 launch_trsm32(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
-                kt_end(ctx, t.ntasks);
+                kt_end(ctx, t.ntasks, EP_KK_TRSM);
                 const Launch& s = P.inner[k];
                 kt_begin(ctx, s.ntasks);
                 launch_syrk_inner32(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
-                kt_end(ctx, s.ntasks);
+                kt_end(ctx, s.ntasks, EP_KK_INNER);
                 const Launch& r = P.trail[k];
                 kt_begin(ctx, r.ntasks);
                 launch_syrk_trail32(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
-                kt_end(ctx, r.ntasks);
+                kt_end(ctx, r.ntasks, EP_KK_TRAIL);
             }
             const Launch& e = P.extend;
             launch_extend_add32(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
@@ -752,26 +817,28 @@ static void enqueue_factor(ep_ctx* ctx) {
             const Launch& t = P.trsm[k];
             kt_begin(ctx, t.ntasks);
             launch_trsm_step(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
-            kt_end(ctx, t.ntasks);
+            kt_end(ctx, t.ntasks, EP_KK_TRSM);
             const Launch& s = P.inner[k];
             kt_begin(ctx, s.ntasks);
             launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
-            kt_end(ctx, s.ntasks);
+            kt_end(ctx, s.ntasks, EP_KK_INNER);
             const Launch& r = P.trail[k];
             kt_begin(ctx, r.ntasks);
             launch_syrk_trail(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
-            kt_end(ctx, r.ntasks);
+            kt_end(ctx, r.ntasks, EP_KK_TRAIL);
         }
         const Launch& e = P.extend;
         launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
     }
     for (size_t s = 0; s < ctx->trtri1.size(); s++) {
-        kt_begin(ctx, ctx->trtri1[s].n);
-        launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri1[s].off, ctx->trtri1[s].n, b, ctx->trtri1[s].a32);
-        kt_end(ctx, ctx->trtri1[s].n);
+        for (const TaskRange* r : {&ctx->trtri1[s], &ctx->trtri1f[s]}) {
+            kt_begin(ctx, r->n);
+            launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b, r->a32);
+            kt_end(ctx, r->n, EP_KK_GEMM);
+        }
         kt_begin(ctx, ctx->trtri2[s].n);
         launch_gemm_tasks(st, ctx->d_tasks + ctx->trtri2[s].off, ctx->trtri2[s].n, b, false);
-        kt_end(ctx, ctx->trtri2[s].n);
+        kt_end(ctx, ctx->trtri2[s].n, EP_KK_GEMM);
     }
 }
 
@@ -843,7 +910,7 @@ static void enqueue_selinv(ep_ctx* ctx) {
         for (const TaskRange* r : {&P.selW, &P.selS21, &P.selS11}) {
             kt_begin(ctx, r->n);
             launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b, r->a32);
-            kt_end(ctx, r->n);
+            kt_end(ctx, r->n, EP_KK_GEMM);
         }
     }
 }
@@ -970,10 +1037,19 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         stats->max_dmu = dmu;
         stats->mfma_ms = 0;
         stats->mfma_launches = (int64_t)(ctx->kt_used / 2);
+        for (int k = 0; k < EP_KK_COUNT; k++) {
+            stats->kernel_ms[k] = 0;
+            stats->kernel_launches[k] = 0;
+        }
         stats->refine_iters = ctx->ir_iters;
         stats->refine_residual = ctx->ir_res;
         stats->surrogate_fallbacks = ctx->fallbacks;
-        for (size_t i = 0; i + 1 < ctx->kt_used; i += 2) stats->mfma_ms += ev_ms(ctx->kt_ev[i], ctx->kt_ev[i + 1]);
+        for (size_t i = 0; i + 1 < ctx->kt_used; i += 2) {
+            const double ms = ev_ms(ctx->kt_ev[i], ctx->kt_ev[i + 1]);
+            stats->mfma_ms += ms;
+            stats->kernel_ms[ctx->kt_kind[i / 2]] += ms;
+            stats->kernel_launches[ctx->kt_kind[i / 2]]++;
+        }
     }
     return EP_OK;
 }
@@ -1158,6 +1234,7 @@ int ep_structure(const ep_ctx* ctx, ep_structure_stats* out) {
     out->max_front = ctx->sym.max_m;
     out->factor_flops = ctx->sym.factor_flops;
     out->selinv_flops = ctx->sym.selinv_flops;
+    out->trail_flops = ctx->sym.trail_flops;
     out->device_bytes = ctx->dev_bytes;
     return EP_OK;
 }

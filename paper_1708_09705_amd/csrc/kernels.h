@@ -18,13 +18,22 @@ struct GemmSeg {
     int32_t lda, ldb, nk;
     int32_t flags;   // 1 transA, 2 transB, 4 negate; bits 8-9 buffer of A, 10-11 buffer of B
 };
-// C (64x64, column-major, ldc) = [C +] sum over segments.
+// C (128x128, column-major, ldc) = [C +] sum over segments: four 64x64
+// quadrants, the second row half and the second column half optional (their
+// operand rows / columns are neither read nor written when absent), and the
+// upper-right quadrant optionally not stored (diagonal blocks of a lower
+// triangle).  A segment's nk counts 64-deep K tiles; sa, sb step one of them.
+// A task without segments is padding and does nothing.
 struct GemmTask {
     int64_t c;
     int32_t ldc;
-    int32_t flags;   // 1 overwrite (else accumulate), 2 atomic add; bits 4-5 nseg; bits 8-9 buffer of C
+    int32_t flags;   // 1 overwrite (else accumulate), 2 atomic add; bits 4-5 nseg; bits 8-9 buffer of C;
+                     // GT_ROWS2, GT_COLS2, GT_NOUPPER
     GemmSeg s[2];
 };
+constexpr int32_t GT_ROWS2 = 1 << 12;    // rows 64..127 present
+constexpr int32_t GT_COLS2 = 1 << 13;    // columns 64..127 present
+constexpr int32_t GT_NOUPPER = 1 << 14;  // do not store rows 0..63 x columns 64..127
 
 // Front metadata (structure of arrays, device pointers).
 struct FrontsDev {

@@ -160,21 +160,6 @@ __device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
         for (int b = 0; b < 2; b++) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
-// A32: the task list may hold A operands in the FP32 copy of the factor
-// (mixed precision), upcast on load.  A separate instance keeps the all-FP64
-// kernel within the register budget of two waves per SIMD.
-template <bool A32>
-__device__ __forceinline__ void seg_apply(d4 acc[2][2], double* sA, double* sB, const Bufs& bufs, const GemmSeg& S) {
-    const int ba = (S.flags >> 8) & 3;
-    const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
-    const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
-    const double sgn = (S.flags & 4) ? -1.0 : 1.0;
-    if (A32 && ba == BUF_F32)
-        seg_run(acc, sA, sB, bufs.F32 + S.a, S.sa, S.lda, ta, sgn, B, S.sb, S.ldb, tb, S.nk);
-    else
-        seg_run(acc, sA, sB, buf_of(bufs, ba) + S.a, S.sa, S.lda, ta, sgn, B, S.sb, S.ldb, tb, S.nk);
-}
-
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // range of tasks instead, so neighbouring tasks (which share operand tiles)
 // meet in the same L2.
@@ -188,29 +173,184 @@ __device__ __forceinline__ int64_t xcd_task(int64_t n) {
     return t;
 }
 
+// ---------------------------------------------------------------------------
+// Task-list GEMM on 128 x 128 output blocks (diagonal-block inverses and the
+// selected inversion).  One block of eight waves per CU, two per SIMD, so one
+// wave's MFMAs cover the other's LDS traffic and barriers.  Wave w computes
+// rows 64 ((w >> 1) & 1) .. +64 and columns 64 (w & 1) + 32 (w >> 2) .. +32
+// (4 x 2 MFMA 16x16x4 blocks, accumulators in AGPRs); waves w and w + 4 share
+// a 64 x 64 quadrant.  K advances in slabs of 32 through two LDS buffers:
+// while the MFMAs consume one slab the next is stored to the other buffer and
+// the global loads of the slab after that are in flight; one barrier per slab.
+// ---------------------------------------------------------------------------
+constexpr int BT = 128;         // output block edge
+constexpr int KH = 32;          // K slab depth
+constexpr int LDS2 = BT + 1;    // LDS row stride (doubles): odd, so the
+                                // k-contiguous stores hit distinct banks
+constexpr int SLAB = KH * LDS2; // one operand slab in LDS (doubles)
+constexpr int GT_THREADS = 512;
+
+// One 128 x 32 operand slab op(M)(i, k), i in [0, 128), k in [0, 32), eight
+// elements per thread.  kc: k is the contiguous index in memory (element at
+// M[k + i ld]), otherwise i is (M[i + k ld]).  Rows i >= 64 are loaded only
+// when half2.
+template <typename T>
+__device__ __forceinline__ void slab_load(double r[8], const T* M, int ld, bool kc, bool half2) {
+    const int t = threadIdx.x;
+    if (!kc) {
+        const int i = t & 127, k0 = t >> 7;
+        if (i < 64 || half2) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) r[q] = (double)M[i + (int64_t)(k0 + 4 * q) * ld];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++) r[q] = 0.0;
+        }
+    } else {
+        const int k = t & 31, i0 = t >> 5;
+#pragma unroll
+        for (int q = 0; q < 4; q++) r[q] = (double)M[k + (int64_t)(i0 + 16 * q) * ld];
+        if (half2) {
+#pragma unroll
+            for (int q = 4; q < 8; q++) r[q] = (double)M[k + (int64_t)(i0 + 16 * q) * ld];
+        } else {
+#pragma unroll
+            for (int q = 4; q < 8; q++) r[q] = 0.0;
+        }
+    }
+}
+
+// Write a slab to LDS as s[k][i] (row stride LDS2), scaled by sgn.
+__device__ __forceinline__ void slab_store(const double r[8], double* s, bool kc, double sgn) {
+    const int t = threadIdx.x;
+    if (!kc) {
+        const int i = t & 127, k0 = t >> 7;
+#pragma unroll
+        for (int q = 0; q < 8; q++) s[(k0 + 4 * q) * LDS2 + i] = sgn * r[q];
+    } else {
+        const int k = t & 31, i0 = t >> 5;
+#pragma unroll
+        for (int q = 0; q < 8; q++) s[k * LDS2 + i0 + 16 * q] = sgn * r[q];
+    }
+}
+
+// acc (this wave's 64 x 32 piece) += sum over the slab's k of sA[k][i] sB[k][j]
+__device__ __forceinline__ void slab_mma(d4 acc[4][2], const double* sA, const double* sB) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = ((w >> 1) & 1) * 64, wc = (w & 1) * 64 + (w >> 2) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < KH; kk += 4) {
+        const double* ra = sA + (kk + lk) * LDS2 + wr + li;
+        const double* rb = sB + (kk + lk) * LDS2 + wc + li;
+        double a[4], b[2];
+#pragma unroll
+        for (int q = 0; q < 4; q++) a[q] = ra[16 * q];
+#pragma unroll
+        for (int q = 0; q < 2; q++) b[q] = rb[16 * q];
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+}
+
+// One segment: acc += sum over its K of op(A) op(B).  smem holds two
+// buffers of (A slab, B slab).  Ends with a barrier after the last read of
+// smem.
+template <typename TA>
+__device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA* A, const double* B,
+                                           const GemmSeg& S, bool rows2, bool cols2, bool active) {
+    const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
+    const double sgn = (S.flags & 4) ? -1.0 : 1.0;
+    // op(A)(i, k): transposed A has k contiguous; op(B)(k, j): plain B has k contiguous
+    const bool kca = ta, kcb = !tb;
+    const int nh = (TS / KH) * S.nk;
+    const int64_t ha = S.sa / (TS / KH), hb = S.sb / (TS / KH);
+    if (nh <= 0) return;
+    double ra[8], rb[8];
+    slab_load(ra, A, S.lda, kca, rows2);
+    slab_load(rb, B, S.ldb, kcb, cols2);
+    slab_store(ra, smem, kca, sgn);
+    slab_store(rb, smem + SLAB, kcb, 1.0);
+    if (nh > 1) {
+        slab_load(ra, A + ha, S.lda, kca, rows2);
+        slab_load(rb, B + hb, S.ldb, kcb, cols2);
+    }
+    __syncthreads();
+    for (int h = 0; h < nh; h++) {
+        const double* cur = smem + (h & 1) * 2 * SLAB;
+        if (active) slab_mma(acc, cur, cur + SLAB);
+        if (h + 1 < nh) {
+            double* nxt = smem + ((h + 1) & 1) * 2 * SLAB;
+            slab_store(ra, nxt, kca, sgn);
+            slab_store(rb, nxt + SLAB, kcb, 1.0);
+            if (h + 2 < nh) {
+                slab_load(ra, A + (h + 2) * ha, S.lda, kca, rows2);
+                slab_load(rb, B + (h + 2) * hb, S.ldb, kcb, cols2);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// A32: the launch's tasks have one segment whose A operand is in the FP32
+// copy of the factor (mixed precision), upcast on load; B is FP64.
 template <bool A32>
-__global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
-    __shared__ double sA[TS * LDP];
-    __shared__ double sB[TS * LDP];
+__global__ __launch_bounds__(GT_THREADS) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
+    __shared__ double smem[4 * SLAB];
     const int64_t t = xcd_task(n);
     if (t >= n) return;
     const GemmTask& T = tasks[t];
-    d4 acc[2][2];
-    acc_zero(acc);
-    const int nseg = (T.flags >> 4) & 3;
-    if (nseg > 0) seg_apply<A32>(acc, sA, sB, bufs, T.s[0]);
-    if (nseg > 1) seg_apply<A32>(acc, sA, sB, bufs, T.s[1]);
+    if (((T.flags >> 4) & 3) == 0) return;   // padding entry
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qr = (w >> 1) & 1, qc = w & 1;
+    const bool rows2 = T.flags & GT_ROWS2, cols2 = (T.flags & GT_COLS2) != 0;
+    // this wave's quadrant is (qr, qc)
+    const bool mine = (qr == 0 || rows2) && (qc == 0 || cols2) && !(qr == 0 && qc == 1 && (T.flags & GT_NOUPPER));
+    d4 acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    if (A32) {
+        const GemmSeg& S = T.s[0];
+        seg128_run(acc, smem, bufs.F32 + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S, rows2, cols2, mine);
+    } else {
+        const int nseg = (T.flags >> 4) & 3;
+        for (int q = 0; q < nseg; q++) {
+            const GemmSeg& S = T.s[q];
+            seg128_run(acc, smem, buf_of(bufs, (S.flags >> 8) & 3) + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S,
+                       rows2, cols2, mine);
+        }
+    }
+    if (!mine) return;
     double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c;
-    int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
-    tile_store(acc, sA, C, T.ldc, mode);
+    const int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
+    const int wr = qr * 64, wc = qc * 64 + (w >> 2) * 32;
+    // v_mfma_f64_16x16x4f64 output: lane l, item r -> row l/16 + 4r, column l%16
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = wr + 16 * x + (lane >> 4) + 4 * r;
+                const int col = wc + 16 * y + (lane & 15);
+                double* p = C + row + (int64_t)col * T.ldc;
+                if (mode == 1) *p = acc[x][y][r];
+                else if (mode == 0) *p += acc[x][y][r];
+                else atomicAdd(p, acc[x][y][r]);
+            }
 }
 
 void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, bool a32) {
     if (n <= 0) return;
     if (a32)
-        hipLaunchKernelGGL(k_gemm_tasks<true>, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
+        hipLaunchKernelGGL(k_gemm_tasks<true>, dim3((unsigned)n), dim3(GT_THREADS), 0, st, t, n, b);
     else
-        hipLaunchKernelGGL(k_gemm_tasks<false>, dim3((unsigned)n), dim3(256), 0, st, t, n, b);
+        hipLaunchKernelGGL(k_gemm_tasks<false>, dim3((unsigned)n), dim3(GT_THREADS), 0, st, t, n, b);
 }
 
 // ---------------------------------------------------------------------------

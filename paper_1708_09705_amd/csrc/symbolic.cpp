@@ -360,7 +360,8 @@ int analyse(const GridGeom& g, const Stencil& st, const Supports& sup, const Ord
     // ---- layout ----
     int64_t off = 0, rp = 0;
     sym.total_elems = 0;
-    sym.factor_flops = sym.selinv_flops = 0;
+    sym.factor_flops = sym.selinv_flops = sym.trail_flops = 0;
+    const int64_t panel_cols = (int64_t)opt.tile * opt.panel_tiles;
     sym.max_m = 0;
     for (int64_t f = 0; f < nf; f++) {
         Front& F = sym.fronts[f];
@@ -372,6 +373,13 @@ int analyse(const GridGeom& g, const Stencil& st, const Supports& sup, const Ord
         double nv = F.nv, mm = F.nv + F.nr, nr = F.nr;
         sym.factor_flops += (mm * mm * mm - (mm - nv) * (mm - nv) * (mm - nv)) / 3.0;
         sym.selinv_flops += 2.0 * nv * nv * nv / 3.0 + 2.0 * nr * nv * nv + 2.0 * nr * nr * nv;
+        // trailing update after each panel of panel_cols pivot columns: the
+        // lower triangle of the remaining R x R block, rank w
+        for (int64_t c0 = 0; c0 < F.nv; c0 += panel_cols) {
+            const double w = (double)(std::min<int64_t>(F.nv, c0 + panel_cols) - c0);
+            const double R = mm - (double)std::min<int64_t>(F.nv, c0 + panel_cols);
+            sym.trail_flops += w * R * (R + 1.0);
+        }
         sym.max_m = std::max<int64_t>(sym.max_m, F.m);
     }
     sym.total_elems = off;

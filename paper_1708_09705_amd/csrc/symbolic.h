@@ -64,6 +64,7 @@ struct Symbolic {
     int64_t total_elems = 0;        // sum m^2
     double factor_flops = 0;        // dense-front partial Cholesky flops
     double selinv_flops = 0;
+    double trail_flops = 0;         // trailing updates after each pivot panel
     int64_t max_m = 0;
 };
 
@@ -71,6 +72,7 @@ struct OrderingOpts {
     int leaf_size = 512;
     double sep_halfwidth = 0;   // half-width of a separator slab (pc)
     int tile = 64;
+    int panel_tiles = 8;        // pivot tiles per factor panel (flop accounting)
 };
 
 // Nested dissection + symbolic multifrontal analysis.  Returns 0 or a

@@ -64,14 +64,16 @@ class ep_sweep_stats(ctypes.Structure):
                [(k, ctypes.c_int64) for k in ("updated", "skipped_cavity", "skipped_negsite")] + \
                [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu", "mfma_ms")] + \
                [("mfma_launches", ctypes.c_int64), ("refine_iters", ctypes.c_int32),
-                ("refine_residual", ctypes.c_double), ("surrogate_fallbacks", ctypes.c_int64)]
+                ("refine_residual", ctypes.c_double), ("surrogate_fallbacks", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4)]
 
 
 class ep_structure_stats(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_stars", ctypes.c_int64), ("nnz_g", ctypes.c_int64),
                 ("n_fronts", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("front_elems", ctypes.c_int64),
                 ("max_front", ctypes.c_int64), ("factor_flops", ctypes.c_double),
-                ("selinv_flops", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("selinv_flops", ctypes.c_double), ("trail_flops", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
 
 
 EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_free",
@@ -79,6 +81,7 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load")
 MLP_NPARAM = 34065
+KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
 
 class ep_mlp_hyper(ctypes.Structure):
@@ -191,7 +194,10 @@ def ep_sweep(ctx, lib=None) -> dict:
     L = lib or load()
     st = ep_sweep_stats()
     _check(L, L.ep_sweep(ctx, ctypes.byref(st)), ctx)
-    return {k: getattr(st, k) for k, _ in ep_sweep_stats._fields_}
+    out = {k: getattr(st, k) for k, _ in ep_sweep_stats._fields_}
+    for k in ("kernel_ms", "kernel_launches"):
+        out[k] = dict(zip(KERNEL_KINDS, list(out[k])))
+    return out
 
 
 def ep_posterior_mean(ctx, N: int, lib=None) -> np.ndarray:

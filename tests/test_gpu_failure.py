@@ -56,8 +56,12 @@ def test_checkpoint_resume_reproduces_the_next_sweep():
     b.sweep()
     ta, na = a.sites()
     tb, nb = b.sites()
-    assert relerr(tb, ta) < 1e-12 and np.allclose(nb, na, rtol=1e-12, atol=1e-12)
-    assert relerr(b.posterior_mean(), a.posterior_mean()) < 1e-12
+    # The restored state is exact, but the assembly and extend-add sum with
+    # atomics in no fixed order: Q differs between the two contexts by a few
+    # ulps per entry, which its conditioning (~1e3 here) amplifies in the
+    # solves.  1e-10 is that rounding level with a margin of ten.
+    assert relerr(tb, ta) < 1e-10 and np.allclose(nb, na, rtol=1e-10, atol=1e-10)
+    assert relerr(b.posterior_mean(), a.posterior_mean()) < 1e-10
 
 
 def test_tiny_noise_gives_finite_degenerate_moments():
