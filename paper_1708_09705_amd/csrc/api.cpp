@@ -46,7 +46,8 @@ struct TaskRange {
 };
 struct LevelPlan {
     std::vector<FList> potrf;   // per pivot step
-    std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k
+    std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k (FP32 levels)
+    std::vector<TaskRange> trailT;            // the same updates as 128 x 128 GEMM tasks (FP64 levels)
     Launch extend;              // also the Sigma-gather enumeration
     Launch conv;                // FP64 -> FP32 copy of the level's fronts (mixed precision)
     Launch fwd_xv, fwd_r, bwd_t, bwd_x;
@@ -300,6 +301,34 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             P.trsm.push_back(mk_launch(tr));
             P.inner.push_back(mk_launch(in));
             P.trail.push_back(mk_launch(tl));
+            // trailing update as tile-pair tasks: C(i, j) -= sum over the
+            // panel of L(i, kk) L(j, kk)^T for gend <= j <= i < M
+            TaskRange tt;
+            tt.off = (int64_t)tasks.size();
+            if (!is_f32_level(ctx, l))
+                for (int f : lv[l]) {
+                    const int Pf = P_of(f), M = M_of(f);
+                    if (Pf <= k) continue;
+                    const int gend = std::min(PW * (g + 1), Pf);
+                    if (gend - 1 != k) continue;
+                    const int k0 = PW * g;
+                    const Front& Fr = sym.fronts[f];
+                    const int64_t m = Fr.m;
+                    for (int i = gend; i < M; i += 2)
+                        for (int j = gend; j <= i; j += 2) {
+                            GemmTask t{};
+                            t.c = Fr.off + TS * i + TS * j * m;
+                            t.ldc = (int32_t)m;
+                            t.flags = (1 << 4) | (BUF_FRONTS << 8) | (i + 1 < M ? GT_ROWS2 : 0) |
+                                      (j + 1 < M ? GT_COLS2 : 0) | (i == j ? GT_NOUPPER : 0);
+                            t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * k0 * m, TS * m, (int)m, false, true,
+                                           BUF_FRONTS, Fr.off + TS * j + TS * k0 * m, TS * m, (int)m, true, gend - k0);
+                            tasks.push_back(t);
+                        }
+                }
+            tt.n = (int64_t)tasks.size() - tt.off;
+            balance_range(tasks, tt);
+            P.trailT.push_back(tt);
         }
         std::vector<std::pair<int, int64_t>> ea, fx, fr;
         for (int f : lv[l]) {
@@ -822,10 +851,10 @@ static void enqueue_factor(ep_ctx* ctx) {
             kt_begin(ctx, s.ntasks);
             launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
             kt_end(ctx, s.ntasks, EP_KK_INNER);
-            const Launch& r = P.trail[k];
-            kt_begin(ctx, r.ntasks);
-            launch_syrk_trail(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
-            kt_end(ctx, r.ntasks, EP_KK_TRAIL);
+            const TaskRange& r = P.trailT[k];
+            kt_begin(ctx, r.n);
+            launch_gemm_tasks(st, ctx->d_tasks + r.off, r.n, b, false);
+            kt_end(ctx, r.n, EP_KK_TRAIL);
         }
         const Launch& e = P.extend;
         launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);

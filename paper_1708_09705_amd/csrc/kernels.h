@@ -73,7 +73,6 @@ void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, boo
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
-void launch_syrk_trail(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b);
 void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 

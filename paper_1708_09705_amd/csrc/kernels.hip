@@ -234,31 +234,40 @@ __device__ __forceinline__ void slab_store(const double r[8], double* s, bool kc
     }
 }
 
-// acc (this wave's 64 x 32 piece) += sum over the slab's k of sA[k][i] sB[k][j]
+// acc (this wave's 64 x 32 piece) += sum over the slab's k of sA[k][i] sB[k][j].
+// The LDS reads of step kk + 4 are issued before the MFMAs of step kk.
 __device__ __forceinline__ void slab_mma(d4 acc[4][2], const double* sA, const double* sB) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = ((w >> 1) & 1) * 64, wc = (w & 1) * 64 + (w >> 2) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    const double* ra = sA + lk * LDS2 + wr + li;
+    const double* rb = sB + lk * LDS2 + wc + li;
+    double a[2][4], b[2][2];
 #pragma unroll
-    for (int kk = 0; kk < KH; kk += 4) {
-        const double* ra = sA + (kk + lk) * LDS2 + wr + li;
-        const double* rb = sB + (kk + lk) * LDS2 + wc + li;
-        double a[4], b[2];
+    for (int q = 0; q < 4; q++) a[0][q] = ra[16 * q];
 #pragma unroll
-        for (int q = 0; q < 4; q++) a[q] = ra[16 * q];
+    for (int q = 0; q < 2; q++) b[0][q] = rb[16 * q];
 #pragma unroll
-        for (int q = 0; q < 2; q++) b[q] = rb[16 * q];
+    for (int s = 0; s < KH / 4; s++) {
+        const int c = s & 1, n = c ^ 1;
+        if (s + 1 < KH / 4) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) a[n][q] = ra[(s + 1) * 4 * LDS2 + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 2; q++) b[n][q] = rb[(s + 1) * 4 * LDS2 + 16 * q];
+        }
 #pragma unroll
         for (int x = 0; x < 4; x++)
 #pragma unroll
             for (int y = 0; y < 2; y++)
-                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][x], b[c][y], acc[x][y], 0, 0, 0);
     }
 }
 
 // One segment: acc += sum over its K of op(A) op(B).  smem holds two
-// buffers of (A slab, B slab).  Ends with a barrier after the last read of
-// smem.
+// buffers of (A slab, B slab) and two register stages hold the next two
+// slabs, so a slab's global loads have two MFMA phases to arrive.  Ends with
+// a barrier after the last read of smem.
 template <typename TA>
 __device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA* A, const double* B,
                                            const GemmSeg& S, bool rows2, bool cols2, bool active) {
@@ -269,26 +278,43 @@ __device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA*
     const int nh = (TS / KH) * S.nk;
     const int64_t ha = S.sa / (TS / KH), hb = S.sb / (TS / KH);
     if (nh <= 0) return;
-    double ra[8], rb[8];
-    slab_load(ra, A, S.lda, kca, rows2);
-    slab_load(rb, B, S.ldb, kcb, cols2);
-    slab_store(ra, smem, kca, sgn);
-    slab_store(rb, smem + SLAB, kcb, 1.0);
+    double* B0 = smem;
+    double* B1 = smem + 2 * SLAB;
+    double a0[8], b0[8], a1[8], b1[8];
+    slab_load(a0, A, S.lda, kca, rows2);
+    slab_load(b0, B, S.ldb, kcb, cols2);
     if (nh > 1) {
-        slab_load(ra, A + ha, S.lda, kca, rows2);
-        slab_load(rb, B + hb, S.ldb, kcb, cols2);
+        slab_load(a1, A + ha, S.lda, kca, rows2);
+        slab_load(b1, B + hb, S.ldb, kcb, cols2);
+    }
+    slab_store(a0, B0, kca, sgn);
+    slab_store(b0, B0 + SLAB, kcb, 1.0);
+    if (nh > 2) {
+        slab_load(a0, A + 2 * ha, S.lda, kca, rows2);
+        slab_load(b0, B + 2 * hb, S.ldb, kcb, cols2);
     }
     __syncthreads();
-    for (int h = 0; h < nh; h++) {
-        const double* cur = smem + (h & 1) * 2 * SLAB;
-        if (active) slab_mma(acc, cur, cur + SLAB);
+    for (int h = 0; h < nh; h += 2) {
+        // slab h in B0; slab h + 1 in stage 1, slab h + 2 in stage 0
+        if (active) slab_mma(acc, B0, B0 + SLAB);
         if (h + 1 < nh) {
-            double* nxt = smem + ((h + 1) & 1) * 2 * SLAB;
-            slab_store(ra, nxt, kca, sgn);
-            slab_store(rb, nxt + SLAB, kcb, 1.0);
-            if (h + 2 < nh) {
-                slab_load(ra, A + (h + 2) * ha, S.lda, kca, rows2);
-                slab_load(rb, B + (h + 2) * hb, S.ldb, kcb, cols2);
+            slab_store(a1, B1, kca, sgn);
+            slab_store(b1, B1 + SLAB, kcb, 1.0);
+            if (h + 3 < nh) {
+                slab_load(a1, A + (h + 3) * ha, S.lda, kca, rows2);
+                slab_load(b1, B + (h + 3) * hb, S.ldb, kcb, cols2);
+            }
+        }
+        __syncthreads();
+        if (h + 1 >= nh) break;
+        // slab h + 1 in B1; slab h + 2 in stage 0, slab h + 3 in stage 1
+        if (active) slab_mma(acc, B1, B1 + SLAB);
+        if (h + 2 < nh) {
+            slab_store(a0, B0, kca, sgn);
+            slab_store(b0, B0 + SLAB, kcb, 1.0);
+            if (h + 4 < nh) {
+                slab_load(a0, A + (h + 4) * ha, S.lda, kca, rows2);
+                slab_load(b0, B + (h + 4) * hb, S.ldb, kcb, cols2);
             }
         }
         __syncthreads();
@@ -466,31 +492,6 @@ __global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__
     tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
 }
 
-// trailing update after panel g: columns j >= gend, rows i >= j,
-//   C_ij -= sum_{kk = k0}^{gend-1} L_{i,kk} L_{j,kk}^T
-__global__ __launch_bounds__(256) void k_syrk_trail(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int g,
-                                                    FrontsDev F, Bufs bufs) {
-    __shared__ double sA[TS * LDP];
-    __shared__ double sB[TS * LDP];
-    const int64_t t = xcd_task(ntasks);
-    if (t >= ntasks) return;
-    const int e = (int)batch_find(be, nbe, t);
-    const int f = be[e].front;
-    const int m = F.m[f];
-    const int P = F.nvpad[f] / TS;
-    const int k0 = PW * g;
-    const int gend = min(k0 + PW, P);
-    int ii, jj;
-    tri_decode(t - be[e].base, ii, jj);
-    const int i = gend + ii, j = gend + jj;
-    double* base = bufs.fronts + F.off[f];
-    d4 acc[2][2];
-    acc_zero(acc);
-    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0,
-            base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, gend - k0);
-    tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
-}
-
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_trsm_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
@@ -498,10 +499,6 @@ void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntask
 void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_syrk_inner, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b);
-}
-void launch_syrk_trail(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b) {
-    if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_syrk_trail, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, g, F, b);
 }
 
 // ---------------------------------------------------------------------------
