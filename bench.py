@@ -27,10 +27,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per step of the dominant kernel from the rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters, scaled by the copy-kernel calibration (None until
-# counters are taken for the current kernel).
-TRAFFIC_GEMM_TASKS = None
+# HBM bytes per launch of the dominant kernel (k_gemm_tasks<false>, every
+# launch of one FP64 sweep of the 64^3 / 100,000-star workload): rocprofv3
+# FETCH_SIZE and WRITE_SIZE summed over the sweep's 183 launches, each scaled
+# by what the same counter reads for a 1 GiB device copy (FETCH_SIZE x 2.000,
+# WRITE_SIZE x 1.000), divided by 183.  Taken for the kernel as it is; set to
+# None whenever the kernel changes until the counters are taken again.
+TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 2.6099e12 / 183, "write_bytes_per_launch": 2.4255e11 / 183,
+                      "bytes_per_launch": (2.6099e12 + 2.4255e11) / 183, "launches_per_sweep": 183,
+                      "source": "profiles/k_gemm_tasks_64cube_100k_traffic.md"}
 
 
 def log(*a):
@@ -158,16 +163,18 @@ def main():
     value = S * args.steps / wall
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
           ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")}
-    # Dominant kernel: k_gemm_tasks, the FP64 MFMA task-list GEMM that forms
-    # the diagonal-block inverses and the selected-inversion products of
-    # every front.  Each launch is timed with HIP events on the library's
-    # stream; the work counted is the algorithmic (unpadded) flop count of
-    # the selected inversion, inverses included.
-    gemm_ms = float(np.mean([s["kernel_ms"]["gemm"] for s in stats]))
-    launches = int(stats[0]["kernel_launches"]["gemm"])
-    flops = st["selinv_flops"]
+    # Dominant kernel: k_gemm_tasks<false>, the FP64 MFMA task-list GEMM on
+    # 128 x 128 blocks.  In an FP64 sweep every one of its launches is either
+    # a trailing update of the factorization (EP_KK_TRAIL) or a
+    # diagonal-block inverse / selected-inversion product (EP_KK_GEMM).  Each
+    # launch is timed with HIP events on the library's stream; the work
+    # counted is the algorithmic (unpadded) flop count of those two parts.
+    gemm_ms = float(np.mean([s["kernel_ms"]["gemm"] + s["kernel_ms"]["trail"] for s in stats]))
+    launches = int(stats[0]["kernel_launches"]["gemm"] + stats[0]["kernel_launches"]["trail"])
+    flops = st["selinv_flops"] + st["trail_flops"]
     achieved = flops / (gemm_ms * 1e-3) / 1e12
     trail_ms = float(np.mean([s["kernel_ms"]["trail"] for s in stats]))
+    sel_ms = float(np.mean([s["kernel_ms"]["gemm"] for s in stats]))
     mfma_ms = float(np.mean([s["mfma_ms"] for s in stats]))
     all_flops = st["factor_flops"] + st["selinv_flops"]
     line = {
@@ -190,14 +197,20 @@ def main():
         "structure": {k: st[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front", "factor_flops",
                                          "selinv_flops", "trail_flops", "device_bytes")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": TRAFFIC_GEMM_TASKS,
-                     "kernel": "k_gemm_tasks<false> (FP64 MFMA: diagonal-block inverses + selected inversion)",
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": TRAFFIC_GEMM_TASKS["bytes_per_launch"] if TRAFFIC_GEMM_TASKS else None,
+                     "traffic_unit": "HBM bytes per launch", "traffic_detail": TRAFFIC_GEMM_TASKS,
+                     "kernel": "k_gemm_tasks<false> (FP64 MFMA, 128x128 blocks: trailing updates, "
+                               "diagonal-block inverses, selected inversion)",
                      "launches_per_step": launches, "kernel_ms_per_step": gemm_ms,
                      "avg_launch_ms": gemm_ms / max(launches, 1),
                      "algorithmic_flop_per_step": flops,
                      "others": {
-                         "k_syrk_trail": {"ms_per_step": trail_ms, "algorithmic_flop_per_step": st["trail_flops"],
-                                          "tflops": st["trail_flops"] / (trail_ms * 1e-3) / 1e12},
+                         "trailing_updates": {"ms_per_step": trail_ms, "algorithmic_flop_per_step": st["trail_flops"],
+                                              "tflops": st["trail_flops"] / (trail_ms * 1e-3) / 1e12},
+                         "selected_inversion_and_inverses": {
+                             "ms_per_step": sel_ms, "algorithmic_flop_per_step": st["selinv_flops"],
+                             "tflops": st["selinv_flops"] / (sel_ms * 1e-3) / 1e12},
                          "all_mfma_tile_kernels": {"ms_per_step": mfma_ms, "algorithmic_flop_per_step": all_flops,
                                                    "tflops": all_flops / (mfma_ms * 1e-3) / 1e12}}},
     }

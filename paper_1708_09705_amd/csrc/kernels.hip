@@ -383,68 +383,71 @@ void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, boo
 // Diagonal tile: Cholesky of tile (k,k) of each listed front, and the
 // inverse of the factor (kept in X as the diagonal tile of L11^{-1}).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
-                                               int* err) {
-    __shared__ double L[TS * LDP];   // L[i * LDP + j], row-major
-    __shared__ double Xs[TS * LDP];
-    __shared__ int bad;
+// One wave per tile, lane i holding row i of the tile in registers.  The
+// right-looking column steps broadcast the pivot and the column entries with
+// readlane (the loops are fully unrolled, so every register index is static);
+// the inverse is forward substitution with lane j holding column j of X and
+// the rows of L read from LDS at wave-uniform addresses.
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
+                                              int* err) {
+    __shared__ double T[TS * LDP];
     const int f = flist[blockIdx.x];
     const int m = F.m[f];
     double* A = bufs.fronts + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
-    const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
-    {
-        const int i = tid & 63;
-        for (int r = 0; r < 16; r++) {
-            int j = (tid >> 6) + 4 * r;
-            L[i * LDP + j] = A[i + (int64_t)j * m];
+    const int i = threadIdx.x;
+    double a[TS];
+#pragma unroll
+    for (int c = 0; c < TS; c++) a[c] = A[i + (int64_t)c * m];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < TS; j++) {
+        double d = lane_bcast(a[j], j);
+        if (!(d > 0.0) || !isfinite(d)) {
+            bad = true;
+            d = 1.0;
         }
+        const double l = sqrt(d);
+        a[j] = (i == j) ? l : a[j] / l;   // rows above j hold unused values
+#pragma unroll
+        for (int c = j + 1; c < TS; c++) a[c] -= a[j] * lane_bcast(a[j], c);
+    }
+    // L (zeros above the diagonal) to the front and to LDS
+#pragma unroll
+    for (int c = 0; c < TS; c++) {
+        const double v = (i >= c) ? a[c] : 0.0;
+        A[i + (int64_t)c * m] = v;
+        T[i * LDP + c] = v;
     }
     __syncthreads();
-    for (int j = 0; j < TS; j++) {
-        if (tid == 0) {
-            double d = L[j * LDP + j];
-            if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
-            L[j * LDP + j] = sqrt(d);
-        }
-        __syncthreads();
-        const double dj = L[j * LDP + j];
-        if (tid > j && tid < TS) L[tid * LDP + j] /= dj;
-        __syncthreads();
-        for (int idx = tid; idx < TS * TS; idx += 256) {
-            int i = idx >> 6, c = idx & 63;
-            if (c > j && i >= c) L[i * LDP + c] -= L[i * LDP + j] * L[c * LDP + j];
-        }
-        __syncthreads();
+    // X = L^{-1}: lane j solves L x = e_j
+    double x[TS];
+#pragma unroll
+    for (int r = 0; r < TS; r++) {
+        double s = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < r; q++) s -= T[r * LDP + q] * x[q];
+        x[r] = s / T[r * LDP + r];
     }
-    // inverse of the lower triangular factor, one column per thread
-    if (tid < TS) {
-        const int j = tid;
-        for (int i = 0; i < j; i++) Xs[i * LDP + j] = 0.0;
-        Xs[j * LDP + j] = 1.0 / L[j * LDP + j];
-        for (int i = j + 1; i < TS; i++) {
-            double s = 0.0;
-            for (int q = j; q < i; q++) s += L[i * LDP + q] * Xs[q * LDP + j];
-            Xs[i * LDP + j] = -s / L[i * LDP + i];
-        }
-    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TS; r++) T[r * LDP + i] = x[r];
     __syncthreads();
     double* Xk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
     const int ldx = F.nvpad[f];
-    {
-        const int i = tid & 63;
-        for (int r = 0; r < 16; r++) {
-            int j = (tid >> 6) + 4 * r;
-            A[i + (int64_t)j * m] = (i >= j) ? L[i * LDP + j] : 0.0;
-            Xk[i + (int64_t)j * ldx] = Xs[i * LDP + j];
-        }
-    }
-    if (tid == 0 && bad) atomicCAS(err, 0, f + 1);
+#pragma unroll
+    for (int c = 0; c < TS; c++) Xk[i + (int64_t)c * ldx] = T[i * LDP + c];
+    if (i == 0 && bad) atomicCAS(err, 0, f + 1);
 }
 
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_potrf, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
+    hipLaunchKernelGGL(k_potrf, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
 }
 
 // ---------------------------------------------------------------------------
