@@ -47,7 +47,12 @@ struct TaskRange {
 struct LevelPlan {
     std::vector<FList> potrf;   // per pivot step
     std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k (FP32 levels)
-    std::vector<TaskRange> trailT;            // the same updates as 128 x 128 GEMM tasks (FP64 levels)
+    // FP64 levels, left-looking by panel, as 128 x 128 GEMM tasks:
+    // panelT[k]: before step k (a panel start), the panel's columns take the
+    //            updates of every earlier panel;
+    // finalT[k]: after step k (a front's last pivot step), the update block
+    //            takes the updates of all pivot columns.
+    std::vector<TaskRange> panelT, finalT;
     Launch extend;              // also the Sigma-gather enumeration
     Launch conv;                // FP64 -> FP32 copy of the level's fronts (mixed precision)
     Launch fwd_xv, fwd_r, bwd_t, bwd_x;
@@ -301,34 +306,45 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             P.trsm.push_back(mk_launch(tr));
             P.inner.push_back(mk_launch(in));
             P.trail.push_back(mk_launch(tl));
-            // trailing update as tile-pair tasks: C(i, j) -= sum over the
-            // panel of L(i, kk) L(j, kk)^T for gend <= j <= i < M
-            TaskRange tt;
-            tt.off = (int64_t)tasks.size();
+            // left-looking updates as tile-pair tasks, C(i, j) -= sum over
+            // K of L(i, kk) L(j, kk)^T, for j <= i < M
+            auto pair_tasks = [&](int f, int j0, int j1, int kk0, int kk1) {
+                const Front& Fr = sym.fronts[f];
+                const int M = M_of(f);
+                const int64_t m = Fr.m;
+                for (int i = j0; i < M; i += 2)
+                    for (int j = j0; j < j1 && j <= i; j += 2) {
+                        GemmTask t{};
+                        t.c = Fr.off + TS * i + TS * j * m;
+                        t.ldc = (int32_t)m;
+                        t.flags = (1 << 4) | (BUF_FRONTS << 8) | (i + 1 < M ? GT_ROWS2 : 0) |
+                                  (j + 1 < j1 ? GT_COLS2 : 0) | (i == j ? GT_NOUPPER : 0);
+                        t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * kk0 * m, TS * m, (int)m, false, true,
+                                       BUF_FRONTS, Fr.off + TS * j + TS * kk0 * m, TS * m, (int)m, true, kk1 - kk0);
+                        tasks.push_back(t);
+                    }
+            };
+            TaskRange pt, ft;
+            pt.off = (int64_t)tasks.size();
+            if (!is_f32_level(ctx, l))
+                for (int f : lv[l]) {
+                    const int Pf = P_of(f);
+                    if (Pf <= k || k % PW != 0 || k == 0) continue;
+                    pair_tasks(f, k, std::min(k + PW, Pf), 0, k);
+                }
+            pt.n = (int64_t)tasks.size() - pt.off;
+            balance_range(tasks, pt);
+            P.panelT.push_back(pt);
+            ft.off = (int64_t)tasks.size();
             if (!is_f32_level(ctx, l))
                 for (int f : lv[l]) {
                     const int Pf = P_of(f), M = M_of(f);
-                    if (Pf <= k) continue;
-                    const int gend = std::min(PW * (g + 1), Pf);
-                    if (gend - 1 != k) continue;
-                    const int k0 = PW * g;
-                    const Front& Fr = sym.fronts[f];
-                    const int64_t m = Fr.m;
-                    for (int i = gend; i < M; i += 2)
-                        for (int j = gend; j <= i; j += 2) {
-                            GemmTask t{};
-                            t.c = Fr.off + TS * i + TS * j * m;
-                            t.ldc = (int32_t)m;
-                            t.flags = (1 << 4) | (BUF_FRONTS << 8) | (i + 1 < M ? GT_ROWS2 : 0) |
-                                      (j + 1 < M ? GT_COLS2 : 0) | (i == j ? GT_NOUPPER : 0);
-                            t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * k0 * m, TS * m, (int)m, false, true,
-                                           BUF_FRONTS, Fr.off + TS * j + TS * k0 * m, TS * m, (int)m, true, gend - k0);
-                            tasks.push_back(t);
-                        }
+                    if (Pf - 1 != k || M == Pf) continue;
+                    pair_tasks(f, Pf, M, 0, Pf);
                 }
-            tt.n = (int64_t)tasks.size() - tt.off;
-            balance_range(tasks, tt);
-            P.trailT.push_back(tt);
+            ft.n = (int64_t)tasks.size() - ft.off;
+            balance_range(tasks, ft);
+            P.finalT.push_back(ft);
         }
         std::vector<std::pair<int, int64_t>> ea, fx, fr;
         for (int f : lv[l]) {
@@ -842,6 +858,10 @@ static void enqueue_factor(ep_ctx* ctx) {
             continue;
         }
         for (size_t k = 0; k < P.potrf.size(); k++) {
+            const TaskRange& pu = P.panelT[k];
+            kt_begin(ctx, pu.n);
+            launch_gemm_tasks(st, ctx->d_tasks + pu.off, pu.n, b, false);
+            kt_end(ctx, pu.n, EP_KK_TRAIL);
             launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
             const Launch& t = P.trsm[k];
             kt_begin(ctx, t.ntasks);
@@ -851,10 +871,10 @@ static void enqueue_factor(ep_ctx* ctx) {
             kt_begin(ctx, s.ntasks);
             launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
             kt_end(ctx, s.ntasks, EP_KK_INNER);
-            const TaskRange& r = P.trailT[k];
-            kt_begin(ctx, r.n);
-            launch_gemm_tasks(st, ctx->d_tasks + r.off, r.n, b, false);
-            kt_end(ctx, r.n, EP_KK_TRAIL);
+            const TaskRange& fu = P.finalT[k];
+            kt_begin(ctx, fu.n);
+            launch_gemm_tasks(st, ctx->d_tasks + fu.off, fu.n, b, false);
+            kt_end(ctx, fu.n, EP_KK_TRAIL);
         }
         const Launch& e = P.extend;
         launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
