@@ -29,12 +29,13 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel (k_gemm_tasks<false>, every
 # launch of one FP64 sweep of the 64^3 / 100,000-star workload): rocprofv3
-# FETCH_SIZE and WRITE_SIZE summed over the sweep's 183 launches, each scaled
+# FETCH_SIZE and WRITE_SIZE summed over the sweep's 186 launches, each scaled
 # by what the same counter reads for a 1 GiB device copy (FETCH_SIZE x 2.000,
-# WRITE_SIZE x 1.000), divided by 183.  Taken for the kernel as it is; set to
-# None whenever the kernel changes until the counters are taken again.
-TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 2.6099e12 / 183, "write_bytes_per_launch": 2.4255e11 / 183,
-                      "bytes_per_launch": (2.6099e12 + 2.4255e11) / 183, "launches_per_sweep": 183,
+# WRITE_SIZE x 1.000), divided by 186.  Taken for the kernel and task lists
+# as they are; set to None whenever either changes until the counters are
+# taken again.
+TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 2.2679e12 / 186, "write_bytes_per_launch": 7.1949e10 / 186,
+                      "bytes_per_launch": (2.2679e12 + 7.1949e10) / 186, "launches_per_sweep": 186,
                       "source": "profiles/k_gemm_tasks_64cube_100k_traffic.md"}
 
 
