@@ -1285,7 +1285,10 @@ void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, 
 }
 
 // Gauss-Legendre 16-point nodes and weights from Newton's iteration on the
-// Legendre recurrence (computed on the host, copied to constant memory).
+// three-term Legendre recurrence, started from the asymptotic node estimate
+// cos(pi (i + 3/4) / (n + 1/2)) (the standard construction, e.g. Press et
+// al., Numerical Recipes, Sec. 4.5); computed on the host, copied to
+// constant memory.
 void set_gauss_legendre(hipStream_t st) {
     const int n = 16;
     double x[16], wgt[16];

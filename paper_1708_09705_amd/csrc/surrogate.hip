@@ -507,7 +507,9 @@ void launch_mlp_tilted(hipStream_t st, StarsDev s, EpParams p, const float* P, c
 }
 
 // n-node Gauss-Hermite rule (weight e^{-x^2}): Newton's iteration on the
-// orthonormal Hermite recurrence from the usual asymptotic first guesses.
+// orthonormal Hermite recurrence from the published asymptotic first guesses
+// for the largest nodes and extrapolation from the previous two for the
+// rest (Press et al., Numerical Recipes, Sec. 4.5).
 // Writes the nodes to out[0..n) and ln(weight) + node^2 to out[n..2n).
 static void gauss_hermite_rule(int n, double* out) {
     std::vector<double> x(n), w(n);
