@@ -191,28 +191,49 @@ constexpr int SLAB = KH * LDS2; // one operand slab in LDS (doubles)
 constexpr int GT_THREADS = 512;
 
 // One 128 x 32 operand slab op(M)(i, k), i in [0, 128), k in [0, 32), eight
-// elements per thread.  kc: k is the contiguous index in memory (element at
-// M[k + i ld]), otherwise i is (M[i + k ld]).  Rows i >= 64 are loaded only
-// when half2.
+// elements per thread loaded as four 16-byte pairs.  kc: k is the contiguous
+// index in memory (element at M[k + i ld]): a thread loads (k, k+1) of one i.
+// Otherwise i is contiguous: a thread loads (i, i+1) of one k.  Rows
+// i >= 64 are loaded only when half2.  Every offset is even, so the pairs
+// are 16-byte aligned.
+template <typename T> struct Pair;
+template <> struct Pair<double> { typedef double2 type; };
+template <> struct Pair<float> { typedef float2 type; };
+
 template <typename T>
 __device__ __forceinline__ void slab_load(double r[8], const T* M, int ld, bool kc, bool half2) {
+    typedef typename Pair<T>::type P2;
     const int t = threadIdx.x;
     if (!kc) {
-        const int i = t & 127, k0 = t >> 7;
-        if (i < 64 || half2) {
+        // lane pair p = t & 63 covers rows 2p, 2p + 1 of column k0 + 8q
+        const int p = t & 63, k0 = t >> 6;
+        if (p < 32 || half2) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) r[q] = (double)M[i + (int64_t)(k0 + 4 * q) * ld];
+            for (int q = 0; q < 4; q++) {
+                const P2 v = *(const P2*)(M + 2 * p + (int64_t)(k0 + 8 * q) * ld);
+                r[2 * q] = (double)v.x;
+                r[2 * q + 1] = (double)v.y;
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < 8; q++) r[q] = 0.0;
         }
     } else {
-        const int k = t & 31, i0 = t >> 5;
+        // k pair 2 (t & 15), column i0 + 32 q
+        const int kp = t & 15, i0 = t >> 4;
 #pragma unroll
-        for (int q = 0; q < 4; q++) r[q] = (double)M[k + (int64_t)(i0 + 16 * q) * ld];
+        for (int q = 0; q < 2; q++) {
+            const P2 v = *(const P2*)(M + 2 * kp + (int64_t)(i0 + 32 * q) * ld);
+            r[2 * q] = (double)v.x;
+            r[2 * q + 1] = (double)v.y;
+        }
         if (half2) {
 #pragma unroll
-            for (int q = 4; q < 8; q++) r[q] = (double)M[k + (int64_t)(i0 + 16 * q) * ld];
+            for (int q = 2; q < 4; q++) {
+                const P2 v = *(const P2*)(M + 2 * kp + (int64_t)(i0 + 32 * q) * ld);
+                r[2 * q] = (double)v.x;
+                r[2 * q + 1] = (double)v.y;
+            }
         } else {
 #pragma unroll
             for (int q = 4; q < 8; q++) r[q] = 0.0;
@@ -224,13 +245,19 @@ __device__ __forceinline__ void slab_load(double r[8], const T* M, int ld, bool 
 __device__ __forceinline__ void slab_store(const double r[8], double* s, bool kc, double sgn) {
     const int t = threadIdx.x;
     if (!kc) {
-        const int i = t & 127, k0 = t >> 7;
+        const int p = t & 63, k0 = t >> 6;
 #pragma unroll
-        for (int q = 0; q < 8; q++) s[(k0 + 4 * q) * LDS2 + i] = sgn * r[q];
+        for (int q = 0; q < 4; q++) {
+            s[(k0 + 8 * q) * LDS2 + 2 * p] = sgn * r[2 * q];
+            s[(k0 + 8 * q) * LDS2 + 2 * p + 1] = sgn * r[2 * q + 1];
+        }
     } else {
-        const int k = t & 31, i0 = t >> 5;
+        const int kp = t & 15, i0 = t >> 4;
 #pragma unroll
-        for (int q = 0; q < 8; q++) s[k * LDS2 + i0 + 16 * q] = sgn * r[q];
+        for (int q = 0; q < 4; q++) {
+            s[(2 * kp) * LDS2 + i0 + 32 * q] = sgn * r[2 * q];
+            s[(2 * kp + 1) * LDS2 + i0 + 32 * q] = sgn * r[2 * q + 1];
+        }
     }
 }
 
