@@ -306,42 +306,84 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             P.trsm.push_back(mk_launch(tr));
             P.inner.push_back(mk_launch(in));
             P.trail.push_back(mk_launch(tl));
-            // left-looking updates as tile-pair tasks, C(i, j) -= sum over
-            // K of L(i, kk) L(j, kk)^T, for j <= i < M
-            auto pair_tasks = [&](int f, int j0, int j1, int kk0, int kk1) {
+            // left-looking updates as 256 x 128 block tasks (four row tiles x
+            // two column tiles), C(i, j) -= sum over K of L(i, kk) L(j, kk)^T
+            // for j <= i < M; blocks straddling the diagonal store only their
+            // lower quadrants
+            // split > 1 cuts K into that many pieces that add into C
+            // atomically (used when a launch has too few blocks to fill the
+            // GPU)
+            auto lower_count = [&](int f, int j0, int j1) {
+                const int M = M_of(f);
+                int64_t c = 0;
+                for (int i = j0; i < M; i += 4)
+                    for (int j = j0; j < j1 && j <= i + 3; j += 2) c++;
+                return c;
+            };
+            auto lower_tasks = [&](int f, int j0, int j1, int kk0, int kk1, int split) {
                 const Front& Fr = sym.fronts[f];
                 const int M = M_of(f);
                 const int64_t m = Fr.m;
-                for (int i = j0; i < M; i += 2)
-                    for (int j = j0; j < j1 && j <= i; j += 2) {
-                        GemmTask t{};
-                        t.c = Fr.off + TS * i + TS * j * m;
-                        t.ldc = (int32_t)m;
-                        t.flags = (1 << 4) | (BUF_FRONTS << 8) | (i + 1 < M ? GT_ROWS2 : 0) |
-                                  (j + 1 < j1 ? GT_COLS2 : 0) | (i == j ? GT_NOUPPER : 0);
-                        t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * kk0 * m, TS * m, (int)m, false, true,
-                                       BUF_FRONTS, Fr.off + TS * j + TS * kk0 * m, TS * m, (int)m, true, kk1 - kk0);
-                        tasks.push_back(t);
-                    }
+                const int nk = kk1 - kk0;
+                for (int i = j0; i < M; i += 4)
+                    for (int j = j0; j < j1 && j <= i + 3; j += 2)
+                        for (int sp = 0; sp < split; sp++) {
+                            const int a0 = kk0 + (int)((int64_t)nk * sp / split);
+                            const int a1 = kk0 + (int)((int64_t)nk * (sp + 1) / split);
+                            if (a1 <= a0) continue;
+                            GemmTask t{};
+                            t.c = Fr.off + TS * i + TS * j * m;
+                            t.ldc = (int32_t)m;
+                            t.flags = (split > 1 ? 2 : 0) | (1 << 4) | (BUF_FRONTS << 8) |
+                                      gt_shape(std::min(4, M - i), j + 1 < j1, true, i - j, false);
+                            t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * a0 * m, TS * m, (int)m, false, true,
+                                           BUF_FRONTS, Fr.off + TS * j + TS * a0 * m, TS * m, (int)m, true, a1 - a0);
+                            tasks.push_back(t);
+                        }
+            };
+            // pieces of at least 8 K tiles, enough to give ~2 blocks per CU
+            auto split_for = [](int64_t nblocks, int nk) {
+                if (nblocks <= 0) return 1;
+                int64_t sp = (512 + nblocks - 1) / nblocks;
+                sp = std::min<int64_t>(sp, std::max(1, nk / 8));
+                return (int)std::max<int64_t>(1, sp);
             };
             TaskRange pt, ft;
             pt.off = (int64_t)tasks.size();
-            if (!is_f32_level(ctx, l))
+            if (!is_f32_level(ctx, l)) {
+                int64_t nb = 0;
                 for (int f : lv[l]) {
                     const int Pf = P_of(f);
                     if (Pf <= k || k % PW != 0 || k == 0) continue;
-                    pair_tasks(f, k, std::min(k + PW, Pf), 0, k);
+                    nb += lower_count(f, k, std::min(k + PW, Pf));
                 }
+                const int sp = split_for(nb, k);
+                for (int f : lv[l]) {
+                    const int Pf = P_of(f);
+                    if (Pf <= k || k % PW != 0 || k == 0) continue;
+                    lower_tasks(f, k, std::min(k + PW, Pf), 0, k, sp);
+                }
+            }
             pt.n = (int64_t)tasks.size() - pt.off;
             balance_range(tasks, pt);
             P.panelT.push_back(pt);
             ft.off = (int64_t)tasks.size();
-            if (!is_f32_level(ctx, l))
+            if (!is_f32_level(ctx, l)) {
+                int64_t nb = 0;
+                int nkmin = 1 << 30;
                 for (int f : lv[l]) {
                     const int Pf = P_of(f), M = M_of(f);
                     if (Pf - 1 != k || M == Pf) continue;
-                    pair_tasks(f, Pf, M, 0, Pf);
+                    nb += lower_count(f, Pf, M);
+                    nkmin = std::min(nkmin, Pf);
                 }
+                const int sp = nb > 0 ? split_for(nb, nkmin) : 1;
+                for (int f : lv[l]) {
+                    const int Pf = P_of(f), M = M_of(f);
+                    if (Pf - 1 != k || M == Pf) continue;
+                    lower_tasks(f, Pf, M, 0, Pf, sp);
+                }
+            }
             ft.n = (int64_t)tasks.size() - ft.off;
             balance_range(tasks, ft);
             P.finalT.push_back(ft);
@@ -376,25 +418,22 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             wb += (int64_t)TS * MR_of(lv[l][q]) * (int64_t)sym.fronts[lv[l][q]].nvpad;
         }
         Wmax = std::max(Wmax, wb);
-        // Tasks are 128 x 128 blocks: tile pairs (2p, 2p+1) of rows and of
-        // columns.  Where a pair's second tile lies in the upper triangle of
-        // a lower-triangular operand, that operand is zero there (X holds
-        // zeros above its diagonal), so a pair shares its first tile's K range.
-        auto pair_flags = [](bool rows2, bool cols2, bool noupper) {
-            return (rows2 ? GT_ROWS2 : 0) | (cols2 ? GT_COLS2 : 0) | (noupper ? GT_NOUPPER : 0);
-        };
+        // Tasks are 256 x 128 blocks: four row tiles x two column tiles.
+        // Where a block's later tiles lie in the upper triangle of a
+        // lower-triangular operand, that operand is zero there (X holds zeros
+        // above its diagonal), so a block shares its first tile's K range.
         P.selW.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int i = 0; i < MR; i += 2)
+            for (int i = 0; i < MR; i += 4)
                 for (int k = 0; k < Pf; k += 2) {
                     GemmTask t{};
                     t.c = wbase[q] + TS * i + TS * k * ldw;
                     t.ldc = (int32_t)ldw;
-                    t.flags = 1 | (1 << 4) | (BUF_W << 8) | pair_flags(i + 1 < MR, k + 1 < Pf, false);
+                    t.flags = 1 | (1 << 4) | (BUF_W << 8) | gt_shape(std::min(4, MR - i), k + 1 < Pf, false, 0, false);
                     // sum_{j=k}^{P-1} L(R_i, j) X(j, k)
                     t.s[0] = mkseg(Lbuf_of(f), Fr.off + nvp + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
                                    xb + TS * k + TS * k * nvp, TS, (int)nvp, false, Pf - k);
@@ -404,28 +443,31 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         P.selW.n = (int64_t)tasks.size() - P.selW.off;
         P.selW.a32 = is_f32_level(ctx, l);
         balance_range(tasks, P.selW);
+        // S21 = -S22 W, computed transposed: S21^T(k, i) = -sum_l W(l, k) S22(l, i),
+        // four pivot tiles k x two update tiles i per block, stored transposed
         P.selS21.off = (int64_t)tasks.size();
         for (size_t q = 0; q < lv[l].size(); q++) {
             const int f = lv[l][q];
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, nvp = Fr.nvpad;
-            for (int i = 0; i < MR; i += 2)
-                for (int k = 0; k < Pf; k += 2) {
+            for (int k = 0; k < Pf; k += 4)
+                for (int i = 0; i < MR; i += 2) {
                     GemmTask t{};
                     t.c = Fr.off + nvp + TS * i + TS * k * m;
                     t.ldc = (int32_t)m;
                     int nseg = 0;
-                    // l <= i: S22 tiles (i, l), (i+1, l) as stored
-                    t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * i + nvp * m, TS * m, (int)m, false, true, BUF_W,
-                                        wbase[q] + TS * k * ldw, TS, (int)ldw, false, i + 1);
-                    // l > i: S22 tiles (l, i), (l, i+1) transposed; at l = i+1
-                    // the second is the (symmetric, fully stored) diagonal tile
+                    // l <= i: S22(l, i) = tile (i, l) as stored, transposed
+                    t.s[nseg++] = mkseg(BUF_W, wbase[q] + TS * k * ldw, TS, (int)ldw, true, true, BUF_FRONTS,
+                                        Fr.off + nvp + TS * i + nvp * m, TS * m, (int)m, true, i + 1);
+                    // l > i: tiles (l, i), (l, i+1) as stored; at l = i+1 the
+                    // second is the (symmetric, fully stored) diagonal tile
                     if (i + 1 < MR)
-                        t.s[nseg++] = mkseg(BUF_FRONTS, Fr.off + nvp + TS * (i + 1) + (nvp + TS * i) * m, TS, (int)m,
-                                            true, true, BUF_W, wbase[q] + TS * (i + 1) + TS * k * ldw, TS, (int)ldw,
+                        t.s[nseg++] = mkseg(BUF_W, wbase[q] + TS * (i + 1) + TS * k * ldw, TS, (int)ldw, true, true,
+                                            BUF_FRONTS, Fr.off + nvp + TS * (i + 1) + (nvp + TS * i) * m, TS, (int)m,
                                             false, MR - i - 1);
-                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) | pair_flags(i + 1 < MR, k + 1 < Pf, false);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) |
+                              gt_shape(std::min(4, Pf - k), i + 1 < MR, false, 0, true);
                     tasks.push_back(t);
                 }
         }
@@ -437,8 +479,8 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             const Front& Fr = sym.fronts[f];
             const int Pf = P_of(f), MR = MR_of(f);
             const int64_t ldw = (int64_t)TS * MR, m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int k = 0; k < Pf; k += 2)
-                for (int j = 0; j <= k; j += 2) {
+            for (int k = 0; k < Pf; k += 4)
+                for (int j = 0; j < Pf && j <= k + 3; j += 2) {
                     GemmTask t{};
                     t.c = Fr.off + TS * k + TS * j * m;
                     t.ldc = (int32_t)m;
@@ -450,7 +492,8 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                     if (MR > 0)
                         t.s[nseg++] = mkseg(BUF_W, wbase[q] + TS * k * ldw, TS, (int)ldw, true, true, BUF_FRONTS,
                                             Fr.off + nvp + TS * j * m, TS, (int)m, false, MR);
-                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) | pair_flags(k + 1 < Pf, j + 1 < Pf, j == k);
+                    t.flags = 1 | (nseg << 4) | (BUF_FRONTS << 8) |
+                              gt_shape(std::min(4, Pf - k), j + 1 < Pf, true, k - j, false);
                     tasks.push_back(t);
                 }
         }
@@ -490,13 +533,12 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                 if ((Lbuf_of(f) == BUF_F32) != (pass == 1)) continue;
                 const Front& Fr = sym.fronts[f];
                 const int64_t ldt = (int64_t)TS * (b1 - b0), m = Fr.m, xb = ctx->xoff[f], nvp = Fr.nvpad;
-                for (int i = b0; i < b1; i += 2)
+                for (int i = b0; i < b1; i += 4)
                     for (int k = t0; k < b0; k += 2) {
                         GemmTask t{};
                         t.c = tbase + TS * (i - b0) + TS * (k - t0) * ldt;
                         t.ldc = (int32_t)ldt;
-                        t.flags = 1 | (1 << 4) | (BUF_W << 8) | (i + 1 < b1 ? GT_ROWS2 : 0) |
-                                  (k + 1 < b0 ? GT_COLS2 : 0);
+                        t.flags = 1 | (1 << 4) | (BUF_W << 8) | gt_shape(std::min(4, b1 - i), k + 1 < b0, false, 0, false);
                         // sum_{j=k}^{b0-1} L(i, j) X(j, k)
                         t.s[0] = mkseg(Lbuf_of(f), Fr.off + TS * i + TS * k * m, TS * m, (int)m, false, false, BUF_X,
                                        xb + TS * k + TS * k * nvp, TS, (int)nvp, false, b0 - k);
@@ -513,16 +555,16 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             std::tie(f, t0, b0, b1, tbase) = pr;
             const Front& Fr = sym.fronts[f];
             const int64_t ldt = (int64_t)TS * (b1 - b0), xb = ctx->xoff[f], nvp = Fr.nvpad;
-            for (int i = b0; i < b1; i += 2)
+            for (int i = b0; i < b1; i += 4)
                 for (int k = t0; k < b0; k += 2) {
-                    const bool rows2 = i + 1 < b1;
+                    const int nq = std::min(4, b1 - i);
                     GemmTask t{};
                     t.c = xb + TS * i + TS * k * nvp;
                     t.ldc = (int32_t)nvp;
-                    t.flags = 1 | (1 << 4) | (BUF_X << 8) | (rows2 ? GT_ROWS2 : 0) | (k + 1 < b0 ? GT_COLS2 : 0);
-                    // - sum_{j=b0}^{i or i+1} X(i, j) T(j, k)
+                    t.flags = 1 | (1 << 4) | (BUF_X << 8) | gt_shape(nq, k + 1 < b0, false, 0, false);
+                    // - sum_{j=b0}^{i + nq - 1} X(i, j) T(j, k)
                     t.s[0] = mkseg(BUF_X, xb + TS * i + TS * b0 * nvp, TS * nvp, (int)nvp, false, true, BUF_W,
-                                   tbase + TS * (k - t0) * ldt, TS, (int)ldt, false, (rows2 ? i + 1 : i) - b0 + 1);
+                                   tbase + TS * (k - t0) * ldt, TS, (int)ldt, false, i + nq - b0);
                     tasks.push_back(t);
                 }
         }
@@ -710,14 +752,20 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     TRY(upload(ctx, &ctx->d_flists, flists));
     TRY(upload(ctx, &ctx->d_batches, batches));
     TRY(upload(ctx, &ctx->d_tasks, tasks));
-    TRY(dev_alloc(ctx, &ctx->d_fronts, sym.total_elems));
-    TRY(dev_alloc(ctx, &ctx->d_X, ctx->X_elems));
+    // The GEMM tasks load whole 256 x 128 footprints, also the row quarters
+    // and column halves a task does not have (their results are discarded):
+    // every dense buffer ends in a pad of 256 leading dimensions (any leading
+    // dimension is at most the largest front order) so those loads stay in
+    // the allocation.
+    const int64_t pad = 256 * (int64_t)sym.max_m + 256;
+    TRY(dev_alloc(ctx, &ctx->d_fronts, sym.total_elems + pad));
+    TRY(dev_alloc(ctx, &ctx->d_X, ctx->X_elems + pad));
     // X tiles above the diagonal are never written and must read as zero
-    // (the 128 x 128 tasks run a tile pair over its first tile's K range)
+    // (a task runs its row and column tiles over the first tile's K range)
     launch_fill(ctx->stream, ctx->d_X, ctx->X_elems, 0.0);
-    TRY(dev_alloc(ctx, &ctx->d_W, ctx->W_elems));
+    TRY(dev_alloc(ctx, &ctx->d_W, ctx->W_elems + pad));
     TRY(dev_alloc(ctx, &ctx->d_err, 1));
-    if (c.precision == EP_PREC_MIXED) TRY(dev_alloc(ctx, &ctx->d_f32, sym.total_elems));
+    if (c.precision == EP_PREC_MIXED) TRY(dev_alloc(ctx, &ctx->d_f32, sym.total_elems + pad));
     TRY(upload(ctx, &ctx->d_brp, ctx->vec.rowptr));
     TRY(upload(ctx, &ctx->d_bcol, ctx->vec.col));
     TRY(upload(ctx, &ctx->d_bval, ctx->vec.val));

@@ -18,22 +18,36 @@ struct GemmSeg {
     int32_t lda, ldb, nk;
     int32_t flags;   // 1 transA, 2 transB, 4 negate; bits 8-9 buffer of A, 10-11 buffer of B
 };
-// C (128x128, column-major, ldc) = [C +] sum over segments: four 64x64
-// quadrants, the second row half and the second column half optional (their
-// operand rows / columns are neither read nor written when absent), and the
-// upper-right quadrant optionally not stored (diagonal blocks of a lower
-// triangle).  A segment's nk counts 64-deep K tiles; sa, sb step one of them.
-// A task without segments is padding and does nothing.
+// C (256 x 128, column-major, ldc) = [C +] sum over segments.  The block is
+// eight 64 x 64 quadrants (four 64-row quarters x two 64-column halves):
+// only the first gt_rows(flags) row quarters and, with GT_COLS2, the second
+// column half are present (their operand rows / columns are neither read
+// nor written when absent).  With GT_LOWER, quadrant (r, c) is stored only
+// when d + r - c >= 0, d = gt_diag(flags) the block's row tile minus column
+// tile (a lower-triangular output).  With GT_TSTORE the block is stored
+// transposed: element (i, j) to C[j + i ldc].  A segment's nk counts 64-deep
+// K tiles; sa, sb step one of them.  A task without segments is padding and
+// does nothing.
 struct GemmTask {
     int64_t c;
     int32_t ldc;
-    int32_t flags;   // 1 overwrite (else accumulate), 2 atomic add; bits 4-5 nseg; bits 8-9 buffer of C;
-                     // GT_ROWS2, GT_COLS2, GT_NOUPPER
+    int32_t flags;   // 1 overwrite, 2 atomic add (else accumulate); bits 4-5 nseg; bits 8-9 buffer of C; bits 12-14 row
+                     // quarters present; GT_COLS2, GT_LOWER (+ bits 17-19 d + 4), GT_TSTORE
     GemmSeg s[2];
 };
-constexpr int32_t GT_ROWS2 = 1 << 12;    // rows 64..127 present
-constexpr int32_t GT_COLS2 = 1 << 13;    // columns 64..127 present
-constexpr int32_t GT_NOUPPER = 1 << 14;  // do not store rows 0..63 x columns 64..127
+constexpr int32_t GT_COLS2 = 1 << 15;    // columns 64..127 present
+constexpr int32_t GT_LOWER = 1 << 16;    // store only quadrants on or below the diagonal
+constexpr int32_t GT_TSTORE = 1 << 20;   // store the block transposed
+__host__ __device__ inline int32_t gt_rows(int32_t flags) { return (flags >> 12) & 7; }
+__host__ __device__ inline int32_t gt_diag(int32_t flags) { return ((flags >> 17) & 7) - 4; }
+// flags for a block with nq row quarters, an optional second column half,
+// optionally lower-triangular with row tile - column tile = d, optionally
+// stored transposed
+inline int32_t gt_shape(int nq, bool cols2, bool lower, int d, bool tstore) {
+    int32_t f = (nq << 12) | (cols2 ? GT_COLS2 : 0) | (tstore ? GT_TSTORE : 0);
+    if (lower) f |= GT_LOWER | ((d < -4 ? 0 : (d > 1 ? 5 : d + 4)) << 17);
+    return f;
+}
 
 // Front metadata (structure of arrays, device pointers).
 struct FrontsDev {

@@ -174,130 +174,116 @@ __device__ __forceinline__ int64_t xcd_task(int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Task-list GEMM on 128 x 128 output blocks (diagonal-block inverses and the
-// selected inversion).  One block of eight waves per CU, two per SIMD, so one
-// wave's MFMAs cover the other's LDS traffic and barriers.  Wave w computes
-// rows 64 ((w >> 1) & 1) .. +64 and columns 64 (w & 1) + 32 (w >> 2) .. +32
-// (4 x 2 MFMA 16x16x4 blocks, accumulators in AGPRs); waves w and w + 4 share
-// a 64 x 64 quadrant.  K advances in slabs of 32 through two LDS buffers:
-// while the MFMAs consume one slab the next is stored to the other buffer and
-// the global loads of the slab after that are in flight; one barrier per slab.
+// Task-list GEMM on 256 x 128 output blocks (trailing updates, diagonal-block
+// inverses, selected inversion).  One block of eight waves per CU, two waves
+// per SIMD; wave w owns the 64 x 64 quadrant (row quarter w >> 1, column
+// half w & 1) as 4 x 4 v_mfma_f64_16x16x4f64 blocks.  K advances in slabs of
+// 16 through two LDS buffers and two register stages: a slab's global loads
+// (16-byte pairs) are issued two MFMA phases before they are stored to LDS;
+// one barrier per slab.
 // ---------------------------------------------------------------------------
-constexpr int BT = 128;         // output block edge
-constexpr int KH = 32;          // K slab depth
-constexpr int LDS2 = BT + 1;    // LDS row stride (doubles): odd, so the
-                                // k-contiguous stores hit distinct banks
-constexpr int SLAB = KH * LDS2; // one operand slab in LDS (doubles)
+constexpr int BM = 256;              // output rows per block (op(A) side)
+constexpr int BN = 128;              // output columns per block (op(B) side)
+constexpr int KH = 16;               // K slab depth
+constexpr int LDA2 = BM + 4;         // LDS row strides (doubles)
+constexpr int LDB2 = BN + 4;
+constexpr int SLA = KH * LDA2, SLB = KH * LDB2;
 constexpr int GT_THREADS = 512;
 
-// One 128 x 32 operand slab op(M)(i, k), i in [0, 128), k in [0, 32), eight
-// elements per thread loaded as four 16-byte pairs.  kc: k is the contiguous
-// index in memory (element at M[k + i ld]): a thread loads (k, k+1) of one i.
-// Otherwise i is contiguous: a thread loads (i, i+1) of one k.  Rows
-// i >= 64 are loaded only when half2.  Every offset is even, so the pairs
-// are 16-byte aligned.
 template <typename T> struct Pair;
 template <> struct Pair<double> { typedef double2 type; };
 template <> struct Pair<float> { typedef float2 type; };
 
-template <typename T>
-__device__ __forceinline__ void slab_load(double r[8], const T* M, int ld, bool kc, bool half2) {
+// One R x 16 operand slab op(M)(i, k), i in [0, R), k in [0, 16), loaded as
+// 16-byte pairs by all 512 threads (NP pairs each).  kc: k is the contiguous
+// index in memory (element at M[k + i ld]): a thread loads (k, k+1) of one
+// i.  Otherwise i is contiguous: a thread loads (i, i+1) of one k.  Every
+// offset and leading dimension is even, so the pairs are aligned.  Row
+// quarters a task does not have are loaded all the same: every buffer ends
+// in a pad of 256 leading dimensions, so the reads stay in the allocation,
+// and only waves whose quadrant is absent (and which skip their MFMAs) ever
+// read those rows of LDS.
+template <int R, typename T>
+__device__ __forceinline__ void slab_load(double* r, const T* M, int ld, bool kc) {
     typedef typename Pair<T>::type P2;
+    constexpr int NP = R * KH / 2 / GT_THREADS;
     const int t = threadIdx.x;
     if (!kc) {
-        // lane pair p = t & 63 covers rows 2p, 2p + 1 of column k0 + 8q
-        const int p = t & 63, k0 = t >> 6;
-        if (p < 32 || half2) {
+        constexpr int PR = R / 2;   // pairs per column
+        constexpr int KS = GT_THREADS / PR;
+        const int p = t % PR, k0 = t / PR;
+        const T* Mp = M + 2 * p + (int64_t)k0 * ld;
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const P2 v = *(const P2*)(M + 2 * p + (int64_t)(k0 + 8 * q) * ld);
-                r[2 * q] = (double)v.x;
-                r[2 * q + 1] = (double)v.y;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 8; q++) r[q] = 0.0;
-        }
-    } else {
-        // k pair 2 (t & 15), column i0 + 32 q
-        const int kp = t & 15, i0 = t >> 4;
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const P2 v = *(const P2*)(M + 2 * kp + (int64_t)(i0 + 32 * q) * ld);
+        for (int q = 0; q < NP; q++) {
+            const P2 v = *(const P2*)(Mp + (int64_t)(KS * q) * ld);
             r[2 * q] = (double)v.x;
             r[2 * q + 1] = (double)v.y;
         }
-        if (half2) {
+    } else {
+        const int kp = t & 7, i0 = t >> 3;   // 64 columns per round
+        const T* Mp = M + 2 * kp + (int64_t)i0 * ld;
 #pragma unroll
-            for (int q = 2; q < 4; q++) {
-                const P2 v = *(const P2*)(M + 2 * kp + (int64_t)(i0 + 32 * q) * ld);
-                r[2 * q] = (double)v.x;
-                r[2 * q + 1] = (double)v.y;
-            }
-        } else {
-#pragma unroll
-            for (int q = 4; q < 8; q++) r[q] = 0.0;
+        for (int q = 0; q < NP; q++) {
+            const P2 v = *(const P2*)(Mp + (int64_t)(64 * q) * ld);
+            r[2 * q] = (double)v.x;
+            r[2 * q + 1] = (double)v.y;
         }
     }
 }
 
-// Write a slab to LDS as s[k][i] (row stride LDS2), scaled by sgn.
-__device__ __forceinline__ void slab_store(const double r[8], double* s, bool kc, double sgn) {
+// Write a slab to LDS as s[k][i] (row stride LD), scaled by sgn.
+template <int R, int LD>
+__device__ __forceinline__ void slab_store(const double* r, double* s, bool kc, double sgn) {
+    constexpr int NP = R * KH / 2 / GT_THREADS;
     const int t = threadIdx.x;
     if (!kc) {
-        const int p = t & 63, k0 = t >> 6;
+        constexpr int PR = R / 2;
+        constexpr int KS = GT_THREADS / PR;
+        const int p = t % PR, k0 = t / PR;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            s[(k0 + 8 * q) * LDS2 + 2 * p] = sgn * r[2 * q];
-            s[(k0 + 8 * q) * LDS2 + 2 * p + 1] = sgn * r[2 * q + 1];
+        for (int q = 0; q < NP; q++) {
+            s[(k0 + KS * q) * LD + 2 * p] = sgn * r[2 * q];
+            s[(k0 + KS * q) * LD + 2 * p + 1] = sgn * r[2 * q + 1];
         }
     } else {
-        const int kp = t & 15, i0 = t >> 4;
+        const int kp = t & 7, i0 = t >> 3;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            s[(2 * kp) * LDS2 + i0 + 32 * q] = sgn * r[2 * q];
-            s[(2 * kp + 1) * LDS2 + i0 + 32 * q] = sgn * r[2 * q + 1];
+        for (int q = 0; q < NP; q++) {
+            s[(2 * kp) * LD + i0 + 64 * q] = sgn * r[2 * q];
+            s[(2 * kp + 1) * LD + i0 + 64 * q] = sgn * r[2 * q + 1];
         }
     }
 }
 
-// acc (this wave's 64 x 32 piece) += sum over the slab's k of sA[k][i] sB[k][j].
-// The LDS reads of step kk + 4 are issued before the MFMAs of step kk.
-__device__ __forceinline__ void slab_mma(d4 acc[4][2], const double* sA, const double* sB) {
+// acc (this wave's quadrant) += sum over the slab's k of sA[k][i] sB[k][j]
+__device__ __forceinline__ void slab_mma(d4 acc[4][4], const double* sA, const double* sB) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wr = ((w >> 1) & 1) * 64, wc = (w & 1) * 64 + (w >> 2) * 32;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
     const int li = lane & 15, lk = lane >> 4;
-    const double* ra = sA + lk * LDS2 + wr + li;
-    const double* rb = sB + lk * LDS2 + wc + li;
-    double a[2][4], b[2][2];
 #pragma unroll
-    for (int q = 0; q < 4; q++) a[0][q] = ra[16 * q];
+    for (int kk = 0; kk < KH; kk += 4) {
+        const double* ra = sA + (kk + lk) * LDA2 + wr + li;
+        const double* rb = sB + (kk + lk) * LDB2 + wc + li;
+        double a[4], b[4];
 #pragma unroll
-    for (int q = 0; q < 2; q++) b[0][q] = rb[16 * q];
-#pragma unroll
-    for (int s = 0; s < KH / 4; s++) {
-        const int c = s & 1, n = c ^ 1;
-        if (s + 1 < KH / 4) {
-#pragma unroll
-            for (int q = 0; q < 4; q++) a[n][q] = ra[(s + 1) * 4 * LDS2 + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 2; q++) b[n][q] = rb[(s + 1) * 4 * LDS2 + 16 * q];
+        for (int q = 0; q < 4; q++) {
+            a[q] = ra[16 * q];
+            b[q] = rb[16 * q];
         }
 #pragma unroll
         for (int x = 0; x < 4; x++)
 #pragma unroll
-            for (int y = 0; y < 2; y++)
-                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][x], b[c][y], acc[x][y], 0, 0, 0);
+            for (int y = 0; y < 4; y++)
+                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
 }
 
 // One segment: acc += sum over its K of op(A) op(B).  smem holds two
-// buffers of (A slab, B slab) and two register stages hold the next two
-// slabs, so a slab's global loads have two MFMA phases to arrive.  Ends with
-// a barrier after the last read of smem.
+// buffers of (A slab, B slab); two register stages hold the next two
+// slabs.  Ends with a barrier after the last read of smem.
 template <typename TA>
-__device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA* A, const double* B,
-                                           const GemmSeg& S, bool rows2, bool cols2, bool active) {
+__device__ __forceinline__ void seg_run(d4 acc[4][4], double* smem, const TA* A, const double* B, const GemmSeg& S,
+                                        bool active) {
     const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
     const double sgn = (S.flags & 4) ? -1.0 : 1.0;
     // op(A)(i, k): transposed A has k contiguous; op(B)(k, j): plain B has k contiguous
@@ -305,43 +291,44 @@ __device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA*
     const int nh = (TS / KH) * S.nk;
     const int64_t ha = S.sa / (TS / KH), hb = S.sb / (TS / KH);
     if (nh <= 0) return;
-    double* B0 = smem;
-    double* B1 = smem + 2 * SLAB;
-    double a0[8], b0[8], a1[8], b1[8];
-    slab_load(a0, A, S.lda, kca, rows2);
-    slab_load(b0, B, S.ldb, kcb, cols2);
+    double* U0 = smem;
+    double* U1 = smem + SLA + SLB;
+    double a0[BM * KH / GT_THREADS], b0[BN * KH / GT_THREADS];
+    double a1[BM * KH / GT_THREADS], b1[BN * KH / GT_THREADS];
+    slab_load<BM>(a0, A, S.lda, kca);
+    slab_load<BN>(b0, B, S.ldb, kcb);
     if (nh > 1) {
-        slab_load(a1, A + ha, S.lda, kca, rows2);
-        slab_load(b1, B + hb, S.ldb, kcb, cols2);
+        slab_load<BM>(a1, A + ha, S.lda, kca);
+        slab_load<BN>(b1, B + hb, S.ldb, kcb);
     }
-    slab_store(a0, B0, kca, sgn);
-    slab_store(b0, B0 + SLAB, kcb, 1.0);
+    slab_store<BM, LDA2>(a0, U0, kca, sgn);
+    slab_store<BN, LDB2>(b0, U0 + SLA, kcb, 1.0);
     if (nh > 2) {
-        slab_load(a0, A + 2 * ha, S.lda, kca, rows2);
-        slab_load(b0, B + 2 * hb, S.ldb, kcb, cols2);
+        slab_load<BM>(a0, A + 2 * ha, S.lda, kca);
+        slab_load<BN>(b0, B + 2 * hb, S.ldb, kcb);
     }
     __syncthreads();
     for (int h = 0; h < nh; h += 2) {
-        // slab h in B0; slab h + 1 in stage 1, slab h + 2 in stage 0
-        if (active) slab_mma(acc, B0, B0 + SLAB);
+        // slab h in U0; slab h + 1 in stage 1, slab h + 2 in stage 0
+        if (active) slab_mma(acc, U0, U0 + SLA);
         if (h + 1 < nh) {
-            slab_store(a1, B1, kca, sgn);
-            slab_store(b1, B1 + SLAB, kcb, 1.0);
+            slab_store<BM, LDA2>(a1, U1, kca, sgn);
+            slab_store<BN, LDB2>(b1, U1 + SLA, kcb, 1.0);
             if (h + 3 < nh) {
-                slab_load(a1, A + (h + 3) * ha, S.lda, kca, rows2);
-                slab_load(b1, B + (h + 3) * hb, S.ldb, kcb, cols2);
+                slab_load<BM>(a1, A + (h + 3) * ha, S.lda, kca);
+                slab_load<BN>(b1, B + (h + 3) * hb, S.ldb, kcb);
             }
         }
         __syncthreads();
         if (h + 1 >= nh) break;
-        // slab h + 1 in B1; slab h + 2 in stage 0, slab h + 3 in stage 1
-        if (active) slab_mma(acc, B1, B1 + SLAB);
+        // slab h + 1 in U1; slab h + 2 in stage 0, slab h + 3 in stage 1
+        if (active) slab_mma(acc, U1, U1 + SLA);
         if (h + 2 < nh) {
-            slab_store(a0, B0, kca, sgn);
-            slab_store(b0, B0 + SLAB, kcb, 1.0);
+            slab_store<BM, LDA2>(a0, U0, kca, sgn);
+            slab_store<BN, LDB2>(b0, U0 + SLA, kcb, 1.0);
             if (h + 4 < nh) {
-                slab_load(a0, A + (h + 4) * ha, S.lda, kca, rows2);
-                slab_load(b0, B + (h + 4) * hb, S.ldb, kcb, cols2);
+                slab_load<BM>(a0, A + (h + 4) * ha, S.lda, kca);
+                slab_load<BN>(b0, B + (h + 4) * hb, S.ldb, kcb);
             }
         }
         __syncthreads();
@@ -352,49 +339,48 @@ __device__ __forceinline__ void seg128_run(d4 acc[4][2], double* smem, const TA*
 // copy of the factor (mixed precision), upcast on load; B is FP64.
 template <bool A32>
 __global__ __launch_bounds__(GT_THREADS) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
-    __shared__ double smem[4 * SLAB];
+    __shared__ double smem[2 * (SLA + SLB)];
     const int64_t t = xcd_task(n);
     if (t >= n) return;
     const GemmTask& T = tasks[t];
     if (((T.flags >> 4) & 3) == 0) return;   // padding entry
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int qr = (w >> 1) & 1, qc = w & 1;
-    const bool rows2 = T.flags & GT_ROWS2, cols2 = (T.flags & GT_COLS2) != 0;
+    const int qr = w >> 1, qc = w & 1;
+    const int nqa = gt_rows(T.flags), nqb = (T.flags & GT_COLS2) ? 2 : 1;
     // this wave's quadrant is (qr, qc)
-    const bool mine = (qr == 0 || rows2) && (qc == 0 || cols2) && !(qr == 0 && qc == 1 && (T.flags & GT_NOUPPER));
-    d4 acc[4][2];
+    const bool mine = qr < nqa && qc < nqb && (!(T.flags & GT_LOWER) || gt_diag(T.flags) + qr - qc >= 0);
+    d4 acc[4][4];
 #pragma unroll
     for (int x = 0; x < 4; x++)
 #pragma unroll
-        for (int y = 0; y < 2; y++) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < 4; y++) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     if (A32) {
         const GemmSeg& S = T.s[0];
-        seg128_run(acc, smem, bufs.F32 + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S, rows2, cols2, mine);
+        seg_run(acc, smem, bufs.F32 + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S, mine);
     } else {
         const int nseg = (T.flags >> 4) & 3;
-        for (int q = 0; q < nseg; q++) {
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            if (q >= nseg) break;
             const GemmSeg& S = T.s[q];
-            seg128_run(acc, smem, buf_of(bufs, (S.flags >> 8) & 3) + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S,
-                       rows2, cols2, mine);
+            seg_run(acc, smem, buf_of(bufs, (S.flags >> 8) & 3) + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S,
+                    mine);
         }
     }
     if (!mine) return;
-    double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c;
-    const int mode = (T.flags & 2) ? 2 : ((T.flags & 1) ? 1 : 0);
-    const int wr = qr * 64, wc = qc * 64 + (w >> 2) * 32;
+    const bool over = T.flags & 1, atom = (T.flags & 2) != 0;
+    const int64_t rs = (T.flags & GT_TSTORE) ? T.ldc : 1, cs = (T.flags & GT_TSTORE) ? 1 : T.ldc;
+    double* C = buf_of(bufs, (T.flags >> 8) & 3) + T.c + (qr * 64 + (lane >> 4)) * rs + (qc * 64 + (lane & 15)) * cs;
     // v_mfma_f64_16x16x4f64 output: lane l, item r -> row l/16 + 4r, column l%16
 #pragma unroll
     for (int x = 0; x < 4; x++)
 #pragma unroll
-        for (int y = 0; y < 2; y++)
+        for (int y = 0; y < 4; y++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int row = wr + 16 * x + (lane >> 4) + 4 * r;
-                const int col = wc + 16 * y + (lane & 15);
-                double* p = C + row + (int64_t)col * T.ldc;
-                if (mode == 1) *p = acc[x][y][r];
-                else if (mode == 0) *p += acc[x][y][r];
-                else atomicAdd(p, acc[x][y][r]);
+                double* p = C + (16 * x + 4 * r) * rs + (16 * y) * cs;
+                if (atom) atomicAdd(p, acc[x][y][r]);
+                else *p = over ? acc[x][y][r] : *p + acc[x][y][r];
             }
 }
 
