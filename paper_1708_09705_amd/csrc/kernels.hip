@@ -961,29 +961,35 @@ void launch_los(hipStream_t st, GridDev g, StarsDev s, const double* f, int cap)
 // Assembly of the sites into the fronts: tau_n g_n g_n^T lands in the front
 // of the star's first-eliminated support node (its whole clique is there).
 // ---------------------------------------------------------------------------
+// One wave per star: its clique P_n x P_n (lower triangle, support nodes in
+// ascending local row) gets tau g g^T.  Column b by column b, the lanes take
+// consecutive rows a >= b, so one wave's atomic adds fall in neighbouring
+// cache lines.
 __global__ __launch_bounds__(256) void k_assemble_stars(StarsDev s, FrontsDev F, double* fronts, int cap) {
     extern __shared__ char smem[];
-    int32_t* sl = (int32_t*)smem;
-    double* sg = (double*)(smem + ((size_t)cap * sizeof(int32_t) + 15) / 16 * 16);
-    const int64_t star = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t* sl = (int32_t*)smem + w * cap;
+    double* sg = (double*)(smem + ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16) + w * cap;
+    const int64_t star = (int64_t)blockIdx.x * 4 + w;
+    if (star >= s.n) return;
     const double tau = s.tau[star];
     if (tau == 0.0) return;
     const int64_t p0 = s.ptr[star];
     const int cnt = (int)(s.ptr[star + 1] - p0);
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-        int slot = s.sord[p0 + k];
+    for (int k = lane; k < cnt; k += 64) {
+        const int slot = s.sord[p0 + k];
         sl[k] = s.loc[p0 + slot];
         sg[k] = s.g[p0 + slot];
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0);
     const int f = s.front[star];
     double* base = fronts + F.off[f];
     const int64_t m = F.m[f];
-    const int64_t npair = (int64_t)cnt * (cnt + 1) / 2;
-    for (int64_t q = threadIdx.x; q < npair; q += blockDim.x) {
-        int a, b;
-        tri_decode(q, a, b);
-        atomicAdd(base + sl[a] + (int64_t)sl[b] * m, tau * sg[a] * sg[b]);
+    for (int b = 0; b < cnt; b++) {
+        const double tg = tau * sg[b];
+        double* col = base + (int64_t)sl[b] * m;
+        for (int a = b + lane; a < cnt; a += 64) atomicAdd(col + sl[a], tg * sg[a]);
     }
 }
 
@@ -1000,8 +1006,8 @@ __global__ void k_assemble_b(StarsDev s, double* b) {
 
 void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int cap) {
     if (s.n <= 0) return;
-    size_t sh = ((size_t)cap * sizeof(int32_t) + 15) / 16 * 16 + (size_t)cap * sizeof(double);
-    hipLaunchKernelGGL(k_assemble_stars, dim3((unsigned)s.n), dim3(256), sh, st, s, F, fronts, cap);
+    size_t sh = ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16 + (size_t)4 * cap * sizeof(double);
+    hipLaunchKernelGGL(k_assemble_stars, dim3((unsigned)((s.n + 3) / 4)), dim3(256), sh, st, s, F, fronts, cap);
 }
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b) {
     if (s.n <= 0) return;
