@@ -34,7 +34,9 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE x 1.000), divided by 186.  Taken for the kernel and task lists
 # as they are; set to None whenever either changes until the counters are
 # taken again.
-TRAFFIC_GEMM_TASKS = None
+TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 1.4808e12 / 186, "write_bytes_per_launch": 7.6430e10 / 186,
+                      "bytes_per_launch": (1.4808e12 + 7.6430e10) / 186, "launches_per_sweep": 186,
+                      "source": "profiles/k_gemm_tasks_64cube_100k_traffic.md"}
 
 
 def log(*a):
@@ -163,7 +165,7 @@ def main():
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
           ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")}
     # Dominant kernel: k_gemm_tasks<false>, the FP64 MFMA task-list GEMM on
-    # 128 x 128 blocks.  In an FP64 sweep every one of its launches is either
+    # 256 x 128 blocks.  In an FP64 sweep every one of its launches is either
     # a trailing update of the factorization (EP_KK_TRAIL) or a
     # diagonal-block inverse / selected-inversion product (EP_KK_GEMM).  Each
     # launch is timed with HIP events on the library's stream; the work
@@ -199,7 +201,7 @@ def main():
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": TRAFFIC_GEMM_TASKS["bytes_per_launch"] if TRAFFIC_GEMM_TASKS else None,
                      "traffic_unit": "HBM bytes per launch", "traffic_detail": TRAFFIC_GEMM_TASKS,
-                     "kernel": "k_gemm_tasks<false> (FP64 MFMA, 128x128 blocks: trailing updates, "
+                     "kernel": "k_gemm_tasks<false> (FP64 MFMA, 256x128 blocks: trailing updates, "
                                "diagonal-block inverses, selected inversion)",
                      "launches_per_step": launches, "kernel_ms_per_step": gemm_ms,
                      "avg_launch_ms": gemm_ms / max(launches, 1),
