@@ -157,7 +157,8 @@ void ep_config_default(ep_config *cfg);
  * distances (Sec. 4.1); A_obs: observed extinction (mag; in the
  * gauss_linear mode the observed log-extinction); sigma: 1-sigma noise
  * (> 0).  Errors: INVALID_ARG (bad config, non-finite input, star outside
- * the cube), OOM, DEVICE. */
+ * the cube or at the observer), OOM, DEVICE.  n_stars = 0 is allowed: the
+ * posterior is then the prior. */
 int ep_init(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *A_obs,
             const double *sigma, ep_ctx **out);
 

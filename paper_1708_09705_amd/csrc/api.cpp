@@ -612,6 +612,14 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
                 err = "star " + std::to_string(s) + " lies outside the cube or is not finite";
                 return EP_ERR_INVALID_ARG;
             }
+        {
+            double d2 = 0;
+            for (int a = 0; a < 3; a++) d2 += (xyz[3 * s + a] - c->observer_pc[a]) * (xyz[3 * s + a] - c->observer_pc[a]);
+            if (!(std::sqrt(d2) > 1e-9 * c->box_pc)) {
+                err = "star " + std::to_string(s) + " coincides with the observer (zero sightline)";
+                return EP_ERR_INVALID_ARG;
+            }
+        }
         if (!std::isfinite(A[s])) { err = "A_obs of star " + std::to_string(s) + " is not finite"; return EP_ERR_INVALID_ARG; }
         if (!(sig[s] > 0) || !std::isfinite(sig[s])) {
             err = "sigma of star " + std::to_string(s) + " must be finite and > 0";

@@ -49,7 +49,8 @@ def test_invalid_inputs_rejected_before_device_work():
     s = np.array([0.05, 0.05])
     cfg = E.make_config()
     for bad in (dict(A=np.array([math.nan, 0.4])), dict(s=np.array([0.05, 0.0])),
-                dict(xyz=np.array([[100.0, 200.0, 300.0], [400.0, 500.0, 1200.0]]))):
+                dict(xyz=np.array([[100.0, 200.0, 300.0], [400.0, 500.0, 1200.0]])),
+                dict(xyz=np.array([[100.0, 200.0, 300.0], [500.0, 0.0, 500.0]]))):   # at the observer
         with pytest.raises(E.EPError) as ei:
             E.ep_init(cfg, bad.get("xyz", xyz), bad.get("A", A), bad.get("s", s))
         assert ei.value.code == -1
