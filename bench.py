@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the surrogate + mixed-precision run (FP32 factor + FP64 refinement, "
                          "network moments with quadrature fallback)")
+    ap.add_argument("--no-maps", dest="maps", action="store_false",
+                    help="skip timing the map predictions after the FP64 run")
     ap.add_argument("--mixed-quadrature", action="store_true",
                     help="also run mixed precision with quadrature moments")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -133,7 +135,43 @@ def main():
 
     weights = np.load(os.path.join(ROOT, "paper_1708_09705_amd", "surrogate_64cube.npy"))
 
-    def run(prec, moments="quadrature"):
+    def maps_leg(g):
+        # Map predictions from the converged state of the FP64 run; every call
+        # recomputes q(f) (factor, solve, selected inversion) first.
+        N = w.n ** 3
+        out = {}
+        t0 = time.perf_counter()
+        g.density_moments()
+        out["ms_density_moments"] = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        g.extinction_map()
+        out["ms_extinction_mean"] = (time.perf_counter() - t0) * 1e3
+        K = 8
+        z = np.random.default_rng(123).standard_normal((K, N))
+        t0 = time.perf_counter()
+        g.extinction_map(z)
+        out["ms_extinction_mean_and_var"] = (time.perf_counter() - t0) * 1e3
+        out["draws"] = K
+        # the paper's two-point layout: every node x and x + 10 pc along the
+        # observer's ray, where that point is still inside the cube
+        h = w.box_pc / (w.n - 1)
+        i = np.arange(N)
+        x = np.stack([(i % w.n) * h, ((i // w.n) % w.n) * h, (i // (w.n * w.n)) * h], axis=1)
+        o = np.asarray(w.ep_fields()["observer_pc"], dtype=np.float64)
+        d = np.linalg.norm(x - o, axis=1)
+        ok = d > 0
+        x2 = x[ok] + 10.0 * (x[ok] - o) / d[ok][:, None]
+        inside = np.all((x2 >= 0) & (x2 <= w.box_pc), axis=1)
+        xyz2 = np.hstack([x[ok][inside], x2[inside]])
+        t0 = time.perf_counter()
+        g.point_predict(xyz2)
+        out["ms_two_point_density"] = (time.perf_counter() - t0) * 1e3
+        out["pairs"] = int(len(xyz2))
+        out["note"] = ("each call includes the factorization, solve and selected inversion of q(f); "
+                       "mean and var: exact mean plus the sample variance over the draws")
+        return out
+
+    def run(prec, moments="quadrature", after=None):
         c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec,
                           moments=moments)
         t0 = time.perf_counter()
@@ -156,10 +194,11 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         mean, var = (g.posterior_mean(), g.marginal_var()) if args.mixed else (None, None)
+        extra = after(g) if after else None
         g.close()
-        return st, stats, wall, mean, var
+        return st, stats, wall, mean, var, extra
 
-    st, stats, wall, mean64, var64 = run("fp64")
+    st, stats, wall, mean64, var64, maps = run("fp64", after=maps_leg if args.maps else None)
     S = w.n_stars
     value = S * args.steps / wall
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
@@ -216,7 +255,7 @@ def main():
                                                    "tflops": all_flops / (mfma_ms * 1e-3) / 1e12}}},
     }
     def leg(prec, moments):
-        st32, stats32, wall32, mean32, var32 = run(prec, moments)
+        st32, stats32, wall32, mean32, var32, _ = run(prec, moments)
         ph32 = {k: float(np.mean([s[k] for s in stats32])) for k in ph}
         return {
             "value": S * args.steps / wall32, "unit": "star-updates/s", "ms_per_step": wall32 / args.steps * 1e3,
@@ -231,6 +270,8 @@ def main():
             "note": "same warm-up and step count as the FP64 run; errors after the same sweeps",
         }
 
+    if maps:
+        line["maps"] = maps
     if args.mixed:
         line["surrogate_mixed"] = leg("mixed", "surrogate")
         if args.mixed_quadrature:

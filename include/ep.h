@@ -269,6 +269,47 @@ int ep_mlp_load(ep_ctx *ctx, const float *weights);
 /* Structure and memory figures of a context. */
 int ep_structure(const ep_ctx *ctx, ep_structure_stats *out);
 
+/* ---- Map prediction from the posterior (Sec. 5: maps of extinction and
+ * of the pseudo-density rho kappa = e^f) ----
+ * Each call, like ep_posterior_mean, recomputes q(f) = N(mu, Sigma) from the
+ * current sites at the current linearisation point and changes no state.
+ * Outputs are host arrays owned by the caller, in node order. */
+
+/* The elimination order: perm[i] is the grid node eliminated i-th (N int32). */
+int ep_ordering(const ep_ctx *ctx, int32_t *perm);
+
+/* Posterior moments of rho kappa = e^f at every node (lognormal under q):
+ * mean = exp(mu + v/2), var = (e^v - 1) exp(2 mu + v). */
+int ep_density_moments(ep_ctx *ctx, double *mean, double *var);
+
+/* Extinction A(x) from the observer to every grid node x, by the sightline
+ * forward model (trapezoid at los_step_pc, trilinear field; 0 at the
+ * observer's own node).  mean: the exact posterior mean (each sample point
+ * s contributes its weight times exp(m(s) + v(s)/2), m and v from mu and
+ * the Sigma block of the point's cell).  var (may be NULL): the sample
+ * variance (divisor n_samples - 1) of A over posterior draws
+ * f = mu + L^{-T} z_k, k < n_samples (>= 2), where z (n_samples x N
+ * standard normals, caller-drawn) is consumed in elimination order
+ * (ep_ordering); in mixed precision the draws use the FP32 factor.
+ * The factor's pattern holds every cell's corners pairwise (ep_init adds
+ * them), so Sigma is there for every sample point.
+ * Errors: INVALID_ARG (n_samples < 2 with var, non-finite z), NOT_PD, OOM,
+ * DEVICE; STATE only if a cell's Sigma block came out non-finite. */
+int ep_extinction_map(ep_ctx *ctx, int32_t n_samples, const double *z, double *mean, double *var);
+
+/* Joint predictive of the pseudo-density at n_pairs pairs of points
+ * (x, x'), e.g. 10 pc apart (Sec. 5 density maps): xyz2 is n_pairs x 6
+ * (x then x', pc, inside the cube); out5 is n_pairs x 5: E[rho(x)],
+ * E[rho(x')], Var[rho(x)], Var[rho(x')], Cov[rho(x), rho(x')] of the
+ * lognormal pair, from the trilinear field's Gaussian moments.  The two
+ * points' cells (cell index clamp(floor(s/h), 0, n-2) per axis) must be the
+ * same or touch (indices at most 1 apart per axis), which holds for points
+ * up to one grid spacing apart; the factor's pattern then holds Sigma among
+ * all 16 corners.  Errors: INVALID_ARG (a point outside the cube or
+ * non-finite, cells that do not touch), NOT_PD, OOM, DEVICE; STATE only if
+ * a Sigma entry came out non-finite. */
+int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *out5);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,12 @@ struct ep_ctx {
     float* d_mlp_P = nullptr;
     short* d_mlp_bf = nullptr;
     int32_t *d_fb_list = nullptr, *d_fb_count = nullptr;
+    // map prediction (allocated at first use)
+    int32_t *d_iperm = nullptr, *d_mapT = nullptr;
+    double *d_cellS = nullptr, *d_fk = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_mapmean = nullptr;
+    double* d_pts = nullptr;
+    int64_t pts_cap = 0;
+    int* d_mapbad = nullptr;
     bool mlp_loaded = false;
     int64_t fallbacks = 0;
 
@@ -670,7 +676,9 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     }
     OrderingOpts opt;
     opt.leaf_size = c.leaf_size > 0 ? c.leaf_size : 512;
-    opt.sep_halfwidth = ctx->pp.rho * (1.0 + 1e-9);
+    // a separator slab is at least as wide as the longest pattern offset:
+    // the prior stencil reaches 2 rho, the {-2..2}^3 block 2 sqrt(3) h
+    opt.sep_halfwidth = std::max(ctx->pp.rho, std::sqrt(3.0) * g.h) * (1.0 + 1e-9);
     opt.tile = TS;
     opt.panel_tiles = PW;
     int rc = analyse(g, ctx->st, ctx->sup, opt, ctx->sym);
@@ -803,8 +811,8 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     double** varr[] = {&ctx->d_fhat, &ctx->d_borig, &ctx->d_y, &ctx->d_x, &ctx->d_t, &ctx->d_mu, &ctx->d_var};
     for (auto p : varr) TRY(dev_alloc(ctx, p, N));
     launch_fill(ctx->stream, ctx->d_fhat, N, ctx->pp.mean);
-    set_gauss_legendre(ctx->stream);
-    set_gauss_hermite(ctx->stream);
+    HIPCHK(set_gauss_legendre(ctx->stream));
+    HIPCHK(set_gauss_hermite(ctx->stream));
     TRY(dev_alloc(ctx, &ctx->d_mlp_P, MLP_NPARAM));
     TRY(dev_alloc(ctx, &ctx->d_mlp_bf, 2 * 128 * 128));
     TRY(dev_alloc(ctx, &ctx->d_fb_list, S));
@@ -858,14 +866,15 @@ static void enqueue_linearise(ep_ctx* ctx) {
     launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
 }
 
-static void enqueue_assemble(ep_ctx* ctx) {
+static int enqueue_assemble(ep_ctx* ctx) {
     hipStream_t st = ctx->stream;
     launch_fill(st, ctx->d_fronts, ctx->sym.total_elems, 0.0);
     launch_scatter_set(st, ctx->d_fronts, ctx->d_q0_dest, ctx->d_q0_val, ctx->n_q0);
     launch_scatter_const(st, ctx->d_fronts, ctx->d_pad_dest, ctx->n_pad, 1.0);
     launch_assemble_stars(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->max_support);
-    hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st);
+    HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));
     launch_assemble_b(st, ctx->SD, ctx->d_borig);
+    return EP_OK;
 }
 
 // Optional per-launch timing of the MFMA tile kernels (cfg.profile_kernels).
@@ -1039,7 +1048,7 @@ static int run_factor(ep_ctx* ctx, hipEvent_t* ev) {
     if (ev) HIPCHK(hipEventRecord(ev[0], st));
     enqueue_linearise(ctx);
     if (ev) HIPCHK(hipEventRecord(ev[1], st));
-    enqueue_assemble(ctx);
+    TRY(enqueue_assemble(ctx));
     if (ev) HIPCHK(hipEventRecord(ev[2], st));
     enqueue_factor(ctx);
     if (ev) HIPCHK(hipEventRecord(ev[3], st));
@@ -1048,7 +1057,7 @@ static int run_factor(ep_ctx* ctx, hipEvent_t* ev) {
 
 static double ev_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0;
-    hipEventElapsedTime(&ms, a, b);
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
     return ms;
 }
 
@@ -1063,7 +1072,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t* e;
-        ~EvGuard() { for (int i = 0; i < 8; i++) hipEventDestroy(e[i]); }
+        ~EvGuard() { for (int i = 0; i < 8; i++) (void)hipEventDestroy(e[i]); }
     } guard{ev};
     ctx->kt_used = 0;
     TRY(run_factor(ctx, ev));
@@ -1160,6 +1169,81 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
 }
 
 // ---------------------------------------------------------------------------
+// Map prediction: buffers and the posterior they read
+// ---------------------------------------------------------------------------
+static int ensure_maps(ep_ctx* ctx) {
+    if (ctx->d_iperm) return EP_OK;
+    const int64_t N = ctx->g.N();
+    const int n = ctx->g.n;
+    // trapezoid step count of the observer's sightline to every node, by the
+    // same rule as the stars' (0 at the observer)
+    std::vector<int32_t> T(N);
+    for (int64_t p = 0; p < N; p++) {
+        const double x[3] = {(double)(p % n) * ctx->g.h, (double)((p / n) % n) * ctx->g.h,
+                             (double)(p / ((int64_t)n * n)) * ctx->g.h};
+        const double dv[3] = {x[0] - ctx->g.obs[0], x[1] - ctx->g.obs[1], x[2] - ctx->g.obs[2]};
+        const double d = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        if (!(d > 0)) {
+            T[p] = 0;
+            continue;
+        }
+        double tt = std::ceil(d / ctx->g.step);
+        if (tt < 1) tt = 1;
+        T[p] = (int32_t)tt;
+    }
+    TRY(upload(ctx, &ctx->d_mapT, T));
+    TRY(upload(ctx, &ctx->d_iperm, ctx->sym.iperm));
+    const int64_t ncell = (int64_t)(n - 1) * (n - 1) * (n - 1);
+    TRY(dev_alloc(ctx, &ctx->d_cellS, 36 * ncell));
+    for (double** q : {&ctx->d_fk, &ctx->d_s1, &ctx->d_s2, &ctx->d_mapmean}) TRY(dev_alloc(ctx, q, N));
+    TRY(dev_alloc(ctx, &ctx->d_mapbad, 1));
+    return EP_OK;
+}
+
+// mu (node order, d_mu) from the current sites at the current
+// linearisation point; the fronts hold the factor afterwards
+static int maps_factor_and_mean(ep_ctx* ctx) {
+    TRY(run_factor(ctx, nullptr));
+    TRY(run_solve(ctx));
+    return EP_OK;
+}
+
+// x = L^{-T} z for z in elimination order (in d_y), into out (node order):
+// the backward half of the triangular solve
+static void enqueue_bwd_only(ep_ctx* ctx, double* out) {
+    hipStream_t st = ctx->stream;
+    for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
+        auto& P = ctx->levels[l];
+        Bufs b = level_bufs(ctx, l);
+        launch_bwd_t(st, ctx->d_batches + P.bwd_t.be_off, P.bwd_t.nbe, P.bwd_t.ntasks, ctx->F, b, ctx->d_y, ctx->d_x,
+                     ctx->d_t);
+        launch_bwd_x(st, ctx->d_batches + P.bwd_x.be_off, P.bwd_x.nbe, P.bwd_x.ntasks, ctx->F, b, ctx->d_t,
+                     ctx->d_x);
+    }
+    launch_scatter_perm(st, ctx->d_perm, ctx->d_x, out, ctx->g.N());
+}
+
+// Sigma on the fronts (selected inversion of the current factor), then the
+// packed Sigma blocks of every cell's corners; STATE if an entry is
+// non-finite (an off-pattern pair reads as NaN, which the pattern's
+// {-2..2}^3 block rules out)
+static int maps_sigma(ep_ctx* ctx, bool cells) {
+    enqueue_selinv(ctx);
+    if (!cells) return EP_OK;
+    HIPCHK(hipMemsetAsync(ctx->d_mapbad, 0, sizeof(int), ctx->stream));
+    launch_cell_sigma(ctx->stream, ctx->GD, ctx->F, ctx->d_fronts, ctx->d_iperm, ctx->d_snode, ctx->d_cellS,
+                      ctx->d_mapbad);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->d_mapbad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (bad) {
+        ctx->err = "non-finite Sigma in a cell's corner block";
+        return EP_ERR_STATE;
+    }
+    return EP_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1195,10 +1279,10 @@ void ep_config_default(ep_config* c) {
 
 void ep_free(ep_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (void* p : ctx->allocs) (void)hipFree(p);
     for (hipEvent_t e : ctx->kt_ev) (void)hipEventDestroy(e);
-    if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
@@ -1257,6 +1341,118 @@ int ep_marginal_var(ep_ctx* ctx, double* out) {
 }
 
 const char* ep_last_error(const ep_ctx* ctx) { return ctx ? ctx->err.c_str() : g_tls_err.c_str(); }
+
+int ep_ordering(const ep_ctx* ctx, int32_t* perm) {
+    if (!ctx || !perm) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    std::copy(ctx->sym.perm.begin(), ctx->sym.perm.end(), perm);
+    return EP_OK;
+}
+
+int ep_density_moments(ep_ctx* ctx, double* mean, double* var) {
+    if (!ctx || !mean || !var) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(maps_factor_and_mean(ctx));
+    enqueue_selinv(ctx);
+    launch_diag(ctx->stream, ctx->d_perm, ctx->d_snode, ctx->F, ctx->d_fronts, ctx->d_var, ctx->g.N());
+    const int64_t N = ctx->g.N();
+    // the two outputs go through d_x and d_t
+    launch_density(ctx->stream, ctx->d_mu, ctx->d_var, ctx->d_x, ctx->d_t, N);
+    HIPCHK(hipMemcpyAsync(mean, ctx->d_x, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    return EP_OK;
+}
+
+int ep_extinction_map(ep_ctx* ctx, int32_t n_samples, const double* z, double* mean, double* var) {
+    if (!ctx || !mean || n_samples < 0 || (var && (n_samples < 2 || !z))) {
+        g_tls_err = "ep_extinction_map: bad arguments";
+        if (ctx) ctx->err = g_tls_err;
+        return EP_ERR_INVALID_ARG;
+    }
+    const int64_t N = ctx->g.N();
+    if (z)
+        for (int64_t i = 0; i < (int64_t)n_samples * N; i++)
+            if (!std::isfinite(z[i])) {
+                ctx->err = "ep_extinction_map: z must be finite";
+                return EP_ERR_INVALID_ARG;
+            }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(ensure_maps(ctx));
+    TRY(maps_factor_and_mean(ctx));
+    // Posterior draws f = mu + L^{-T} z need the factor, so they come before
+    // the selected inversion overwrites it with Sigma.  Their A are summed as
+    // deviations from a centre, A at f = mu (the shifted sums give the
+    // sample variance exactly for any centre, with less cancellation).
+    const bool sample = var != nullptr;
+    if (sample) {
+        launch_ext_plugin(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_mu, ctx->d_mapmean, N);
+        launch_fill(ctx->stream, ctx->d_s1, N, 0.0);
+        launch_fill(ctx->stream, ctx->d_s2, N, 0.0);
+        for (int k = 0; k < n_samples; k++) {
+            HIPCHK(hipMemcpyAsync(ctx->d_y, z + (int64_t)k * N, sizeof(double) * N, hipMemcpyHostToDevice,
+                                  ctx->stream));
+            enqueue_bwd_only(ctx, ctx->d_fk);
+            launch_sum2(ctx->stream, ctx->d_fk, ctx->d_mu, ctx->d_fk, N);
+            launch_ext_sample(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_fk, ctx->d_mapmean, ctx->d_s1, ctx->d_s2, N);
+        }
+        launch_sample_var(ctx->stream, ctx->d_s1, ctx->d_s2, ctx->d_t, n_samples, N);
+        HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    TRY(maps_sigma(ctx, true));
+    launch_ext_mean(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_mu, ctx->d_cellS, ctx->d_mapmean, N);
+    HIPCHK(hipMemcpyAsync(mean, ctx->d_mapmean, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    return EP_OK;
+}
+
+int ep_point_predict(ep_ctx* ctx, int64_t n_pairs, const double* xyz2, double* out5) {
+    if (!ctx || n_pairs < 0 || (n_pairs > 0 && (!xyz2 || !out5))) {
+        g_tls_err = "ep_point_predict: bad arguments";
+        if (ctx) ctx->err = g_tls_err;
+        return EP_ERR_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < 6 * n_pairs; i++)
+        if (!std::isfinite(xyz2[i]) || xyz2[i] < 0 || xyz2[i] > ctx->g.L) {
+            ctx->err = "ep_point_predict: points must lie in the cube";
+            return EP_ERR_INVALID_ARG;
+        }
+    // the two cells must touch (the forward model's cell rule), which keeps
+    // all 16 corners pairwise on the factor's pattern
+    for (int64_t i = 0; i < n_pairs; i++)
+        for (int a = 0; a < 3; a++) {
+            auto cell = [&](double s) { return std::min<double>(std::max<double>(std::floor(s / ctx->g.h), 0), ctx->g.n - 2); };
+            if (std::fabs(cell(xyz2[6 * i + a]) - cell(xyz2[6 * i + 3 + a])) > 1) {
+                ctx->err = "ep_point_predict: the two points of a pair must lie in the same or touching cells";
+                return EP_ERR_INVALID_ARG;
+            }
+        }
+    if (n_pairs == 0) return EP_OK;
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(ensure_maps(ctx));
+    if (ctx->pts_cap < n_pairs) {
+        TRY(dev_alloc(ctx, &ctx->d_pts, 11 * n_pairs));
+        ctx->pts_cap = n_pairs;
+    }
+    TRY(maps_factor_and_mean(ctx));
+    TRY(maps_sigma(ctx, false));
+    HIPCHK(hipMemcpyAsync(ctx->d_pts, xyz2, sizeof(double) * 6 * n_pairs, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_mapbad, 0, sizeof(int), ctx->stream));
+    launch_point_pred(ctx->stream, ctx->GD, ctx->F, ctx->d_fronts, ctx->d_iperm, ctx->d_snode, ctx->d_mu, ctx->d_pts,
+                      ctx->d_pts + 6 * n_pairs, n_pairs, ctx->d_mapbad);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(out5, ctx->d_pts + 6 * n_pairs, sizeof(double) * 5 * n_pairs, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(&bad, ctx->d_mapbad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    if (bad) {
+        ctx->err = "non-finite Sigma among the corners of a pair of points";
+        return EP_ERR_STATE;
+    }
+    return EP_OK;
+}
 
 int ep_get_sites(ep_ctx* ctx, double* tau, double* nu) {
     if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
@@ -1364,29 +1560,37 @@ int ep_tilted_moments(int32_t mode, int64_t n, const double* mu_c, const double*
         g_tls_err = "stream creation failed";
         return EP_ERR_DEVICE;
     }
-    set_gauss_legendre(st);
+    if (set_gauss_legendre(st) != hipSuccess) {
+        g_tls_err = "quadrature table upload failed";
+        (void)hipStreamDestroy(st);
+        return EP_ERR_DEVICE;
+    }
     double* d = nullptr;
     const size_t b = sizeof(double) * n;
     int rc = EP_OK;
     if (hipMalloc((void**)&d, 7 * b) != hipSuccess) {
         g_tls_err = "device allocation failed";
-        hipStreamDestroy(st);
+        (void)hipStreamDestroy(st);
         return EP_ERR_OOM;
     }
-    hipMemcpyAsync(d, mu_c, b, hipMemcpyHostToDevice, st);
-    hipMemcpyAsync(d + n, v_c, b, hipMemcpyHostToDevice, st);
-    hipMemcpyAsync(d + 2 * n, A, b, hipMemcpyHostToDevice, st);
-    hipMemcpyAsync(d + 3 * n, sigma, b, hipMemcpyHostToDevice, st);
-    launch_tilted_batch(st, mode, n, d, d + n, d + 2 * n, d + 3 * n, d + 4 * n, d + 5 * n, d + 6 * n);
-    hipMemcpyAsync(lnZ, d + 4 * n, b, hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(mean, d + 5 * n, b, hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(var, d + 6 * n, b, hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+    hipError_t e = hipSuccess;
+    auto keep = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    keep(hipMemcpyAsync(d, mu_c, b, hipMemcpyHostToDevice, st));
+    keep(hipMemcpyAsync(d + n, v_c, b, hipMemcpyHostToDevice, st));
+    keep(hipMemcpyAsync(d + 2 * n, A, b, hipMemcpyHostToDevice, st));
+    keep(hipMemcpyAsync(d + 3 * n, sigma, b, hipMemcpyHostToDevice, st));
+    if (e == hipSuccess) launch_tilted_batch(st, mode, n, d, d + n, d + 2 * n, d + 3 * n, d + 4 * n, d + 5 * n, d + 6 * n);
+    keep(hipMemcpyAsync(lnZ, d + 4 * n, b, hipMemcpyDeviceToHost, st));
+    keep(hipMemcpyAsync(mean, d + 5 * n, b, hipMemcpyDeviceToHost, st));
+    keep(hipMemcpyAsync(var, d + 6 * n, b, hipMemcpyDeviceToHost, st));
+    keep(hipStreamSynchronize(st));
+    keep(hipGetLastError());
+    if (e != hipSuccess) {
         g_tls_err = "tilted-moment kernel failed";
         rc = EP_ERR_DEVICE;
     }
-    hipFree(d);
-    hipStreamDestroy(st);
+    (void)hipFree(d);
+    (void)hipStreamDestroy(st);
     return rc;
 }
 

@@ -149,7 +149,7 @@ struct EpParams {
 void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p, const int32_t* list = nullptr, int64_t nlist = 0);
 void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
                          const double* sig, double* lnZ, double* mean, double* var);
-void set_gauss_legendre(hipStream_t st);
+hipError_t set_gauss_legendre(hipStream_t st);
 
 // mixed precision factor (FP32 storage and MFMA, FP64 diagonal pivots)
 void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
@@ -163,5 +163,21 @@ void launch_residual(hipStream_t st, int64_t N, const int64_t* rp, const int32_t
                      const double* d, StarsDev s, const double* b, const double* x, double* u, double* w, double* r);
 void launch_add(hipStream_t st, int64_t n, double* x, const double* dx);
 void launch_maxabs_diff(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
+
+// Map prediction (maps.hip).  S: (n-1)^3 cells x 36 packed Sigma entries of
+// the cell's 8 corners.  T: per node, the trapezoid step count of the
+// observer's sightline to it (0 for the observer's own node).
+void launch_cell_sigma(hipStream_t st, GridDev g, FrontsDev F, const double* fronts, const int32_t* iperm,
+                       const int32_t* snode, double* S, int* bad);
+void launch_ext_mean(hipStream_t st, GridDev g, const int32_t* T, const double* mu, const double* S, double* mean,
+                     int64_t N);
+void launch_ext_sample(hipStream_t st, GridDev g, const int32_t* T, const double* f, const double* mean, double* s1,
+                       double* s2, int64_t N);
+void launch_ext_plugin(hipStream_t st, GridDev g, const int32_t* T, const double* f, double* centre, int64_t N);
+void launch_sum2(hipStream_t st, const double* a, const double* b, double* out, int64_t n);
+void launch_sample_var(hipStream_t st, const double* s1, const double* s2, double* var, int K, int64_t n);
+void launch_density(hipStream_t st, const double* mu, const double* var, double* m, double* v, int64_t n);
+void launch_point_pred(hipStream_t st, GridDev g, FrontsDev F, const double* fronts, const int32_t* iperm,
+                       const int32_t* snode, const double* mu, const double* xyz2, double* out, int64_t np, int* bad);
 
 }  // namespace ep

@@ -1308,7 +1308,7 @@ void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, 
 // cos(pi (i + 3/4) / (n + 1/2)) (the standard construction, e.g. Press et
 // al., Numerical Recipes, Sec. 4.5); computed on the host, copied to
 // constant memory.
-void set_gauss_legendre(hipStream_t st) {
+hipError_t set_gauss_legendre(hipStream_t st) {
     const int n = 16;
     double x[16], wgt[16];
     for (int i = 0; i < n; i++) {
@@ -1338,9 +1338,10 @@ void set_gauss_legendre(hipStream_t st) {
         x[i] = z;
         wgt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
-    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, st);
-    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), wgt, sizeof(wgt), 0, hipMemcpyHostToDevice, st);
-    hipStreamSynchronize(st);
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), wgt, sizeof(wgt), 0, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
 }
 
 // ===========================================================================

@@ -21,7 +21,7 @@ void mlp_fwd_bwd(hipStream_t st, const MlpWork& w, int B, const int32_t* idx, co
 void mlp_zero(hipStream_t st, float* p, int64_t n);
 void mlp_adam(hipStream_t st, float* P, const float* G, float* m, float* v, float lr, int step);
 void mlp_make_bf16(hipStream_t st, const float* P, short* Wbf);
-void set_gauss_hermite(hipStream_t st);
+hipError_t set_gauss_hermite(hipStream_t st);
 // gated surrogate moments for every star; stars whose check fails are
 // appended to fb_list.  With s.status == nullptr it only evaluates
 // (out3 / errest / accepted may be null).

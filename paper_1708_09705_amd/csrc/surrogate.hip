@@ -545,13 +545,14 @@ static void gauss_hermite_rule(int n, double* out) {
     }
 }
 
-void set_gauss_hermite(hipStream_t st) {
+hipError_t set_gauss_hermite(hipStream_t st) {
     double r1[2 * NGH1], r2[2 * NGH2];
     gauss_hermite_rule(NGH1, r1);
     gauss_hermite_rule(NGH2, r2);
-    (void)hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gh1), r1, sizeof(r1), 0, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gh2), r2, sizeof(r2), 0, hipMemcpyHostToDevice, st);
-    (void)hipStreamSynchronize(st);
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gh1), r1, sizeof(r1), 0, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gh2), r2, sizeof(r2), 0, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
 }
 
 }  // namespace ep

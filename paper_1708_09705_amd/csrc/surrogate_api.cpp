@@ -256,7 +256,7 @@ int ep_mlp_predict(const float* weights, int64_t n, const double* inputs, double
         hipStream_t s;
         ~SG() { (void)hipStreamDestroy(s); }
     } sg{st};
-    set_gauss_hermite(st);
+    if (set_gauss_hermite(st) != hipSuccess) { set_last_error("quadrature table upload failed"); return EP_ERR_DEVICE; }
     std::vector<double> mu(n), v(n), A(n), s(n), zero(n, 0.0);
     for (int64_t i = 0; i < n; i++) {
         mu[i] = inputs[4 * i];

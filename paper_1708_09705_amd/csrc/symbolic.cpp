@@ -130,6 +130,15 @@ void build_stencil(const GridGeom& g, double rho, Stencil& st) {
             seen[key] = 1;
             st.full.push_back(di); st.full.push_back(dj); st.full.push_back(dk);
         }
+    st.pattern = st.full;
+    for (int dk = -2; dk <= 2; dk++)
+        for (int dj = -2; dj <= 2; dj++)
+            for (int di = -2; di <= 2; di++) {   // R >= 1, so the block lies inside seen's range
+                size_t key = ((size_t)(dk + 2 * R) * W + (dj + 2 * R)) * W + (di + 2 * R);
+                if (seen[key]) continue;
+                seen[key] = 1;
+                st.pattern.push_back(di); st.pattern.push_back(dj); st.pattern.push_back(dk);
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,8 +345,8 @@ int analyse(const GridGeom& g, const Stencil& st, const Supports& sup, const Ord
         for (int32_t k = 0; k < F.nv; k++) {
             int32_t p = sym.perm[F.first + k];
             int i = p % n, j = (p / n) % n, l = p / (n * n);
-            for (size_t o = 0; o < st.full.size(); o += 3) {
-                int ii = i + st.full[o], jj = j + st.full[o + 1], ll = l + st.full[o + 2];
+            for (size_t o = 0; o < st.pattern.size(); o += 3) {
+                int ii = i + st.pattern[o], jj = j + st.pattern[o + 1], ll = l + st.pattern[o + 2];
                 if (ii < 0 || jj < 0 || ll < 0 || ii >= n || jj >= n || ll >= n) continue;
                 add(sym.iperm[ii + (int64_t)n * (jj + (int64_t)n * ll)]);
             }

@@ -34,6 +34,10 @@ struct Stencil {
     int R = 0;                           // max |offset| per axis of H
     std::vector<int> half;               // H as packed (di, dj, dk) triples, q - p < 0 lexicographically
     std::vector<int> full;               // all offsets of Q0 (including 0), packed triples
+    // offsets of the factor's pattern: full plus the block {-2..2}^3, so that
+    // the 8 corners of every cell, and the 16 corners of any two cells that
+    // touch, are pairwise on the pattern (the map predictions read Sigma there)
+    std::vector<int> pattern;
 };
 void build_stencil(const GridGeom& g, double rho, Stencil& st);
 

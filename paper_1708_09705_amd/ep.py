@@ -79,7 +79,8 @@ class ep_structure_stats(ctypes.Structure):
 EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_free",
            "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
-           "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load")
+           "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
+           "ep_extinction_map", "ep_point_predict")
 MLP_NPARAM = 34065
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
@@ -124,10 +125,15 @@ def load(path: str | None = None):
     L.ep_mlp_predict.argtypes = [vp, i64, vp, ctypes.c_double, vp, vp, vp, i32]
     L.ep_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, i32]
     L.ep_mlp_load.argtypes = [vp, vp]
+    L.ep_ordering.argtypes = [vp, vp]
+    L.ep_density_moments.argtypes = [vp, vp, vp]
+    L.ep_extinction_map.argtypes = [vp, i32, vp, vp, vp]
+    L.ep_point_predict.argtypes = [vp, i64, vp, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
-                 "ep_mlp_loss_grad", "ep_mlp_load"):
+                 "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
+                 "ep_point_predict"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -333,6 +339,35 @@ class EP:
         if w.size != MLP_NPARAM:
             raise ValueError(f"expected {MLP_NPARAM} weights")
         _check(self.L, self.L.ep_mlp_load(self.ctx, _ptr(w)), self.ctx)
+
+    def ordering(self) -> np.ndarray:
+        perm = np.empty(self.N, dtype=np.int32)
+        _check(self.L, self.L.ep_ordering(self.ctx, _ptr(perm)), self.ctx)
+        return perm
+
+    def density_moments(self):
+        m, v = np.empty(self.N), np.empty(self.N)
+        _check(self.L, self.L.ep_density_moments(self.ctx, _ptr(m), _ptr(v)), self.ctx)
+        return m, v
+
+    def extinction_map(self, z=None):
+        """Exact posterior mean of A to every node; with z (K x N standard
+        normals, K >= 2, consumed in elimination order) also the sample
+        variance over the K posterior draws."""
+        mean = np.empty(self.N)
+        if z is None:
+            _check(self.L, self.L.ep_extinction_map(self.ctx, 0, None, _ptr(mean), None), self.ctx)
+            return mean
+        zz = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, self.N)
+        var = np.empty(self.N)
+        _check(self.L, self.L.ep_extinction_map(self.ctx, zz.shape[0], _ptr(zz), _ptr(mean), _ptr(var)), self.ctx)
+        return mean, var
+
+    def point_predict(self, xyz2) -> np.ndarray:
+        x = np.ascontiguousarray(xyz2, dtype=np.float64).reshape(-1, 6)
+        out = np.empty((x.shape[0], 5))
+        _check(self.L, self.L.ep_point_predict(self.ctx, x.shape[0], _ptr(x), _ptr(out)), self.ctx)
+        return out
 
     def structure(self) -> dict:
         st = ep_structure_stats()
