@@ -27,8 +27,9 @@
  *  - Every call returns an ep_status (0 = success).  On failure
  *    ep_last_error(ctx) (or ep_last_error(NULL) for failures without a
  *    context) holds a message.
- *  - Host pointers unless stated otherwise.  The library copies every input
- *    it keeps; the caller owns every buffer it passes.
+ *  - Host pointers, or device pointers on cfg.device for ep_init and every
+ *    call on a context when cfg.pointers_on_device = 1.  The library copies
+ *    every input it keeps; the caller owns every buffer it passes.
  *  - Grid node p = i + n (j + n k) sits at h (i, j, k), h = box/(n-1).
  *  - Work runs on the context's HIP stream; calls return after completion.
  *    A context is not thread-safe; distinct contexts are independent.
@@ -91,6 +92,15 @@ typedef struct ep_config {
                                   dissection tree in FP64 (0 = all levels FP32) */
     double surrogate_tol;      /* surrogate moments: accept a star when the network's
                                   moments and the Gauss-Hermite check agree to this */
+    int32_t pointers_on_device; /* 0: the array arguments of ep_init and of every call
+                                   on a context are host memory; 1: they are device
+                                   memory on `device` (e.g. torch tensors), written and
+                                   read before the call returns.  Arrays that need
+                                   checks or host-side work (star inputs, sites, the
+                                   linearisation point, z, point pairs, weights) are
+                                   copied to the host first.  Context-free calls
+                                   (ep_tilted_moments, ep_simulate, ep_mlp_*) always
+                                   take host memory. */
 } ep_config;
 
 /* Kinds of timed MFMA tile-kernel launches (ep_sweep_stats.kernel_ms):
@@ -273,7 +283,8 @@ int ep_structure(const ep_ctx *ctx, ep_structure_stats *out);
  * of the pseudo-density rho kappa = e^f) ----
  * Each call, like ep_posterior_mean, recomputes q(f) = N(mu, Sigma) from the
  * current sites at the current linearisation point and changes no state.
- * Outputs are host arrays owned by the caller, in node order. */
+ * Outputs are arrays owned by the caller (host, or device memory with
+ * pointers_on_device), in node order. */
 
 /* The elimination order: perm[i] is the grid node eliminated i-th (N int32). */
 int ep_ordering(const ep_ctx *ctx, int32_t *perm);

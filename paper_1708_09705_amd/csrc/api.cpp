@@ -603,6 +603,7 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
         return EP_ERR_INVALID_ARG;
     }
     if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED) { err = "unknown precision"; return EP_ERR_INVALID_ARG; }
+    if (c->pointers_on_device != 0 && c->pointers_on_device != 1) { err = "pointers_on_device must be 0 or 1"; return EP_ERR_INVALID_ARG; }
     if (c->mixed_fp64_levels < 0) { err = "mixed_fp64_levels must be >= 0"; return EP_ERR_INVALID_ARG; }
     if (c->moments != EP_MOM_QUADRATURE && c->moments != EP_MOM_SURROGATE) { err = "unknown moments mode"; return EP_ERR_INVALID_ARG; }
     if (c->moments == EP_MOM_SURROGATE && !(c->surrogate_tol > 0)) { err = "surrogate_tol must be > 0"; return EP_ERR_INVALID_ARG; }
@@ -1244,6 +1245,24 @@ static int maps_sigma(ep_ctx* ctx, bool cells) {
 }
 
 // ---------------------------------------------------------------------------
+// Caller arrays: host memory, or device memory on cfg.device when
+// cfg.pointers_on_device = 1.
+// ---------------------------------------------------------------------------
+static hipMemcpyKind kind_out(const ep_ctx* c) {
+    return c->cfg.pointers_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+// The caller's array as host memory (itself, or a copy staged in buf) for
+// the checks and host-side work that read it.
+template <class T>
+static hipError_t host_view(bool on_device, const T*& p, int64_t n, std::vector<T>& buf) {
+    if (!on_device || !p || n <= 0) return hipSuccess;
+    buf.resize((size_t)n);
+    hipError_t e = hipMemcpy(buf.data(), p, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost);
+    p = buf.data();
+    return e;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1291,6 +1310,14 @@ int ep_init(const ep_config* cfg, int64_t n_stars, const double* xyz, const doub
     if (!out) { g_tls_err = "out is NULL"; return EP_ERR_INVALID_ARG; }
     *out = nullptr;
     std::string err;
+    std::vector<double> hx, ha, hs;
+    if (cfg && cfg->pointers_on_device == 1 && n_stars > 0) {
+        if (hipSetDevice(cfg->device) != hipSuccess || host_view(true, xyz, 3 * n_stars, hx) != hipSuccess ||
+            host_view(true, A_obs, n_stars, ha) != hipSuccess || host_view(true, sigma, n_stars, hs) != hipSuccess) {
+            g_tls_err = "copying the star arrays from the device failed";
+            return EP_ERR_DEVICE;
+        }
+    }
     int rc = validate(cfg, n_stars, xyz, A_obs, sigma, err);
     if (rc) { g_tls_err = err; return rc; }
     ep_ctx* ctx = new ep_ctx();
@@ -1322,7 +1349,7 @@ int ep_posterior_mean(ep_ctx* ctx, double* out) {
     HIPCHK(hipSetDevice(ctx->cfg.device));
     TRY(run_factor(ctx, nullptr));
     TRY(run_solve(ctx));
-    HIPCHK(hipMemcpyAsync(out, ctx->d_mu, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, ctx->d_mu, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     return EP_OK;
@@ -1334,7 +1361,7 @@ int ep_marginal_var(ep_ctx* ctx, double* out) {
     TRY(run_factor(ctx, nullptr));
     enqueue_selinv(ctx);
     launch_diag(ctx->stream, ctx->d_perm, ctx->d_snode, ctx->F, ctx->d_fronts, ctx->d_var, ctx->g.N());
-    HIPCHK(hipMemcpyAsync(out, ctx->d_var, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, ctx->d_var, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     return EP_OK;
@@ -1344,7 +1371,16 @@ const char* ep_last_error(const ep_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 
 int ep_ordering(const ep_ctx* ctx, int32_t* perm) {
     if (!ctx || !perm) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
-    std::copy(ctx->sym.perm.begin(), ctx->sym.perm.end(), perm);
+    if (ctx->cfg.pointers_on_device) {
+        if (hipSetDevice(ctx->cfg.device) != hipSuccess ||
+            hipMemcpy(perm, ctx->sym.perm.data(), sizeof(int32_t) * ctx->sym.perm.size(), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            g_tls_err = "copying the ordering to the device failed";
+            return EP_ERR_DEVICE;
+        }
+    } else {
+        std::copy(ctx->sym.perm.begin(), ctx->sym.perm.end(), perm);
+    }
     return EP_OK;
 }
 
@@ -1357,8 +1393,8 @@ int ep_density_moments(ep_ctx* ctx, double* mean, double* var) {
     const int64_t N = ctx->g.N();
     // the two outputs go through d_x and d_t
     launch_density(ctx->stream, ctx->d_mu, ctx->d_var, ctx->d_x, ctx->d_t, N);
-    HIPCHK(hipMemcpyAsync(mean, ctx->d_x, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(mean, ctx->d_x, sizeof(double) * N, kind_out(ctx), ctx->stream));
+    HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     return EP_OK;
@@ -1371,7 +1407,10 @@ int ep_extinction_map(ep_ctx* ctx, int32_t n_samples, const double* z, double* m
         return EP_ERR_INVALID_ARG;
     }
     const int64_t N = ctx->g.N();
-    if (z)
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<double> hz;
+    if (var) HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, z, (int64_t)n_samples * N, hz));
+    if (z && var)
         for (int64_t i = 0; i < (int64_t)n_samples * N; i++)
             if (!std::isfinite(z[i])) {
                 ctx->err = "ep_extinction_map: z must be finite";
@@ -1391,17 +1430,17 @@ int ep_extinction_map(ep_ctx* ctx, int32_t n_samples, const double* z, double* m
         launch_fill(ctx->stream, ctx->d_s2, N, 0.0);
         for (int k = 0; k < n_samples; k++) {
             HIPCHK(hipMemcpyAsync(ctx->d_y, z + (int64_t)k * N, sizeof(double) * N, hipMemcpyHostToDevice,
-                                  ctx->stream));
+                                  ctx->stream));   // z is host memory here (staged if need be)
             enqueue_bwd_only(ctx, ctx->d_fk);
             launch_sum2(ctx->stream, ctx->d_fk, ctx->d_mu, ctx->d_fk, N);
             launch_ext_sample(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_fk, ctx->d_mapmean, ctx->d_s1, ctx->d_s2, N);
         }
         launch_sample_var(ctx->stream, ctx->d_s1, ctx->d_s2, ctx->d_t, n_samples, N);
-        HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, kind_out(ctx), ctx->stream));
     }
     TRY(maps_sigma(ctx, true));
     launch_ext_mean(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_mu, ctx->d_cellS, ctx->d_mapmean, N);
-    HIPCHK(hipMemcpyAsync(mean, ctx->d_mapmean, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(mean, ctx->d_mapmean, sizeof(double) * N, kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     return EP_OK;
@@ -1413,6 +1452,9 @@ int ep_point_predict(ep_ctx* ctx, int64_t n_pairs, const double* xyz2, double* o
         if (ctx) ctx->err = g_tls_err;
         return EP_ERR_INVALID_ARG;
     }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<double> hp;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, xyz2, 6 * n_pairs, hp));
     for (int64_t i = 0; i < 6 * n_pairs; i++)
         if (!std::isfinite(xyz2[i]) || xyz2[i] < 0 || xyz2[i] > ctx->g.L) {
             ctx->err = "ep_point_predict: points must lie in the cube";
@@ -1438,11 +1480,12 @@ int ep_point_predict(ep_ctx* ctx, int64_t n_pairs, const double* xyz2, double* o
     TRY(maps_factor_and_mean(ctx));
     TRY(maps_sigma(ctx, false));
     HIPCHK(hipMemcpyAsync(ctx->d_pts, xyz2, sizeof(double) * 6 * n_pairs, hipMemcpyHostToDevice, ctx->stream));
+    // (xyz2 is host memory here, staged if need be)
     HIPCHK(hipMemsetAsync(ctx->d_mapbad, 0, sizeof(int), ctx->stream));
     launch_point_pred(ctx->stream, ctx->GD, ctx->F, ctx->d_fronts, ctx->d_iperm, ctx->d_snode, ctx->d_mu, ctx->d_pts,
                       ctx->d_pts + 6 * n_pairs, n_pairs, ctx->d_mapbad);
     int bad = 0;
-    HIPCHK(hipMemcpyAsync(out5, ctx->d_pts + 6 * n_pairs, sizeof(double) * 5 * n_pairs, hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(out5, ctx->d_pts + 6 * n_pairs, sizeof(double) * 5 * n_pairs, kind_out(ctx),
                           ctx->stream));
     HIPCHK(hipMemcpyAsync(&bad, ctx->d_mapbad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1456,14 +1499,19 @@ int ep_point_predict(ep_ctx* ctx, int64_t n_pairs, const double* xyz2, double* o
 
 int ep_get_sites(ep_ctx* ctx, double* tau, double* nu) {
     if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
-    if (tau) HIPCHK(hipMemcpyAsync(tau, ctx->d_tau, sizeof(double) * ctx->S, hipMemcpyDeviceToHost, ctx->stream));
-    if (nu) HIPCHK(hipMemcpyAsync(nu, ctx->d_nu, sizeof(double) * ctx->S, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    if (tau) HIPCHK(hipMemcpyAsync(tau, ctx->d_tau, sizeof(double) * ctx->S, kind_out(ctx), ctx->stream));
+    if (nu) HIPCHK(hipMemcpyAsync(nu, ctx->d_nu, sizeof(double) * ctx->S, kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return EP_OK;
 }
 
 int ep_set_sites(ep_ctx* ctx, const double* tau, const double* nu) {
     if (!ctx || !tau || !nu) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<double> ht, hn;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, tau, ctx->S, ht));
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, nu, ctx->S, hn));
     for (int64_t s = 0; s < ctx->S; s++)
         if (!std::isfinite(tau[s]) || !std::isfinite(nu[s])) {
             ctx->err = "sites must be finite";
@@ -1477,13 +1525,17 @@ int ep_set_sites(ep_ctx* ctx, const double* tau, const double* nu) {
 
 int ep_get_linpoint(ep_ctx* ctx, double* f) {
     if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
-    HIPCHK(hipMemcpyAsync(f, ctx->d_fhat, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    HIPCHK(hipMemcpyAsync(f, ctx->d_fhat, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return EP_OK;
 }
 
 int ep_set_linpoint(ep_ctx* ctx, const double* f) {
     if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<double> hf;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, f, ctx->g.N(), hf));
     for (int64_t i = 0; i < ctx->g.N(); i++)
         if (!std::isfinite(f[i])) { ctx->err = "linearisation point must be finite"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipMemcpyAsync(ctx->d_fhat, f, sizeof(double) * ctx->g.N(), hipMemcpyHostToDevice, ctx->stream));
@@ -1496,18 +1548,23 @@ int ep_star_state(ep_ctx* ctx, double* lnA, double* cav_mu, double* cav_var, dou
     if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
     const size_t b = sizeof(double) * ctx->S;
     hipStream_t st = ctx->stream;
-    if (lnA) HIPCHK(hipMemcpyAsync(lnA, ctx->d_lnA, b, hipMemcpyDeviceToHost, st));
-    if (cav_mu) HIPCHK(hipMemcpyAsync(cav_mu, ctx->d_cmu, b, hipMemcpyDeviceToHost, st));
-    if (cav_var) HIPCHK(hipMemcpyAsync(cav_var, ctx->d_cvar, b, hipMemcpyDeviceToHost, st));
-    if (lnZ) HIPCHK(hipMemcpyAsync(lnZ, ctx->d_lnZ, b, hipMemcpyDeviceToHost, st));
-    if (tmean) HIPCHK(hipMemcpyAsync(tmean, ctx->d_tmean, b, hipMemcpyDeviceToHost, st));
-    if (tvar) HIPCHK(hipMemcpyAsync(tvar, ctx->d_tvar, b, hipMemcpyDeviceToHost, st));
+    const hipMemcpyKind k = kind_out(ctx);
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    if (lnA) HIPCHK(hipMemcpyAsync(lnA, ctx->d_lnA, b, k, st));
+    if (cav_mu) HIPCHK(hipMemcpyAsync(cav_mu, ctx->d_cmu, b, k, st));
+    if (cav_var) HIPCHK(hipMemcpyAsync(cav_var, ctx->d_cvar, b, k, st));
+    if (lnZ) HIPCHK(hipMemcpyAsync(lnZ, ctx->d_lnZ, b, k, st));
+    if (tmean) HIPCHK(hipMemcpyAsync(tmean, ctx->d_tmean, b, k, st));
+    if (tvar) HIPCHK(hipMemcpyAsync(tvar, ctx->d_tvar, b, k, st));
     HIPCHK(hipStreamSynchronize(st));
     return EP_OK;
 }
 
 int ep_mlp_load(ep_ctx* ctx, const float* weights) {
     if (!ctx || !weights) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<float> hw;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, weights, MLP_NPARAM, hw));
     for (int i = 0; i < MLP_NPARAM; i++)
         if (!std::isfinite(weights[i])) { ctx->err = "network weights must be finite"; return EP_ERR_INVALID_ARG; }
     for (int k = 0; k < 7; k++)

@@ -55,6 +55,7 @@ class ep_config(ctypes.Structure):
         ("profile_kernels", ctypes.c_int32),
         ("mixed_fp64_levels", ctypes.c_int32),
         ("surrogate_tol", ctypes.c_double),
+        ("pointers_on_device", ctypes.c_int32),
     ]
 
 
@@ -90,6 +91,17 @@ class ep_mlp_hyper(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 _lib = None
+
+
+class _TorchDtypes(dict):
+    def __missing__(self, k):
+        import torch
+        v = {np.float64: torch.float64, np.float32: torch.float32, np.int32: torch.int32}[k]
+        self[k] = v
+        return v
+
+
+_TORCH = _TorchDtypes()
 
 
 def load(path: str | None = None):
@@ -179,6 +191,34 @@ def make_config(fields: Mapping | None = None, lib=None, **kw) -> ep_config:
     return c
 
 
+def _marshal_in(a, n, on_device: bool, device: int, dtype=np.float64):
+    """(object to keep alive, pointer) for an input array: a contiguous host
+    copy, or with on_device a tensor on cuda:device (pointers_on_device)."""
+    if not on_device:
+        a = np.ascontiguousarray(a, dtype=dtype)
+        if n is not None and a.size != n:
+            raise ValueError(f"expected {n} values, got {a.size}")
+        return a, _ptr(a)
+    import torch
+    t = torch.as_tensor(a, device=f"cuda:{device}").to(_TORCH[dtype]).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    torch.cuda.current_stream(t.device).synchronize()   # the library's stream does not wait for torch's
+    return t, ctypes.c_void_p(t.data_ptr())
+
+
+def _marshal_out(shape, on_device: bool, device: int, dtype=np.float64):
+    """(array, pointer) for an output: numpy on the host, or a tensor on
+    cuda:device (pointers_on_device)."""
+    if not on_device:
+        a = np.empty(shape, dtype=dtype)
+        return a, _ptr(a)
+    import torch
+    t = torch.empty(shape, dtype=_TORCH[dtype], device=f"cuda:{device}")
+    torch.cuda.current_stream(t.device).synchronize()
+    return t, ctypes.c_void_p(t.data_ptr())
+
+
 def _check(L, rc: int, ctx=None):
     if rc != EP_OK:
         msg = L.ep_last_error(ctx).decode()
@@ -187,12 +227,14 @@ def _check(L, rc: int, ctx=None):
 
 # ---- C names -----------------------------------------------------------------
 def ep_init(cfg: ep_config, xyz, A_obs, sigma, lib=None):
+    """With cfg.pointers_on_device the arrays may be numpy arrays or tensors;
+    they are passed as tensors on cuda:cfg.device."""
     L = lib or load()
-    xyz = _arr(xyz).reshape(-1, 3)
-    S = xyz.shape[0]
-    A_obs, sigma = _arr(A_obs, S), _arr(sigma, S)
+    dev, d = bool(cfg.pointers_on_device), int(cfg.device)
+    S = int(np.prod(tuple(xyz.shape))) // 3 if hasattr(xyz, "shape") else len(np.asarray(xyz).reshape(-1, 3))
+    keep = [_marshal_in(a, n, dev, d) for a, n in ((xyz, 3 * S), (A_obs, S), (sigma, S))]
     out = ctypes.c_void_p()
-    _check(L, L.ep_init(ctypes.byref(cfg), S, _ptr(xyz), _ptr(A_obs), _ptr(sigma), ctypes.byref(out)))
+    _check(L, L.ep_init(ctypes.byref(cfg), S, keep[0][1], keep[1][1], keep[2][1], ctypes.byref(out)))
     return out
 
 
@@ -206,17 +248,19 @@ def ep_sweep(ctx, lib=None) -> dict:
     return out
 
 
-def ep_posterior_mean(ctx, N: int, lib=None) -> np.ndarray:
+def ep_posterior_mean(ctx, N: int, lib=None, on_device: bool = False, device: int = 0):
+    """on_device must match the context's pointers_on_device."""
     L = lib or load()
-    out = np.empty(N)
-    _check(L, L.ep_posterior_mean(ctx, _ptr(out)), ctx)
+    out, p = _marshal_out(N, on_device, device)
+    _check(L, L.ep_posterior_mean(ctx, p), ctx)
     return out
 
 
-def ep_marginal_var(ctx, N: int, lib=None) -> np.ndarray:
+def ep_marginal_var(ctx, N: int, lib=None, on_device: bool = False, device: int = 0):
+    """on_device must match the context's pointers_on_device."""
     L = lib or load()
-    out = np.empty(N)
-    _check(L, L.ep_marginal_var(ctx, _ptr(out)), ctx)
+    out, p = _marshal_out(N, on_device, device)
+    _check(L, L.ep_marginal_var(ctx, p), ctx)
     return out
 
 
@@ -292,81 +336,92 @@ def ep_mlp_loss_grad(weights, xstd, ystd, device=0, lib=None):
 
 # ---- convenience wrapper -----------------------------------------------------
 class EP:
-    """One EP context on the GPU."""
+    """One EP context on the GPU.  With cfg pointers_on_device = 1 every
+    array goes in and comes out as a tensor on cuda:device."""
 
     def __init__(self, cfg: Mapping | ep_config, xyz, A_obs, sigma, lib=None):
         self.L = lib or load()
         self.cfg = cfg if isinstance(cfg, ep_config) else make_config(cfg, lib=self.L)
         self.N = self.cfg.n ** 3
-        self.S = int(np.asarray(xyz).reshape(-1, 3).shape[0])
+        self.on_device = bool(self.cfg.pointers_on_device)
+        self.device = int(self.cfg.device)
         self.ctx = ep_init(self.cfg, xyz, A_obs, sigma, lib=self.L)
+        st = ep_structure_stats()
+        _check(self.L, self.L.ep_structure(self.ctx, ctypes.byref(st)), self.ctx)
+        self.S = int(st.n_stars)
+
+    def _in(self, a, n, dtype=np.float64):
+        return _marshal_in(a, n, self.on_device, self.device, dtype)
+
+    def _out(self, shape, dtype=np.float64):
+        return _marshal_out(shape, self.on_device, self.device, dtype)
 
     def sweep(self) -> dict:
         return ep_sweep(self.ctx, lib=self.L)
 
-    def posterior_mean(self) -> np.ndarray:
-        return ep_posterior_mean(self.ctx, self.N, lib=self.L)
+    def posterior_mean(self):
+        return ep_posterior_mean(self.ctx, self.N, lib=self.L, on_device=self.on_device, device=self.device)
 
-    def marginal_var(self) -> np.ndarray:
-        return ep_marginal_var(self.ctx, self.N, lib=self.L)
+    def marginal_var(self):
+        return ep_marginal_var(self.ctx, self.N, lib=self.L, on_device=self.on_device, device=self.device)
 
     def sites(self):
-        tau, nu = np.empty(self.S), np.empty(self.S)
-        _check(self.L, self.L.ep_get_sites(self.ctx, _ptr(tau), _ptr(nu)), self.ctx)
+        (tau, pt), (nu, pn) = self._out(self.S), self._out(self.S)
+        _check(self.L, self.L.ep_get_sites(self.ctx, pt, pn), self.ctx)
         return tau, nu
 
     def set_sites(self, tau, nu) -> None:
-        tau, nu = _arr(tau, self.S), _arr(nu, self.S)
-        _check(self.L, self.L.ep_set_sites(self.ctx, _ptr(tau), _ptr(nu)), self.ctx)
+        (kt, pt), (kn, pn) = self._in(tau, self.S), self._in(nu, self.S)
+        _check(self.L, self.L.ep_set_sites(self.ctx, pt, pn), self.ctx)
 
-    def linpoint(self) -> np.ndarray:
-        f = np.empty(self.N)
-        _check(self.L, self.L.ep_get_linpoint(self.ctx, _ptr(f)), self.ctx)
+    def linpoint(self):
+        f, p = self._out(self.N)
+        _check(self.L, self.L.ep_get_linpoint(self.ctx, p), self.ctx)
         return f
 
     def set_linpoint(self, f) -> None:
-        f = _arr(f, self.N)
-        _check(self.L, self.L.ep_set_linpoint(self.ctx, _ptr(f)), self.ctx)
+        k, p = self._in(f, self.N)
+        _check(self.L, self.L.ep_set_linpoint(self.ctx, p), self.ctx)
 
     def star_state(self) -> dict:
         keys = ("lnA", "cav_mu", "cav_var", "lnZ", "tilted_mean", "tilted_var")
-        arrs = [np.empty(self.S) for _ in keys]
-        _check(self.L, self.L.ep_star_state(self.ctx, *[_ptr(a) for a in arrs]), self.ctx)
-        return dict(zip(keys, arrs))
+        outs = [self._out(self.S) for _ in keys]
+        _check(self.L, self.L.ep_star_state(self.ctx, *[p for _, p in outs]), self.ctx)
+        return dict(zip(keys, [a for a, _ in outs]))
 
     def load_surrogate(self, weights) -> None:
-        w = np.ascontiguousarray(weights, dtype=np.float32)
-        if w.size != MLP_NPARAM:
-            raise ValueError(f"expected {MLP_NPARAM} weights")
-        _check(self.L, self.L.ep_mlp_load(self.ctx, _ptr(w)), self.ctx)
+        k, p = self._in(weights, MLP_NPARAM, np.float32)
+        _check(self.L, self.L.ep_mlp_load(self.ctx, p), self.ctx)
 
-    def ordering(self) -> np.ndarray:
-        perm = np.empty(self.N, dtype=np.int32)
-        _check(self.L, self.L.ep_ordering(self.ctx, _ptr(perm)), self.ctx)
+    def ordering(self):
+        perm, p = self._out(self.N, np.int32)
+        _check(self.L, self.L.ep_ordering(self.ctx, p), self.ctx)
         return perm
 
     def density_moments(self):
-        m, v = np.empty(self.N), np.empty(self.N)
-        _check(self.L, self.L.ep_density_moments(self.ctx, _ptr(m), _ptr(v)), self.ctx)
+        (m, pm), (v, pv) = self._out(self.N), self._out(self.N)
+        _check(self.L, self.L.ep_density_moments(self.ctx, pm, pv), self.ctx)
         return m, v
 
     def extinction_map(self, z=None):
         """Exact posterior mean of A to every node; with z (K x N standard
         normals, K >= 2, consumed in elimination order) also the sample
         variance over the K posterior draws."""
-        mean = np.empty(self.N)
+        mean, pm = self._out(self.N)
         if z is None:
-            _check(self.L, self.L.ep_extinction_map(self.ctx, 0, None, _ptr(mean), None), self.ctx)
+            _check(self.L, self.L.ep_extinction_map(self.ctx, 0, None, pm, None), self.ctx)
             return mean
-        zz = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, self.N)
-        var = np.empty(self.N)
-        _check(self.L, self.L.ep_extinction_map(self.ctx, zz.shape[0], _ptr(zz), _ptr(mean), _ptr(var)), self.ctx)
+        K = int(np.prod(tuple(z.shape))) // self.N if hasattr(z, "shape") else np.asarray(z).size // self.N
+        kz, pz = self._in(z, K * self.N)
+        var, pv = self._out(self.N)
+        _check(self.L, self.L.ep_extinction_map(self.ctx, K, pz, pm, pv), self.ctx)
         return mean, var
 
-    def point_predict(self, xyz2) -> np.ndarray:
-        x = np.ascontiguousarray(xyz2, dtype=np.float64).reshape(-1, 6)
-        out = np.empty((x.shape[0], 5))
-        _check(self.L, self.L.ep_point_predict(self.ctx, x.shape[0], _ptr(x), _ptr(out)), self.ctx)
+    def point_predict(self, xyz2):
+        n = (int(np.prod(tuple(xyz2.shape))) if hasattr(xyz2, "shape") else np.asarray(xyz2).size) // 6
+        kx, px = self._in(xyz2, 6 * n)
+        out, po = self._out((n, 5))
+        _check(self.L, self.L.ep_point_predict(self.ctx, n, px, po), self.ctx)
         return out
 
     def structure(self) -> dict:
