@@ -56,6 +56,7 @@ typedef enum {
 typedef enum { EP_LIK_EXTINCTION = 0, EP_LIK_GAUSS_LINEAR = 1 } ep_likelihood;
 typedef enum { EP_PREC_FP64 = 0, EP_PREC_MIXED = 1 } ep_precision;
 typedef enum { EP_MOM_QUADRATURE = 0, EP_MOM_SURROGATE = 1 } ep_moments;
+typedef enum { EP_MEAN_CONSTANT = 0, EP_MEAN_DISC_BUMP = 1 } ep_mean_fn;
 
 typedef struct ep_config {
     /* grid */
@@ -101,6 +102,22 @@ typedef struct ep_config {
                                    copied to the host first.  Context-free calls
                                    (ep_tilted_moments, ep_simulate, ep_mlp_*) always
                                    take host memory. */
+    /* prior mean of f (Sec. 5): CONSTANT = prior_mean; DISC_BUMP = ln of an
+     * exponential disc plus a Gaussian bump in rho kappa, whose five
+     * parameters theta = (L, H, rho kappa_0, s_bump, A_bump) are inferred
+     * with the field (EP over the field and phi = ln theta jointly, Sec. 4.1).
+     * Geometry: the observer is in the disc mid-plane z = observer z at
+     * Galactocentric radius sun_radius_pc and looks along +y away from the
+     * Galactic centre; R = sqrt((R0 + y - y_o)^2 + (x - x_o)^2), h = z - z_o;
+     * the bump is a slab across the line of sight at y - y_o = s_bump.
+     *   rho kappa = rk0 exp(-(R - R0)/L - |h|/H) + A_b N(y - y_o; s_b, w^2) exp(-|h|/H).
+     * DISC_BUMP needs precision FP64. */
+    int32_t mean_fn;           /* ep_mean_fn */
+    double theta_prior[5];     /* log-normal hyperprior means of theta (pc, pc, mag/pc, pc,
+                                  mag); each hyperprior's sd equals its mean.  ep_simulate
+                                  with DISC_BUMP draws around m(x; theta_prior). */
+    double sun_radius_pc;      /* R0 (default 8000) */
+    double bump_width_pc;      /* w, the bump's fixed standard deviation (default 400) */
 } ep_config;
 
 /* Kinds of timed MFMA tile-kernel launches (ep_sweep_stats.kernel_ms):
@@ -191,6 +208,14 @@ int ep_marginal_var(ep_ctx *ctx, double *out);
 /* Release everything.  NULL is allowed. */
 void ep_free(ep_ctx *ctx);
 
+/* Posterior of the mean parameters (mean_fn DISC_BUMP), recomputed like
+ * ep_posterior_mean: mean (5) and covariance (5 x 5 row-major, may be NULL)
+ * of phi = ln theta, theta = (L, H, rho kappa_0, s_bump, A_bump).  The border
+ * of the joint precision is eliminated by its Schur complement after the
+ * grid factorization (five extra solves).  STATE with mean_fn CONSTANT;
+ * NOT_PD if the Schur complement is not positive definite. */
+int ep_theta(ep_ctx *ctx, double *mean, double *cov);
+
 /* Message of the last failure on ctx (or of the calling thread when ctx is
  * NULL).  Never NULL. */
 const char *ep_last_error(const ep_ctx *ctx);
@@ -200,7 +225,8 @@ const char *ep_last_error(const ep_ctx *ctx);
 int ep_get_sites(ep_ctx *ctx, double *tau, double *nu);
 int ep_set_sites(ep_ctx *ctx, const double *tau, const double *nu);
 
-/* Linearisation point fhat (n^3 doubles). */
+/* Linearisation point: fhat (n^3 doubles), followed with mean_fn DISC_BUMP
+ * by phihat, the 5 log-parameters about which the mean is linearised. */
 int ep_get_linpoint(ep_ctx *ctx, double *f);
 int ep_set_linpoint(ep_ctx *ctx, const double *f);
 
@@ -220,7 +246,7 @@ int ep_tilted_moments(int32_t mode, int64_t n, const double *mu_c, const double 
 
 /* Synthetic observations with the library's own arithmetic (for
  * benchmarks): f_true = m0 + (I-B)^{-1} D^{1/2} xi (exact draw from the
- * Vecchia prior) and A_obs = A(f_true) + sigma * eps (extinction) or
+ * Vecchia prior; with mean_fn DISC_BUMP m0 is the field m(x; theta_prior)) and A_obs = A(f_true) + sigma * eps (extinction) or
  * c_n + g_n.f_true + sigma * eps with g, c at the prior mean
  * (gauss_linear).  xi: n^3 deviates; xyz, sigma, eps per star.  Outputs:
  * f_true (n^3) and A_obs (n_stars), either may be NULL. */

@@ -119,6 +119,12 @@ struct ep_ctx {
     int* d_mapbad = nullptr;
     bool mlp_loaded = false;
     int64_t fallbacks = 0;
+    // inferred prior-mean parameters (mean_fn DISC_BUMP): M = 5, else 0
+    int M = 0;
+    double mu0[NTHETA] = {}, s0sq[NTHETA] = {};   // hyperprior of phi = ln theta
+    double phihat[NTHETA] = {};                   // mean linearisation point
+    BorderDev border{};                           // mu_phi, phihat, Sigma_phiphi of the last border solve
+    double *d_mhat = nullptr, *d_J = nullptr, *d_h = nullptr, *d_R = nullptr, *d_Wb = nullptr, *d_part = nullptr;
 
     std::vector<LevelPlan> levels;
     std::vector<TaskRange> trtri1, trtri1f, trtri2;   // per doubling stage (1f: FP32 factor copy)
@@ -604,6 +610,20 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
     }
     if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED) { err = "unknown precision"; return EP_ERR_INVALID_ARG; }
     if (c->pointers_on_device != 0 && c->pointers_on_device != 1) { err = "pointers_on_device must be 0 or 1"; return EP_ERR_INVALID_ARG; }
+    if (c->mean_fn != EP_MEAN_CONSTANT && c->mean_fn != EP_MEAN_DISC_BUMP) { err = "unknown mean_fn"; return EP_ERR_INVALID_ARG; }
+    if (c->mean_fn == EP_MEAN_DISC_BUMP) {
+        for (int j = 0; j < 5; j++)
+            if (!(c->theta_prior[j] > 0) || !std::isfinite(c->theta_prior[j])) {
+                err = "theta_prior must be finite and > 0";
+                return EP_ERR_INVALID_ARG;
+            }
+        if (!(c->sun_radius_pc > 0) || !std::isfinite(c->sun_radius_pc) || !(c->bump_width_pc > 0) ||
+            !std::isfinite(c->bump_width_pc)) {
+            err = "sun_radius_pc and bump_width_pc must be finite and > 0";
+            return EP_ERR_INVALID_ARG;
+        }
+        if (c->precision != EP_PREC_FP64) { err = "mean_fn DISC_BUMP needs precision FP64"; return EP_ERR_INVALID_ARG; }
+    }
     if (c->mixed_fp64_levels < 0) { err = "mixed_fp64_levels must be >= 0"; return EP_ERR_INVALID_ARG; }
     if (c->moments != EP_MOM_QUADRATURE && c->moments != EP_MOM_SURROGATE) { err = "unknown moments mode"; return EP_ERR_INVALID_ARG; }
     if (c->moments == EP_MOM_SURROGATE && !(c->surrogate_tol > 0)) { err = "surrogate_tol must be > 0"; return EP_ERR_INVALID_ARG; }
@@ -647,6 +667,23 @@ static void geom_from_cfg(const ep_config* c, GridGeom& g, PriorParams& p) {
     p.ell = c->outer_scale_pc;
     p.support = c->support_pc;
     p.rho = c->vecchia_radius_pc > 0 ? c->vecchia_radius_pc : c->support_pc;
+}
+
+// the disc + bump mean function at theta = exp(phihat)
+static MeanDev mean_params(const ep_ctx* ctx) {
+    MeanDev P{};
+    for (int j = 0; j < NTHETA; j++) P.theta[j] = std::exp(ctx->phihat[j]);
+    P.R0 = ctx->cfg.sun_radius_pc;
+    P.w = ctx->cfg.bump_width_pc;
+    return P;
+}
+static void enqueue_mean(ep_ctx* ctx) {
+    launch_mean_fn(ctx->stream, ctx->GD, mean_params(ctx), ctx->d_mhat, ctx->d_J, ctx->g.N());
+}
+static Phi5 phi5(const double* v) {
+    Phi5 p{};
+    for (int j = 0; j < NTHETA; j++) p.v[j] = v[j];
+    return p;
 }
 
 static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const double* sig) {
@@ -730,7 +767,19 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     ctx->n_q0 = (int64_t)q0dest.size();
     ctx->n_pad = (int64_t)paddest.size();
     std::vector<double> b0;
-    q0_times_const(g, ctx->vec, ctx->pp.mean, b0);
+    if (c.mean_fn == EP_MEAN_DISC_BUMP) {
+        // the latent field is delta = f - m(phi), of prior mean 0; phi = ln theta
+        // has independent log-normal hyperpriors whose sd equals their mean
+        ctx->M = NTHETA;
+        b0.assign((size_t)N, 0.0);
+        for (int j = 0; j < NTHETA; j++) {
+            ctx->s0sq[j] = std::log(2.0);
+            ctx->mu0[j] = std::log(c.theta_prior[j]) - 0.5 * ctx->s0sq[j];
+            ctx->phihat[j] = ctx->mu0[j];
+        }
+    } else {
+        q0_times_const(g, ctx->vec, ctx->pp.mean, b0);
+    }
     // per-star slot order by local row
     std::vector<int32_t> sord(ctx->sup.nodes.size());
     for (int64_t s = 0; s < S; s++) {
@@ -831,6 +880,18 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     SD.tmean = ctx->d_tmean; SD.tvar = ctx->d_tvar; SD.status = ctx->d_status; SD.dtau = ctx->d_dtau;
     GridDev& GD = ctx->GD;
     GD.n = g.n; GD.h = g.h; GD.ox = g.obs[0]; GD.oy = g.obs[1]; GD.oz = g.obs[2];
+    if (ctx->M) {
+        TRY(dev_alloc(ctx, &ctx->d_mhat, N));
+        TRY(dev_alloc(ctx, &ctx->d_J, NTHETA * N));
+        TRY(dev_alloc(ctx, &ctx->d_h, NTHETA * std::max<int64_t>(S, 1)));
+        TRY(dev_alloc(ctx, &ctx->d_R, NTHETA * N));
+        TRY(dev_alloc(ctx, &ctx->d_Wb, (NTHETA + 1) * N));
+        TRY(dev_alloc(ctx, &ctx->d_part, DOT_BLOCKS * (NTHETA * (NTHETA + 1) + NTHETA * (NTHETA + 1) / 2 + NTHETA)));
+        launch_fill(ctx->stream, ctx->d_h, NTHETA * S, 0.0);
+        // fhat = m(phihat) + deltahat with deltahat = 0
+        enqueue_mean(ctx);
+        HIPCHK(hipMemcpyAsync(ctx->d_fhat, ctx->d_mhat, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     // free host-side bulk no longer needed
@@ -855,16 +916,23 @@ static bool frozen(const ep_ctx* ctx) {
     return ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR || ctx->cfg.relinearize == 0;
 }
 
+// sightlines at fhat; with an inferred mean also the border projections
+// h_n = J^T g_n and c'_n (the mean linearised about phihat)
 static void enqueue_linearise(ep_ctx* ctx) {
     if (frozen(ctx)) {
         if (ctx->linearised) return;
-        // freeze at the prior mean
-        launch_fill(ctx->stream, ctx->d_t, ctx->g.N(), ctx->pp.mean);
-        launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_t, ctx->max_support);
-        ctx->linearised = true;
-        return;
+        // freeze at the prior mean (m(mu0) with an inferred mean, held in fhat)
+        if (ctx->M) {
+            launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
+        } else {
+            launch_fill(ctx->stream, ctx->d_t, ctx->g.N(), ctx->pp.mean);
+            launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_t, ctx->max_support);
+        }
+    } else {
+        launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
     }
-    launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
+    if (ctx->M) launch_star_border(ctx->stream, ctx->SD, ctx->d_mhat, ctx->d_J, phi5(ctx->phihat), ctx->d_h, ctx->g.N());
+    ctx->linearised = true;
 }
 
 static int enqueue_assemble(ep_ctx* ctx) {
@@ -1016,6 +1084,95 @@ static int run_solve(ep_ctx* ctx) {
     return EP_OK;
 }
 
+// Small dense SPD inverse (the border's Schur complement); false if not PD.
+static bool spd_inverse(int n, const double* A, double* inv) {
+    double L[NTHETA * NTHETA] = {};
+    for (int j = 0; j < n; j++) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; k++) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0) || !std::isfinite(d)) return false;
+        L[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; i++) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; k++) v -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = v / L[j * n + j];
+        }
+    }
+    for (int c = 0; c < n; c++) {   // solve L L^T x = e_c
+        double y[NTHETA];
+        for (int i = 0; i < n; i++) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; k++) v -= L[i * n + k] * y[k];
+            y[i] = v / L[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; i--) {
+            double v = y[i];
+            for (int k = i + 1; k < n; k++) v -= L[k * n + i] * inv[k * n + c];
+            inv[i * n + c] = v / L[i * n + i];
+        }
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < i; j++) inv[i * n + j] = inv[j * n + i] = 0.5 * (inv[i * n + j] + inv[j * n + i]);
+    return true;
+}
+
+// The border of the inferred mean parameters, after run_solve left
+// y = Q_dd^{-1} b_d in d_mu: W = Q_dd^{-1} R (five solves), the Schur
+// complement S = S0^{-1} + H^T T H - R^T W, mu_phi = S^{-1} (b_phi - R^T y),
+// Sigma_phiphi = S^{-1}; then d_mu <- mu_delta = y - W mu_phi.  Partial sums
+// come back per block and are added on the host in block order.
+static int border_solve(ep_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->g.N();
+    constexpr int NP = NTHETA * (NTHETA + 1), NS = NTHETA * (NTHETA + 1) / 2 + NTHETA;
+    launch_fill(st, ctx->d_R, NTHETA * N, 0.0);
+    launch_border_rhs(st, ctx->SD, ctx->d_h, ctx->d_R, N);
+    for (int j = 0; j < NTHETA; j++) {
+        launch_gather_perm(st, ctx->d_perm, ctx->d_R + j * N, ctx->d_y, N);
+        enqueue_tri_solve(ctx, ctx->d_Wb + j * N);
+    }
+    double* y = ctx->d_Wb + NTHETA * N;
+    HIPCHK(hipMemcpyAsync(y, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    launch_dots_5x6(st, ctx->d_R, ctx->d_Wb, N, ctx->d_part);
+    launch_star_sums(st, ctx->SD, ctx->d_h, ctx->d_part + DOT_BLOCKS * NP);
+    std::vector<double> part((size_t)DOT_BLOCKS * (NP + NS));
+    HIPCHK(hipMemcpyAsync(part.data(), ctx->d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double dots[NP] = {}, sums[NS] = {};
+    for (int b = 0; b < DOT_BLOCKS; b++) {
+        for (int i = 0; i < NP; i++) dots[i] += part[(size_t)b * NP + i];
+        for (int i = 0; i < NS; i++) sums[i] += part[(size_t)DOT_BLOCKS * NP + (size_t)b * NS + i];
+    }
+    // dots[i * 6 + k] = R_i . W_k (k < 5), R_i . y (k = 5); sums: tau h_j h_k
+    // (j <= k, row by row), then (nu - tau c') h_j
+    double S[NTHETA * NTHETA], rhs[NTHETA];
+    int q = 0;
+    for (int j = 0; j < NTHETA; j++)
+        for (int k = j; k < NTHETA; k++, q++) {
+            const double rw = 0.5 * (dots[j * (NTHETA + 1) + k] + dots[k * (NTHETA + 1) + j]);
+            S[j * NTHETA + k] = S[k * NTHETA + j] = (j == k ? 1.0 / ctx->s0sq[j] : 0.0) + sums[q] - rw;
+        }
+    for (int j = 0; j < NTHETA; j++)
+        rhs[j] = ctx->mu0[j] / ctx->s0sq[j] + sums[q + j] - dots[j * (NTHETA + 1) + NTHETA];
+    BorderDev& B = ctx->border;
+    if (!spd_inverse(NTHETA, S, B.sinv)) {
+        ctx->err = "the Schur complement of the mean parameters is not positive definite";
+        return EP_ERR_NOT_PD;
+    }
+    for (int j = 0; j < NTHETA; j++) {
+        double v = 0;
+        for (int k = 0; k < NTHETA; k++) v += B.sinv[j * NTHETA + k] * rhs[k];
+        if (!std::isfinite(v)) {
+            ctx->err = "posterior mean of the mean parameters is not finite";
+            return EP_ERR_NUMERIC;
+        }
+        B.mu_phi[j] = v;
+        B.phihat[j] = ctx->phihat[j];
+    }
+    launch_minus_w(st, y, ctx->d_Wb, phi5(B.mu_phi), ctx->d_mu, N);
+    return EP_OK;
+}
+
 static void enqueue_selinv(ep_ctx* ctx) {
     hipStream_t st = ctx->stream;
     Bufs b = bufs(ctx);
@@ -1078,12 +1235,15 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     ctx->kt_used = 0;
     TRY(run_factor(ctx, ev));
     TRY(run_solve(ctx));
+    if (ctx->M) TRY(border_solve(ctx));
     HIPCHK(hipEventRecord(ev[4], st));
     enqueue_selinv(ctx);
     HIPCHK(hipEventRecord(ev[5], st));
-    // non-finite posterior mean -> NUMERIC, nothing changed
+    // non-finite posterior mean -> NUMERIC, nothing changed (with an
+    // inferred mean: the mean of f = mhat + J (mu_phi - phihat) + mu_delta)
     std::vector<double> mu(N), fh(N);
-    HIPCHK(hipMemcpyAsync(mu.data(), ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    if (ctx->M) launch_f_mean(st, ctx->d_mhat, ctx->d_J, ctx->d_mu, ctx->border, ctx->d_t, N);
+    HIPCHK(hipMemcpyAsync(mu.data(), ctx->M ? ctx->d_t : ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(fh.data(), ctx->d_fhat, sizeof(double) * N, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double dmu = 0;
@@ -1099,6 +1259,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     HIPCHK(hipMemcpyAsync(ctx->d_nu_bak, ctx->d_nu, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(ev[6], st));
     launch_cavity(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->d_mu, ctx->max_support);
+    if (ctx->M) launch_cavity_border(st, ctx->SD, ctx->d_Wb, ctx->d_h, ctx->border, N);
     EpParams p{ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR ? 1 : 0, ctx->cfg.damping, ctx->cfg.cavity_var_floor};
     ctx->fallbacks = 0;
     if (ctx->cfg.moments == EP_MOM_SURROGATE && p.mode == 0) {
@@ -1131,7 +1292,16 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
             ctx->err = "non-finite site after the update";
             return EP_ERR_NUMERIC;
         }
-    if (!frozen(ctx)) HIPCHK(hipMemcpyAsync(ctx->d_fhat, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    if (!frozen(ctx)) {
+        if (ctx->M) {
+            // relinearise the mean at the posterior mean of phi: fhat = m(mu_phi) + mu_delta
+            for (int j = 0; j < NTHETA; j++) ctx->phihat[j] = ctx->border.mu_phi[j];
+            enqueue_mean(ctx);
+            launch_sum2(st, ctx->d_mhat, ctx->d_mu, ctx->d_fhat, N);
+        } else {
+            HIPCHK(hipMemcpyAsync(ctx->d_fhat, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        }
+    }
     HIPCHK(hipStreamSynchronize(st));
     if (stats) {
         stats->ms_linearise = ev_ms(ev[0], ev[1]);
@@ -1281,6 +1451,10 @@ void ep_config_default(ep_config* c) {
     c->support_pc = 150.0;
     c->vecchia_radius_pc = 0.0;
     c->los_step_pc = 2.0;
+    const double tp[5] = {3000.0, 150.0, 7.5e-4, 2000.0, 0.1};   // Sec. 5 hyperprior means
+    for (int j = 0; j < 5; j++) c->theta_prior[j] = tp[j];
+    c->sun_radius_pc = 8000.0;
+    c->bump_width_pc = 400.0;
     c->likelihood = EP_LIK_EXTINCTION;
     c->precision = EP_PREC_FP64;
     c->moments = EP_MOM_QUADRATURE;
@@ -1349,7 +1523,13 @@ int ep_posterior_mean(ep_ctx* ctx, double* out) {
     HIPCHK(hipSetDevice(ctx->cfg.device));
     TRY(run_factor(ctx, nullptr));
     TRY(run_solve(ctx));
-    HIPCHK(hipMemcpyAsync(out, ctx->d_mu, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
+    const double* src = ctx->d_mu;
+    if (ctx->M) {
+        TRY(border_solve(ctx));
+        launch_f_mean(ctx->stream, ctx->d_mhat, ctx->d_J, ctx->d_mu, ctx->border, ctx->d_t, ctx->g.N());
+        src = ctx->d_t;
+    }
+    HIPCHK(hipMemcpyAsync(out, src, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
     return EP_OK;
@@ -1359,11 +1539,33 @@ int ep_marginal_var(ep_ctx* ctx, double* out) {
     if (!ctx || !out) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
     TRY(run_factor(ctx, nullptr));
+    if (ctx->M) {
+        TRY(run_solve(ctx));
+        TRY(border_solve(ctx));
+    }
     enqueue_selinv(ctx);
     launch_diag(ctx->stream, ctx->d_perm, ctx->d_snode, ctx->F, ctx->d_fronts, ctx->d_var, ctx->g.N());
+    if (ctx->M) launch_f_var(ctx->stream, ctx->d_Wb, ctx->d_J, ctx->border, ctx->d_var, ctx->g.N());
     HIPCHK(hipMemcpyAsync(out, ctx->d_var, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
+    return EP_OK;
+}
+
+int ep_theta(ep_ctx* ctx, double* mean, double* cov) {
+    if (!ctx || !mean) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
+    if (!ctx->M) {
+        ctx->err = "ep_theta: the context has no inferred mean parameters (mean_fn CONSTANT)";
+        return EP_ERR_STATE;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    TRY(run_factor(ctx, nullptr));
+    TRY(run_solve(ctx));
+    TRY(border_solve(ctx));
+    const hipMemcpyKind k = ctx->cfg.pointers_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    HIPCHK(hipMemcpyAsync(mean, ctx->border.mu_phi, sizeof(double) * NTHETA, k, ctx->stream));
+    if (cov) HIPCHK(hipMemcpyAsync(cov, ctx->border.sinv, sizeof(double) * NTHETA * NTHETA, k, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return EP_OK;
 }
 
@@ -1388,11 +1590,18 @@ int ep_density_moments(ep_ctx* ctx, double* mean, double* var) {
     if (!ctx || !mean || !var) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
     TRY(maps_factor_and_mean(ctx));
+    const int64_t N = ctx->g.N();
+    const double* fmean = ctx->d_mu;
+    if (ctx->M) {
+        TRY(border_solve(ctx));
+        launch_f_mean(ctx->stream, ctx->d_mhat, ctx->d_J, ctx->d_mu, ctx->border, ctx->d_y, N);
+        fmean = ctx->d_y;
+    }
     enqueue_selinv(ctx);
     launch_diag(ctx->stream, ctx->d_perm, ctx->d_snode, ctx->F, ctx->d_fronts, ctx->d_var, ctx->g.N());
-    const int64_t N = ctx->g.N();
+    if (ctx->M) launch_f_var(ctx->stream, ctx->d_Wb, ctx->d_J, ctx->border, ctx->d_var, N);
     // the two outputs go through d_x and d_t
-    launch_density(ctx->stream, ctx->d_mu, ctx->d_var, ctx->d_x, ctx->d_t, N);
+    launch_density(ctx->stream, fmean, ctx->d_var, ctx->d_x, ctx->d_t, N);
     HIPCHK(hipMemcpyAsync(mean, ctx->d_x, sizeof(double) * N, kind_out(ctx), ctx->stream));
     HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, kind_out(ctx), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1417,6 +1626,10 @@ int ep_extinction_map(ep_ctx* ctx, int32_t n_samples, const double* z, double* m
                 return EP_ERR_INVALID_ARG;
             }
     HIPCHK(hipSetDevice(ctx->cfg.device));
+    if (ctx->M) {
+        ctx->err = "ep_extinction_map: not available with an inferred prior mean (mean_fn DISC_BUMP)";
+        return EP_ERR_STATE;
+    }
     TRY(ensure_maps(ctx));
     TRY(maps_factor_and_mean(ctx));
     // Posterior draws f = mu + L^{-T} z need the factor, so they come before
@@ -1472,6 +1685,10 @@ int ep_point_predict(ep_ctx* ctx, int64_t n_pairs, const double* xyz2, double* o
         }
     if (n_pairs == 0) return EP_OK;
     HIPCHK(hipSetDevice(ctx->cfg.device));
+    if (ctx->M) {
+        ctx->err = "ep_point_predict: not available with an inferred prior mean (mean_fn DISC_BUMP)";
+        return EP_ERR_STATE;
+    }
     TRY(ensure_maps(ctx));
     if (ctx->pts_cap < n_pairs) {
         TRY(dev_alloc(ctx, &ctx->d_pts, 11 * n_pairs));
@@ -1526,7 +1743,11 @@ int ep_set_sites(ep_ctx* ctx, const double* tau, const double* nu) {
 int ep_get_linpoint(ep_ctx* ctx, double* f) {
     if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
-    HIPCHK(hipMemcpyAsync(f, ctx->d_fhat, sizeof(double) * ctx->g.N(), kind_out(ctx), ctx->stream));
+    const int64_t N = ctx->g.N();
+    HIPCHK(hipMemcpyAsync(f, ctx->d_fhat, sizeof(double) * N, kind_out(ctx), ctx->stream));
+    if (ctx->M)   // then phihat
+        HIPCHK(hipMemcpyAsync(f + N, ctx->phihat, sizeof(double) * NTHETA,
+                              ctx->cfg.pointers_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return EP_OK;
 }
@@ -1535,10 +1756,15 @@ int ep_set_linpoint(ep_ctx* ctx, const double* f) {
     if (!ctx || !f) { g_tls_err = "NULL argument"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::vector<double> hf;
-    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, f, ctx->g.N(), hf));
-    for (int64_t i = 0; i < ctx->g.N(); i++)
+    const int64_t N = ctx->g.N(), n = N + ctx->M;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, f, n, hf));
+    for (int64_t i = 0; i < n; i++)
         if (!std::isfinite(f[i])) { ctx->err = "linearisation point must be finite"; return EP_ERR_INVALID_ARG; }
-    HIPCHK(hipMemcpyAsync(ctx->d_fhat, f, sizeof(double) * ctx->g.N(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_fhat, f, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->M) {
+        for (int j = 0; j < NTHETA; j++) ctx->phihat[j] = f[N + j];
+        enqueue_mean(ctx);
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return EP_OK;
 }
@@ -1668,11 +1894,15 @@ int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const 
     Vecchia v;
     if (build_vecchia(g, pp, st, v) != 0) { g_tls_err = "Vecchia prior not positive definite"; return EP_ERR_NUMERIC; }
     const int64_t N = g.N();
+    const bool disc = cfg->mean_fn == EP_MEAN_DISC_BUMP;
     std::vector<double> f(N);
-    prior_draw(g, v, pp.mean, xi, f.data());
-    if (f_true) std::copy(f.begin(), f.end(), f_true);
-    if (!A_obs || n_stars == 0) return EP_OK;
-    // line-of-sight integrals on the GPU with the library's kernel
+    prior_draw(g, v, disc ? 0.0 : pp.mean, xi, f.data());
+    if (!disc) {
+        if (f_true) std::copy(f.begin(), f.end(), f_true);
+        if (!A_obs || n_stars == 0) return EP_OK;
+    }
+    // the disc + bump mean at theta_prior, and the line-of-sight integrals,
+    // on the GPU with the library's kernels
     ep_config c2 = *cfg;
     ep_ctx* ctx = new ep_ctx();
     ctx->cfg = c2;
@@ -1686,6 +1916,23 @@ int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const 
     HIPCHK(hipSetDevice(c2.device));
     HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
     ctx->own_stream = true;
+    GridDev GD{g.n, g.h, g.obs[0], g.obs[1], g.obs[2]};
+    std::vector<double> mfield((size_t)N, pp.mean);
+    if (disc) {
+        TRY(dev_alloc(ctx, &ctx->d_mhat, N));
+        TRY(dev_alloc(ctx, &ctx->d_J, NTHETA * N));
+        MeanDev P{};
+        for (int j = 0; j < NTHETA; j++) P.theta[j] = cfg->theta_prior[j];
+        P.R0 = cfg->sun_radius_pc;
+        P.w = cfg->bump_width_pc;
+        launch_mean_fn(ctx->stream, GD, P, ctx->d_mhat, ctx->d_J, N);
+        HIPCHK(hipMemcpyAsync(mfield.data(), ctx->d_mhat, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+        for (int64_t i = 0; i < N; i++) f[i] += mfield[i];
+        if (f_true) std::copy(f.begin(), f.end(), f_true);
+        if (!A_obs || n_stars == 0) return EP_OK;
+    }
     build_supports(g, n_stars, xyz, ctx->sup);
     int cap = 0;
     for (int64_t s = 0; s < n_stars; s++) cap = std::max<int>(cap, (int)(ctx->sup.ptr[s + 1] - ctx->sup.ptr[s]));
@@ -1700,13 +1947,11 @@ int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const 
     TRY(dev_alloc(ctx, &ctx->d_c, n_stars));
     std::vector<double> field(N);
     const bool gauss = cfg->likelihood == EP_LIK_GAUSS_LINEAR;
-    if (gauss) std::fill(field.begin(), field.end(), pp.mean);
-    else field = f;
+    field = gauss ? mfield : f;   // the Gaussian mode's observation operator is frozen at the prior mean
     TRY(upload(ctx, &ctx->d_fhat, field));
     StarsDev SD{};
     SD.n = n_stars; SD.xyz = ctx->d_xyz; SD.ptr = ctx->d_sptr; SD.nodes = ctx->d_snodes; SD.nsamp = ctx->d_nsamp;
     SD.g = ctx->d_g; SD.lnA = ctx->d_lnA; SD.c = ctx->d_c;
-    GridDev GD{g.n, g.h, g.obs[0], g.obs[1], g.obs[2]};
     launch_los(ctx->stream, GD, SD, ctx->d_fhat, cap);
     std::vector<double> lnA(n_stars), cc(n_stars), gv(ctx->sup.nodes.size());
     HIPCHK(hipMemcpyAsync(lnA.data(), ctx->d_lnA, sizeof(double) * n_stars, hipMemcpyDeviceToHost, ctx->stream));

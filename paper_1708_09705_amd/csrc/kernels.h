@@ -132,6 +132,31 @@ struct GridDev {
     double ox, oy, oz;
 };
 void launch_los(hipStream_t st, GridDev g, StarsDev s, const double* f, int max_support);
+
+// ---- inferred prior-mean parameters (theta.hip) ----
+constexpr int NTHETA = 5;        // (L, H, rho kappa_0, s_bump, A_bump)
+constexpr int DOT_BLOCKS = 256;  // blocks of the partial-sum kernels
+struct MeanDev {                 // disc + bump mean function at theta
+    double theta[NTHETA];
+    double R0, w;                // Galactocentric radius of the observer; bump width
+};
+struct Phi5 { double v[NTHETA]; };
+struct BorderDev {
+    double mu_phi[NTHETA];
+    double phihat[NTHETA];
+    double sinv[NTHETA * NTHETA];  // Sigma_phiphi = S^-1, row-major
+};
+void launch_mean_fn(hipStream_t st, GridDev g, MeanDev P, double* mhat, double* J, int64_t N);
+void launch_star_border(hipStream_t st, StarsDev s, const double* mhat, const double* J, Phi5 phihat, double* h,
+                        int64_t N);
+void launch_border_rhs(hipStream_t st, StarsDev s, const double* h, double* R, int64_t N);
+void launch_dots_5x6(hipStream_t st, const double* A, const double* B, int64_t n, double* part);
+void launch_star_sums(hipStream_t st, StarsDev s, const double* h, double* part);
+void launch_minus_w(hipStream_t st, const double* y, const double* W, Phi5 c, double* out, int64_t N);
+void launch_cavity_border(hipStream_t st, StarsDev s, const double* W, const double* h, BorderDev b, int64_t N);
+void launch_f_mean(hipStream_t st, const double* mhat, const double* J, const double* mu_d, BorderDev b, double* out,
+                   int64_t N);
+void launch_f_var(hipStream_t st, const double* W, const double* J, BorderDev b, double* var, int64_t N);
 void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int max_support);
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b);
 void launch_gather_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);

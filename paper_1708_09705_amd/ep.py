@@ -22,6 +22,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "NOT_PD", -4: "DEVICE", -5: "STATE",
 LIKELIHOOD = {"extinction": 0, "gauss_linear": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 MOMENTS = {"quadrature": 0, "surrogate": 1}
+MEAN_FN = {"constant": 0, "disc_bump": 1}
+N_THETA = 5
 
 
 class EPError(RuntimeError):
@@ -56,6 +58,10 @@ class ep_config(ctypes.Structure):
         ("mixed_fp64_levels", ctypes.c_int32),
         ("surrogate_tol", ctypes.c_double),
         ("pointers_on_device", ctypes.c_int32),
+        ("mean_fn", ctypes.c_int32),
+        ("theta_prior", ctypes.c_double * 5),
+        ("sun_radius_pc", ctypes.c_double),
+        ("bump_width_pc", ctypes.c_double),
     ]
 
 
@@ -81,7 +87,7 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
-           "ep_extinction_map", "ep_point_predict")
+           "ep_extinction_map", "ep_point_predict", "ep_theta")
 MLP_NPARAM = 34065
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
@@ -141,11 +147,12 @@ def load(path: str | None = None):
     L.ep_density_moments.argtypes = [vp, vp, vp]
     L.ep_extinction_map.argtypes = [vp, i32, vp, vp, vp]
     L.ep_point_predict.argtypes = [vp, i64, vp, vp]
+    L.ep_theta.argtypes = [vp, vp, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
-                 "ep_point_predict"):
+                 "ep_point_predict", "ep_theta"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -178,10 +185,14 @@ def make_config(fields: Mapping | None = None, lib=None, **kw) -> ep_config:
             v = PRECISION[v]
         elif k == "moments" and isinstance(v, str):
             v = MOMENTS[v]
+        elif k == "mean_fn" and isinstance(v, str):
+            v = MEAN_FN[v]
         elif k == "relinearize":
             v = int(bool(v))
         if k == "observer_pc":
             c.observer_pc = (ctypes.c_double * 3)(*v)
+        elif k == "theta_prior":
+            c.theta_prior = (ctypes.c_double * 5)(*v)
         elif k == "stream":
             c.stream = ctypes.c_void_p(int(v) if v else None)
         elif hasattr(c, k):
@@ -374,14 +385,26 @@ class EP:
         (kt, pt), (kn, pn) = self._in(tau, self.S), self._in(nu, self.S)
         _check(self.L, self.L.ep_set_sites(self.ctx, pt, pn), self.ctx)
 
+    @property
+    def n_lin(self) -> int:
+        """Length of the linearisation point: n^3, plus the 5 log-parameters
+        of an inferred mean."""
+        return self.N + (N_THETA if self.cfg.mean_fn == MEAN_FN["disc_bump"] else 0)
+
     def linpoint(self):
-        f, p = self._out(self.N)
+        f, p = self._out(self.n_lin)
         _check(self.L, self.L.ep_get_linpoint(self.ctx, p), self.ctx)
         return f
 
     def set_linpoint(self, f) -> None:
-        k, p = self._in(f, self.N)
+        k, p = self._in(f, self.n_lin)
         _check(self.L, self.L.ep_set_linpoint(self.ctx, p), self.ctx)
+
+    def theta(self):
+        """Posterior mean (5) and covariance (5 x 5) of phi = ln theta."""
+        (m, pm), (c, pc) = self._out(N_THETA), self._out((N_THETA, N_THETA))
+        _check(self.L, self.L.ep_theta(self.ctx, pm, pc), self.ctx)
+        return m, c
 
     def star_state(self) -> dict:
         keys = ("lnA", "cav_mu", "cav_var", "lnZ", "tilted_mean", "tilted_var")
