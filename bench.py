@@ -92,6 +92,9 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
                       "ms_per_copy": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+THETA_TRUE = (2500.0, 200.0, 1.2e-3, 1800.0, 0.15)   # (L, H, rho kappa_0, s_bump, A_bump) of the synthetic sky
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +108,8 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the surrogate + mixed-precision run (FP32 factor + FP64 refinement, "
                          "network moments with quadrature fallback)")
+    ap.add_argument("--no-theta", dest="theta", action="store_false",
+                    help="skip the sweeps with the inferred disc + bump prior mean")
     ap.add_argument("--no-maps", dest="maps", action="store_false",
                     help="skip timing the map predictions after the FP64 run")
     ap.add_argument("--mixed-quadrature", action="store_true",
@@ -171,11 +176,12 @@ def main():
                        "mean and var: exact mean plus the sample variance over the draws")
         return out
 
-    def run(prec, moments="quadrature", after=None):
+    def run(prec, moments="quadrature", after=None, A_in=None, extra=None):
         c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec,
-                          moments=moments)
+                          moments=moments, **(extra or {}))
+        A_run = A if A_in is None else A_in
         t0 = time.perf_counter()
-        g = E.EP(c, raw["xyz"], A, raw["sigma"])
+        g = E.EP(c, raw["xyz"], A_run, raw["sigma"])
         if moments == "surrogate":
             g.load_surrogate(weights)
         prec = f"{prec}/{moments}"
@@ -272,6 +278,31 @@ def main():
 
     if maps:
         line["maps"] = maps
+    if args.theta:
+        # Data drawn around a disc + bump mean at THETA_TRUE; EP infers the
+        # field and theta jointly from the Sec. 5 hyperprior means.
+        sim = E.make_config(w.ep_fields(), device=0, mean_fn="disc_bump", theta_prior=THETA_TRUE)
+        _, A_th = E.ep_simulate(sim, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+        thv = {}
+
+        def theta_after(g):
+            m, c = g.theta()
+            sd = np.sqrt(np.diag(c))
+            thv["theta_mean"] = [float(v) for v in np.exp(m + 0.5 * sd ** 2)]
+            thv["log_theta_sd"] = [float(v) for v in sd]
+            thv["z_true"] = [float(v) for v in (m - np.log(THETA_TRUE)) / sd]
+            return None
+
+        st_t, stats_t, wall_t, _, _, _ = run("fp64", A_in=A_th, after=theta_after, extra=dict(mean_fn="disc_bump"))
+        line["theta_leg"] = {
+            "value": S * args.steps / wall_t, "unit": "star-updates/s", "ms_per_step": wall_t / args.steps * 1e3,
+            "phases_ms": {k: float(np.mean([s[k] for s in stats_t])) for k in ph},
+            "theta_names": ["L_pc", "H_pc", "rho_kappa0_per_pc", "s_bump_pc", "A_bump_mag"],
+            "theta_true": list(THETA_TRUE), "theta_prior_mean": list(E.make_config().theta_prior),
+            **thv,
+            "note": ("field and phi = ln theta inferred jointly (five-column Schur border); theta_mean is the "
+                     "log-normal posterior mean after warm-up + timed sweeps"),
+        }
     if args.mixed:
         line["surrogate_mixed"] = leg("mixed", "surrogate")
         if args.mixed_quadrature:
