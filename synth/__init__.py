@@ -6,4 +6,4 @@ arithmetic: the prior draw of the true field and the line-of-sight extinction
 of each star are computed separately by the oracle and by the GPU library from
 the deviates drawn here.
 """
-from .workloads import Workload, preset, draw, PRESETS  # noqa: F401
+from .workloads import Workload, preset, draw, gmm_catalogue, PRESETS  # noqa: F401

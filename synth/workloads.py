@@ -14,7 +14,7 @@ Each preset fixes a grid, a prior and a star sample:
   observation noise (one per star).
 
 Seeds: numpy PCG64 with seed 17080000 + 100 * preset + {0 field, 1 positions,
-2 noise}.
+2 noise, 3 the synthetic distance-extinction mixtures}.
 """
 from __future__ import annotations
 
@@ -158,3 +158,46 @@ def draw(w: Workload, n_stars: int | None = None, field: bool = True) -> dict:
         rng_f = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * w.seed_id + 0))
         out["xi"] = rng_f.standard_normal(w.N)
     return out
+
+
+def gmm_catalogue(w: Workload, xyz_true: np.ndarray, a_true: np.ndarray, weight_main: float = 0.75,
+                  sd_l: float = 0.15, sd_b: float = 0.08, rho: float = 0.6,
+                  alias_l: float = math.log(2.5), alias_b: float = 0.25) -> dict:
+    """Synthetic per-star photometric likelihoods with unknown distance: a
+    two-component Gaussian mixture in (l, b) = (ln distance, log-extinction)
+    per star (the paper's real mixtures come from stellar models and are not
+    available).  The main component (weight weight_main) is centred on a
+    draw around the truth (l_true, a_true) with covariance
+    C = [[sd_l^2, rho sd_l sd_b], [., sd_b^2]]; the alias component is the
+    same shifted by (alias_l, alias_b), as for a dwarf / giant confusion.
+    The catalogue position is the true direction at the main component's
+    distance, pulled inside the cube.  a_true (the log-extinction at the true
+    position) is an input: this module does no extinction arithmetic.
+
+    Returns dict(xyz=(S, 3) catalogue positions, comps=(S, 2, 6) rows
+    (weight, m_l, m_b, C_ll, C_lb, C_bb))."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * w.seed_id + 3))
+    xyz_true = np.asarray(xyz_true, dtype=np.float64)
+    S = xyz_true.shape[0]
+    o = np.asarray(w.observer, dtype=np.float64)
+    dv = xyz_true - o
+    d = np.linalg.norm(dv, axis=1)
+    u = dv / d[:, None]
+    cll, clb, cbb = sd_l ** 2, rho * sd_l * sd_b, sd_b ** 2
+    z1 = rng.standard_normal(S)
+    z2 = rng.standard_normal(S)
+    nl = sd_l * z1
+    nb = sd_b * (rho * z1 + math.sqrt(1 - rho * rho) * z2)
+    comps = np.zeros((S, 2, 6))
+    comps[:, 0] = np.stack([np.full(S, weight_main), np.log(d) + nl, a_true + nb,
+                            np.full(S, cll), np.full(S, clb), np.full(S, cbb)], axis=1)
+    comps[:, 1] = comps[:, 0]
+    comps[:, 1, 0] = 1.0 - weight_main
+    comps[:, 1, 1] += alias_l
+    comps[:, 1, 2] += alias_b
+    # largest distance along u that stays in the cube
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tmax = np.where(u > 0, (w.box_pc - o) / u, np.where(u < 0, -o / u, np.inf))
+    dmax = np.min(tmax, axis=1)
+    dref = np.clip(np.exp(comps[:, 0, 1]), 1.0, 0.999 * dmax)
+    return dict(xyz=np.ascontiguousarray(o + u * dref[:, None]), comps=np.ascontiguousarray(comps))
