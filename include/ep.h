@@ -53,7 +53,7 @@ typedef enum {
     EP_ERR_NUMERIC = -6      /* non-finite value in the sites or the posterior */
 } ep_status;
 
-typedef enum { EP_LIK_EXTINCTION = 0, EP_LIK_GAUSS_LINEAR = 1 } ep_likelihood;
+typedef enum { EP_LIK_EXTINCTION = 0, EP_LIK_GAUSS_LINEAR = 1, EP_LIK_GMM = 2 } ep_likelihood;
 typedef enum { EP_PREC_FP64 = 0, EP_PREC_MIXED = 1 } ep_precision;
 typedef enum { EP_MOM_QUADRATURE = 0, EP_MOM_SURROGATE = 1 } ep_moments;
 typedef enum { EP_MEAN_CONSTANT = 0, EP_MEAN_DISC_BUMP = 1 } ep_mean_fn;
@@ -183,9 +183,11 @@ void ep_config_default(ep_config *cfg);
  * prior mean.  xyz: n_stars x 3 positions (pc, cube frame) at known
  * distances (Sec. 4.1); A_obs: observed extinction (mag; in the
  * gauss_linear mode the observed log-extinction); sigma: 1-sigma noise
- * (> 0).  Errors: INVALID_ARG (bad config, non-finite input, star outside
- * the cube or at the observer), OOM, DEVICE.  n_stars = 0 is allowed: the
- * posterior is then the prior. */
+ * (> 0).  With likelihood GMM (unknown distances) xyz are the catalogue
+ * positions, A_obs and sigma are unused (may be NULL) and ep_set_gmm must
+ * give the per-star mixtures before the first sweep.  Errors: INVALID_ARG
+ * (bad config, non-finite input, star outside the cube or at the observer),
+ * OOM, DEVICE.  n_stars = 0 is allowed: the posterior is then the prior. */
 int ep_init(const ep_config *cfg, int64_t n_stars, const double *xyz, const double *A_obs,
             const double *sigma, ep_ctx **out);
 
@@ -224,6 +226,21 @@ const char *ep_last_error(const ep_ctx *ctx);
  * replaces them (checkpoint / resume). */
 int ep_get_sites(ep_ctx *ctx, double *tau, double *nu);
 int ep_set_sites(ep_ctx *ctx, const double *tau, const double *nu);
+
+/* Unknown distances (Sec. 4.2 general case; likelihood GMM): per-star
+ * Gaussian mixtures over (l, b) = (ln distance / pc, log-extinction implied at
+ * that distance), K (1..8) components per star, comps n_stars x K x 6 rows
+ * (w, m_l, m_b, C_ll, C_lb, C_bb): weights >= 0 with a positive sum, C_bb > 0,
+ * C positive definite (or C_ll = C_lb = 0: the distance is known).  The
+ * distance is marginalised in the tilted distribution with the
+ * log-extinction linearised in ln s about the catalogue distance s~
+ * (beta_n = d ln A / d ln s = s~ e^{F(x_n)} / A_n at the current field);
+ * each component then gives a Gaussian likelihood in a_n with mean
+ * m_b - beta (m_l - ln s~) and variance C_bb - 2 beta C_lb + beta^2 C_ll, and
+ * the tilted moments are those of a Gaussian mixture.  May be called again
+ * (e.g. with another K).  Errors: INVALID_ARG, STATE (likelihood not GMM),
+ * OOM, DEVICE. */
+int ep_set_gmm(ep_ctx *ctx, int32_t K, const double *comps);
 
 /* Linearisation point: fhat (n^3 doubles), followed with mean_fn DISC_BUMP
  * by phihat, the 5 log-parameters about which the mean is linearised. */

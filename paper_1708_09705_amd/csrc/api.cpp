@@ -125,6 +125,9 @@ struct ep_ctx {
     double phihat[NTHETA] = {};                   // mean linearisation point
     BorderDev border{};                           // mu_phi, phihat, Sigma_phiphi of the last border solve
     double *d_mhat = nullptr, *d_J = nullptr, *d_h = nullptr, *d_R = nullptr, *d_Wb = nullptr, *d_part = nullptr;
+    // unknown distances (likelihood GMM): per-star mixtures (ep_set_gmm), beta_n, ln of the catalogue distance
+    int gmm_K = 0;
+    double *d_gmm = nullptr, *d_beta = nullptr, *d_lref = nullptr;
 
     std::vector<LevelPlan> levels;
     std::vector<TaskRange> trtri1, trtri1f, trtri2;   // per doubling stage (1f: FP32 factor copy)
@@ -604,7 +607,7 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
     }
     if (!(c->los_step_pc > 0)) { err = "los_step_pc must be > 0"; return EP_ERR_INVALID_ARG; }
     if (!(c->damping > 0 && c->damping <= 1)) { err = "damping must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
-    if (c->likelihood != EP_LIK_EXTINCTION && c->likelihood != EP_LIK_GAUSS_LINEAR) {
+    if (c->likelihood != EP_LIK_EXTINCTION && c->likelihood != EP_LIK_GAUSS_LINEAR && c->likelihood != EP_LIK_GMM) {
         err = "unknown likelihood";
         return EP_ERR_INVALID_ARG;
     }
@@ -632,7 +635,9 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
             err = "observer must lie in the cube";
             return EP_ERR_INVALID_ARG;
         }
-    if (S < 0 || (S > 0 && (!xyz || !A || !sig))) { err = "bad star arrays"; return EP_ERR_INVALID_ARG; }
+    const bool gmm = c->likelihood == EP_LIK_GMM;   // the mixtures come later (ep_set_gmm); A_obs, sigma unused
+    if (gmm && c->moments != EP_MOM_QUADRATURE) { err = "the distance mixture needs moments QUADRATURE"; return EP_ERR_INVALID_ARG; }
+    if (S < 0 || (S > 0 && (!xyz || (!gmm && (!A || !sig))))) { err = "bad star arrays"; return EP_ERR_INVALID_ARG; }
     for (int64_t s = 0; s < S; s++) {
         for (int a = 0; a < 3; a++)
             if (!std::isfinite(xyz[3 * s + a]) || xyz[3 * s + a] < 0 || xyz[3 * s + a] > c->box_pc) {
@@ -647,6 +652,7 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
                 return EP_ERR_INVALID_ARG;
             }
         }
+        if (gmm) continue;
         if (!std::isfinite(A[s])) { err = "A_obs of star " + std::to_string(s) + " is not finite"; return EP_ERR_INVALID_ARG; }
         if (!(sig[s] > 0) || !std::isfinite(sig[s])) {
             err = "sigma of star " + std::to_string(s) + " must be finite and > 0";
@@ -838,7 +844,21 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     TRY(upload(ctx, &ctx->d_bd, ctx->vec.d));
     for (double** p : {&ctx->d_u, &ctx->d_w, &ctx->d_r, &ctx->d_dx}) TRY(dev_alloc(ctx, p, N));
     // stars
-    std::vector<double> vx(xyz, xyz + 3 * S), vA(A, A + S), vs(sig, sig + S);
+    const bool gmm = c.likelihood == EP_LIK_GMM;   // A_obs and sigma unused (may be NULL)
+    std::vector<double> vx(xyz, xyz + 3 * S), vA((size_t)S, 0.0), vs((size_t)S, 1.0);
+    if (!gmm) {
+        std::copy(A, A + S, vA.begin());
+        std::copy(sig, sig + S, vs.begin());
+    } else {
+        std::vector<double> lref((size_t)S);
+        for (int64_t s = 0; s < S; s++) {
+            double d2 = 0;
+            for (int a = 0; a < 3; a++) d2 += (xyz[3 * s + a] - g.obs[a]) * (xyz[3 * s + a] - g.obs[a]);
+            lref[s] = 0.5 * std::log(d2);
+        }
+        TRY(upload(ctx, &ctx->d_lref, lref));
+        TRY(dev_alloc(ctx, &ctx->d_beta, S));
+    }
     TRY(upload(ctx, &ctx->d_xyz, vx));
     TRY(upload(ctx, &ctx->d_A, vA));
     TRY(upload(ctx, &ctx->d_sigma, vs));
@@ -919,18 +939,17 @@ static bool frozen(const ep_ctx* ctx) {
 // sightlines at fhat; with an inferred mean also the border projections
 // h_n = J^T g_n and c'_n (the mean linearised about phihat)
 static void enqueue_linearise(ep_ctx* ctx) {
+    const double* field = ctx->d_fhat;
     if (frozen(ctx)) {
         if (ctx->linearised) return;
         // freeze at the prior mean (m(mu0) with an inferred mean, held in fhat)
-        if (ctx->M) {
-            launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
-        } else {
+        if (!ctx->M) {
             launch_fill(ctx->stream, ctx->d_t, ctx->g.N(), ctx->pp.mean);
-            launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_t, ctx->max_support);
+            field = ctx->d_t;
         }
-    } else {
-        launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_fhat, ctx->max_support);
     }
+    launch_los(ctx->stream, ctx->GD, ctx->SD, field, ctx->max_support);
+    if (ctx->cfg.likelihood == EP_LIK_GMM) launch_beta(ctx->stream, ctx->GD, ctx->SD, field, ctx->d_beta);
     if (ctx->M) launch_star_border(ctx->stream, ctx->SD, ctx->d_mhat, ctx->d_J, phi5(ctx->phihat), ctx->d_h, ctx->g.N());
     ctx->linearised = true;
 }
@@ -1225,6 +1244,10 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         ctx->err = "surrogate moments need network weights (ep_mlp_load)";
         return EP_ERR_STATE;
     }
+    if (ctx->cfg.likelihood == EP_LIK_GMM && !ctx->gmm_K) {
+        ctx->err = "the distance-mixture likelihood needs the per-star mixtures (ep_set_gmm)";
+        return EP_ERR_STATE;
+    }
     const int64_t N = ctx->g.N(), S = ctx->S;
     hipEvent_t ev[8];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -1262,7 +1285,10 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     if (ctx->M) launch_cavity_border(st, ctx->SD, ctx->d_Wb, ctx->d_h, ctx->border, N);
     EpParams p{ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR ? 1 : 0, ctx->cfg.damping, ctx->cfg.cavity_var_floor};
     ctx->fallbacks = 0;
-    if (ctx->cfg.moments == EP_MOM_SURROGATE && p.mode == 0) {
+    if (ctx->cfg.likelihood == EP_LIK_GMM) {
+        p.mode = 2;
+        launch_gmm_update(st, ctx->SD, p, ctx->d_gmm, ctx->gmm_K, ctx->d_beta, ctx->d_lref);
+    } else if (ctx->cfg.moments == EP_MOM_SURROGATE && p.mode == 0) {
         // gated surrogate for every star, quadrature for the rejected ones
         HIPCHK(hipMemsetAsync(ctx->d_fb_count, 0, sizeof(int32_t), st));
         launch_mlp_tilted(st, ctx->SD, p, ctx->d_mlp_P, ctx->d_mlp_bf, ctx->cfg.surrogate_tol, ctx->d_fb_list,
@@ -1737,6 +1763,49 @@ int ep_set_sites(ep_ctx* ctx, const double* tau, const double* nu) {
     HIPCHK(hipMemcpyAsync(ctx->d_tau, tau, sizeof(double) * ctx->S, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->d_nu, nu, sizeof(double) * ctx->S, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return EP_OK;
+}
+
+int ep_set_gmm(ep_ctx* ctx, int32_t K, const double* comps) {
+    if (!ctx || (ctx->S > 0 && !comps) || K < 1 || K > 8) {
+        g_tls_err = "ep_set_gmm: bad arguments";
+        if (ctx) ctx->err = g_tls_err;
+        return EP_ERR_INVALID_ARG;
+    }
+    if (ctx->cfg.likelihood != EP_LIK_GMM) {
+        ctx->err = "ep_set_gmm: the context's likelihood is not GMM";
+        return EP_ERR_STATE;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    const int64_t n = ctx->S * K * 6;
+    std::vector<double> hc;
+    HIPCHK(host_view(ctx->cfg.pointers_on_device != 0, comps, n, hc));
+    for (int64_t s = 0; s < ctx->S; s++) {
+        double wsum = 0;
+        for (int z = 0; z < K; z++) {
+            const double* c = comps + (s * K + z) * 6;
+            for (int k = 0; k < 6; k++)
+                if (!std::isfinite(c[k])) { ctx->err = "ep_set_gmm: non-finite component"; return EP_ERR_INVALID_ARG; }
+            const bool ok = c[0] >= 0 && c[5] > 0 && c[3] >= 0 &&
+                            (c[3] * c[5] - c[4] * c[4] > 0 || (c[3] == 0 && c[4] == 0));
+            if (!ok) {
+                ctx->err = "ep_set_gmm: star " + std::to_string(s) +
+                           " needs weights >= 0 and covariances with C_bb > 0 that are positive definite";
+                return EP_ERR_INVALID_ARG;
+            }
+            wsum += c[0];
+        }
+        if (!(wsum > 0)) { ctx->err = "ep_set_gmm: star " + std::to_string(s) + " has no positive weight"; return EP_ERR_INVALID_ARG; }
+    }
+    if (ctx->gmm_K != K) {
+        if (ctx->d_gmm) {   // resize: the old buffer stays in the context's list until ep_free
+            ctx->d_gmm = nullptr;
+        }
+        TRY(dev_alloc(ctx, &ctx->d_gmm, n));
+    }
+    if (n > 0) HIPCHK(hipMemcpyAsync(ctx->d_gmm, comps, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->gmm_K = K;
     return EP_OK;
 }
 

@@ -166,10 +166,15 @@ void launch_diag(hipStream_t st, const int32_t* perm, const int32_t* snode, Fron
 void launch_cavity(hipStream_t st, StarsDev s, FrontsDev F, const double* fronts, const double* mu,
                    int max_support);
 struct EpParams {
-    int mode;          // 0 extinction, 1 gaussian
+    int mode;          // 0 extinction, 1 gaussian, 2 distance mixture
     double damping;
     double vfloor;
 };
+// unknown distances (gmm.hip): beta_n = d ln A / d ln s at the field f, and
+// the mixture tilted moments with the site update
+void launch_beta(hipStream_t st, GridDev g, StarsDev s, const double* f, double* beta);
+void launch_gmm_update(hipStream_t st, StarsDev s, EpParams p, const double* comps, int K, const double* beta,
+                       const double* lref);
 // list: optional subset of stars (nlist entries)
 void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p, const int32_t* list = nullptr, int64_t nlist = 0);
 void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libep.so")
 
 EP_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "NOT_PD", -4: "DEVICE", -5: "STATE", -6: "NUMERIC"}
-LIKELIHOOD = {"extinction": 0, "gauss_linear": 1}
+LIKELIHOOD = {"extinction": 0, "gauss_linear": 1, "gmm": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 MOMENTS = {"quadrature": 0, "surrogate": 1}
 MEAN_FN = {"constant": 0, "disc_bump": 1}
@@ -87,7 +87,7 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
-           "ep_extinction_map", "ep_point_predict", "ep_theta")
+           "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm")
 MLP_NPARAM = 34065
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
@@ -148,11 +148,12 @@ def load(path: str | None = None):
     L.ep_extinction_map.argtypes = [vp, i32, vp, vp, vp]
     L.ep_point_predict.argtypes = [vp, i64, vp, vp]
     L.ep_theta.argtypes = [vp, vp, vp]
+    L.ep_set_gmm.argtypes = [vp, i32, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
-                 "ep_point_predict", "ep_theta"):
+                 "ep_point_predict", "ep_theta", "ep_set_gmm"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -243,7 +244,8 @@ def ep_init(cfg: ep_config, xyz, A_obs, sigma, lib=None):
     L = lib or load()
     dev, d = bool(cfg.pointers_on_device), int(cfg.device)
     S = int(np.prod(tuple(xyz.shape))) // 3 if hasattr(xyz, "shape") else len(np.asarray(xyz).reshape(-1, 3))
-    keep = [_marshal_in(a, n, dev, d) for a, n in ((xyz, 3 * S), (A_obs, S), (sigma, S))]
+    keep = [_marshal_in(a, n, dev, d) if a is not None else (None, None)
+            for a, n in ((xyz, 3 * S), (A_obs, S), (sigma, S))]   # A_obs, sigma: None with the GMM likelihood
     out = ctypes.c_void_p()
     _check(L, L.ep_init(ctypes.byref(cfg), S, keep[0][1], keep[1][1], keep[2][1], ctypes.byref(out)))
     return out
@@ -350,7 +352,7 @@ class EP:
     """One EP context on the GPU.  With cfg pointers_on_device = 1 every
     array goes in and comes out as a tensor on cuda:device."""
 
-    def __init__(self, cfg: Mapping | ep_config, xyz, A_obs, sigma, lib=None):
+    def __init__(self, cfg: Mapping | ep_config, xyz, A_obs=None, sigma=None, lib=None):
         self.L = lib or load()
         self.cfg = cfg if isinstance(cfg, ep_config) else make_config(cfg, lib=self.L)
         self.N = self.cfg.n ** 3
@@ -399,6 +401,14 @@ class EP:
     def set_linpoint(self, f) -> None:
         k, p = self._in(f, self.n_lin)
         _check(self.L, self.L.ep_set_linpoint(self.ctx, p), self.ctx)
+
+    def set_gmm(self, comps) -> None:
+        """Per-star distance / log-extinction mixtures, (S, K, 6) rows
+        (w, m_l, m_b, C_ll, C_lb, C_bb), for the GMM likelihood."""
+        shape = tuple(comps.shape) if hasattr(comps, "shape") else np.asarray(comps).shape
+        K = int(np.prod(shape)) // (6 * self.S) if self.S else 1
+        k, p = self._in(comps, self.S * K * 6)
+        _check(self.L, self.L.ep_set_gmm(self.ctx, K, p), self.ctx)
 
     def theta(self):
         """Posterior mean (5) and covariance (5 x 5) of phi = ln theta."""
