@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -54,6 +55,7 @@ struct LevelPlan {
     //            takes the updates of all pivot columns.
     std::vector<TaskRange> panelT, finalT;
     Launch extend;              // also the Sigma-gather enumeration
+    std::vector<Launch> extend_groups;   // the same fronts, at most one child per parent in each group
     Launch conv;                // FP64 -> FP32 copy of the level's fronts (mixed precision)
     Launch fwd_xv, fwd_r, bwd_t, bwd_x;
     FList fronts;
@@ -411,6 +413,16 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             fr.emplace_back(f, MR);
         }
         P.extend = mk_launch(ea);
+        {   // group r: the r-th child (in this level) of every parent
+            std::map<int, int> rank;
+            std::vector<std::vector<std::pair<int, int64_t>>> groups;
+            for (auto& x : ea) {
+                const int r = rank[sym.fronts[x.first].parent]++;
+                if ((int)groups.size() <= r) groups.resize(r + 1);
+                groups[r].push_back(x);
+            }
+            for (auto& gv : groups) P.extend_groups.push_back(mk_launch(gv));
+        }
         std::vector<std::pair<int, int64_t>> cv;
         for (int f : lv[l]) cv.emplace_back(f, M_of(f));
         P.conv = mk_launch(cv);
@@ -1029,8 +1041,8 @@ static void enqueue_factor(ep_ctx* ctx) {
             launch_gemm_tasks(st, ctx->d_tasks + fu.off, fu.n, b, false);
             kt_end(ctx, fu.n, EP_KK_TRAIL);
         }
-        const Launch& e = P.extend;
-        launch_extend_add(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
+        for (const Launch& e : P.extend_groups)
+            launch_extend_add_plain(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);
     }
     for (size_t s = 0; s < ctx->trtri1.size(); s++) {
         for (const TaskRange* r : {&ctx->trtri1[s], &ctx->trtri1f[s]}) {

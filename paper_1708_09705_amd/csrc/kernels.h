@@ -88,6 +88,8 @@ void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
 void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+// the same with at most one child per parent in the launch: no atomics
+void launch_extend_add_plain(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 
 // solves (vectors in the new node order)

@@ -523,6 +523,10 @@ void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntas
 // parent's selected inverse into the child's R x R block (both triangles of
 // diagonal tiles, zeros on padding).
 // ---------------------------------------------------------------------------
+// ATOMIC: fronts of one launch may share a parent (FP64 atomic adds);
+// otherwise the launch holds at most one child per parent, whose rows map
+// injectively into the parent, so a plain read-add-write is race-free.
+template <bool ATOMIC>
 __global__ __launch_bounds__(256) void k_extend_add(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
                                                     FrontsDev F, Bufs bufs) {
     __shared__ int32_t rel_i[TS], rel_j[TS];
@@ -551,7 +555,9 @@ __global__ __launch_bounds__(256) void k_extend_add(const BatchEnt* __restrict__
     for (int q = threadIdx.x >> 6; q < TS; q += 4) {
         const int b = TS * tj + q;
         if (rel_j[q] < 0 || b > a) continue;
-        atomicAdd(dst + rel_i[r] + (int64_t)rel_j[q] * mp, src[a + (int64_t)b * m]);
+        double* d = dst + rel_i[r] + (int64_t)rel_j[q] * mp;
+        if (ATOMIC) atomicAdd(d, src[a + (int64_t)b * m]);
+        else *d += src[a + (int64_t)b * m];
     }
 }
 
@@ -596,7 +602,11 @@ __global__ __launch_bounds__(256) void k_sigma_gather(const BatchEnt* __restrict
 
 void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_extend_add, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+    hipLaunchKernelGGL(k_extend_add<true>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
+}
+void launch_extend_add_plain(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_extend_add<false>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
 }
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
