@@ -132,6 +132,7 @@ struct ep_ctx {
     double *d_gmm = nullptr, *d_beta = nullptr, *d_lref = nullptr;
 
     std::vector<LevelPlan> levels;
+    Launch zero_lower;                       // lower tiles of all fronts
     std::vector<TaskRange> trtri1, trtri1f, trtri2;   // per doubling stage (1f: FP32 factor copy)
     bool linearised = false;                 // g, c valid for the current fhat (frozen modes)
     std::vector<hipEvent_t> kt_ev;           // per-launch timing events (profile_kernels)
@@ -602,6 +603,11 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         ctx->trtri2.push_back(r2);
     }
     ctx->W_elems = std::max<int64_t>(std::max(Wmax, Tmax), 1);
+    {   // the lower-triangular 64 x 64 tiles of every front (the assembly's zeroing)
+        std::vector<std::pair<int, int64_t>> zl;
+        for (int f = 0; f < (int)sym.fronts.size(); f++) zl.emplace_back(f, (int64_t)M_of(f) * (M_of(f) + 1) / 2);
+        ctx->zero_lower = mk_launch(zl);
+    }
     return EP_OK;
 }
 
@@ -968,7 +974,10 @@ static void enqueue_linearise(ep_ctx* ctx) {
 
 static int enqueue_assemble(ep_ctx* ctx) {
     hipStream_t st = ctx->stream;
-    launch_fill(st, ctx->d_fronts, ctx->sym.total_elems, 0.0);
+    // Only the lower-triangular tiles of a front are assembled, accumulated
+    // into or read; the strictly upper tiles are left as they are.
+    launch_zero_lower(st, ctx->d_batches + ctx->zero_lower.be_off, ctx->zero_lower.nbe, ctx->zero_lower.ntasks, ctx->F,
+                      ctx->d_fronts);
     launch_scatter_set(st, ctx->d_fronts, ctx->d_q0_dest, ctx->d_q0_val, ctx->n_q0);
     launch_scatter_const(st, ctx->d_fronts, ctx->d_pad_dest, ctx->n_pad, 1.0);
     launch_assemble_stars(st, ctx->SD, ctx->F, ctx->d_fronts, ctx->max_support);

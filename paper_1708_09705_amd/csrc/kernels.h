@@ -91,6 +91,8 @@ void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntas
 // the same with at most one child per parent in the launch: no atomics
 void launch_extend_add_plain(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
+// zero the lower-triangular 64 x 64 tiles of the listed fronts
+void launch_zero_lower(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, double* fronts);
 
 // solves (vectors in the new node order)
 void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,

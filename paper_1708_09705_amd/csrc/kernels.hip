@@ -608,6 +608,26 @@ void launch_extend_add_plain(hipStream_t st, const BatchEnt* be, int nbe, int64_
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_extend_add<false>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
 }
+// one block per lower tile (ti >= tj) of a front; 16-byte stores down the columns
+__global__ __launch_bounds__(256) void k_zero_lower(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                    FrontsDev F, double* fronts) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntasks) return;
+    const int e = (int)batch_find(be, nbe, t);
+    const int f = be[e].front;
+    int ti, tj;
+    tri_decode(t - be[e].base, ti, tj);
+    const int64_t m = F.m[f];
+    double* base = fronts + F.off[f] + (int64_t)TS * ti + (int64_t)TS * tj * m;
+    const int r2 = (threadIdx.x & 31) * 2, c0 = threadIdx.x >> 5;
+#pragma unroll
+    for (int c = c0; c < TS; c += 8) *(double2*)(base + r2 + (int64_t)c * m) = make_double2(0.0, 0.0);
+}
+void launch_zero_lower(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, double* fronts) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(k_zero_lower, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, fronts);
+}
+
 void launch_sigma_gather(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_sigma_gather, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b);
