@@ -113,3 +113,25 @@ class DenseEPGMM(DenseEP):
         return dict(updated=int(good.sum()), skipped_cavity=int((~ok).sum()),
                     skipped_negsite=int((ok & ~good).sum()), beta=beta, cav_mu=mu_c, cav_var=v_c,
                     lnZ=lnZ, tilted_mean=mh, tilted_var=vh)
+
+
+class DenseEPThetaGMM:
+    """The inferred-mean EP (meanfn.DenseEPTheta) with the distance-mixture
+    likelihood: beta at the linearisation point fhat = m(phihat) + deltahat."""
+
+    def __new__(cls, cfg, xyz, comps, sightlines=None, vecchia=None):
+        from .meanfn import DenseEPTheta
+
+        class _Impl(DenseEPTheta):
+            def tilted_moments(self, mu_c, v_c):
+                beta = beta_at(self.cfg, self.xyz, self.fhat, self._lnA)
+                return gmm_tilted(mu_c, v_c, self.comps, beta, self.lref)
+
+        S = len(np.atleast_2d(xyz))
+        ep = _Impl(dict(cfg, likelihood="extinction"), xyz, np.zeros(S), np.ones(S), sightlines=sightlines,
+                   vecchia=vecchia)
+        ep.xyz = np.atleast_2d(np.asarray(xyz, dtype=np.float64))
+        ep.comps = np.asarray(comps, dtype=np.float64).reshape(S, -1, NCOMP)
+        o = np.asarray(cfg["observer_pc"], dtype=np.float64)
+        ep.lref = np.log(np.linalg.norm(ep.xyz - o, axis=1))
+        return ep

@@ -125,11 +125,17 @@ class DenseEPTheta(DenseEP):
     def augmented(self):
         """(Gx = [G, H], c') of the site variables a = c' + Gx (delta, phi)."""
         gval, lnA, c = self.linearisation()
+        self._lnA = lnA
         G = self.sl.G_dense(gval)
         m, J = self.mean_linearisation()
         H = G @ J
         cp = c + G @ m - H @ self.phihat
         return np.hstack([G, H]), cp
+
+    def tilted_moments(self, mu_c, v_c):
+        """The per-star tilted moments (the likelihood's; a subclass may
+        replace the likelihood)."""
+        return tilted(self.mode, mu_c, v_c, self.A_obs, self.sigma)
 
     def posterior_x(self):
         Gx, cp = self.augmented()
@@ -155,7 +161,7 @@ class DenseEPTheta(DenseEP):
         v_c = np.where(ok, np.maximum(1.0 / np.where(ok, tau_c, 1.0), self.vfloor), 1.0)
         mu_c = np.where(ok, nu_c / np.where(ok, tau_c, 1.0), 0.0)
         tau_c, nu_c = 1.0 / v_c, mu_c / v_c
-        lnZ, mh, vh = tilted(self.mode, mu_c, v_c, self.A_obs, self.sigma)
+        lnZ, mh, vh = self.tilted_moments(mu_c, v_c)
         tau_new = 1.0 / vh - tau_c
         nu_new = mh / vh - nu_c
         good = ok & np.isfinite(tau_new) & np.isfinite(nu_new) & (tau_new >= 0.0)

@@ -116,3 +116,36 @@ def test_config2_gmm_first_sweep_sites_sampled():
           flush=True)
     assert np.allclose(tau_g[idx], tau_o, rtol=1e-8)
     assert np.allclose(nu_g[idx], nu_o, rtol=1e-8, atol=1e-8)
+
+
+def test_gmm_with_inferred_mean_matches_oracle():
+    """Both widenings at once: the disc + bump mean inferred with the field,
+    and per-star distance mixtures."""
+    from paper_1708_09705_amd import ep as E
+    from oracle import meanfn
+    w = Workload("t", n=9, box_pc=1200.0, n_stars=200, sweeps=3, star_law="uniform", d_max_pc=1200.0,
+                 noise_law="const", noise_a=0.05, seed_id=33)
+    cfg = w.ep_fields()
+    cfg.update(sun_radius_pc=8000.0, bump_width_pc=200.0, theta_prior=(1500.0, 150.0, 7.5e-4, 600.0, 0.1))
+    raw = draw(w)
+    f_true, _, sl = meanfn.simulate(cfg, raw, (1000.0, 200.0, 1.2e-3, 500.0, 0.2))
+    _, lnA_true, _ = sl.linearise(f_true)
+    cat = gmm_catalogue(w, raw["xyz"], lnA_true)
+    ora = gmm.DenseEPThetaGMM(cfg, cat["xyz"], cat["comps"])
+    g = E.EP(dict(cfg, leaf_size=48, likelihood="gmm", mean_fn="disc_bump"), cat["xyz"])
+    g.set_gmm(cat["comps"])
+    for s in range(3):
+        so = ora.sweep()
+        sg = g.sweep()
+        tg, ng = g.sites()
+        print(f"sweep {s}: tau {relerr(tg, ora.tau):.2e} nu {relerr(ng, ora.nu):.2e} "
+              f"updated {sg['updated']}/{so['updated']}", flush=True)
+        assert sg["updated"] == so["updated"]
+        assert np.allclose(tg, ora.tau, rtol=1e-8, atol=1e-10)
+        assert np.allclose(ng, ora.nu, rtol=1e-8, atol=1e-8)
+    mo, vo = ora.posterior_mean(), ora.marginal_var()
+    assert relerr(g.posterior_mean(), mo) < 1e-8 and relerr(g.marginal_var(), vo) < 1e-8
+    pm_o, _ = ora.theta_posterior()
+    pm_g, _ = g.theta()
+    assert np.max(np.abs(pm_g - pm_o) / np.maximum(np.abs(pm_o), 1.0)) < 1e-8
+    g.close()

@@ -143,3 +143,30 @@ def test_synthetic_catalogue_is_consistent():
     u1 = (raw["xyz"] - o) / d[:, None]
     u2 = (cat["xyz"] - o) / np.linalg.norm(cat["xyz"] - o, axis=1)[:, None]
     assert np.allclose(u1, u2, atol=1e-12)
+
+
+def test_degenerate_mixture_with_inferred_mean_is_the_gaussian_theta_ep():
+    # the combined oracle (inferred disc + bump mean, mixture likelihood) with
+    # degenerate mixtures must give the inferred-mean EP with the Gaussian
+    # likelihood N(a; m_b, C_bb) (frozen linearisation in both)
+    from oracle import meanfn
+    w = Workload("t", n=7, box_pc=1200.0, n_stars=60, sweeps=2, star_law="uniform", d_max_pc=1200.0,
+                 noise_law="const", noise_a=0.05, likelihood="gauss_linear", seed_id=6)
+    cfg = dict(w.ep_fields(), relinearize=False, sun_radius_pc=8000.0, bump_width_pc=200.0,
+               theta_prior=(1500.0, 150.0, 7.5e-4, 600.0, 0.1))
+    raw = draw(w)
+    S = w.n_stars
+    o = np.asarray(cfg["observer_pc"])
+    comps = np.zeros((S, 1, 6))
+    comps[:, 0, 0] = 1.0
+    comps[:, 0, 1] = np.log(np.linalg.norm(raw["xyz"] - o, axis=1))
+    comps[:, 0, 2] = -1.0 + 0.3 * raw["eps"]
+    comps[:, 0, 3] = 1e-300
+    comps[:, 0, 5] = raw["sigma"] ** 2
+    a = gmm.DenseEPThetaGMM(cfg, raw["xyz"], comps)
+    b = meanfn.DenseEPTheta(cfg, raw["xyz"], comps[:, 0, 2], raw["sigma"])
+    for _ in range(2):
+        a.sweep()
+        b.sweep()
+        assert np.allclose(a.tau, b.tau, rtol=1e-12) and np.allclose(a.nu, b.nu, rtol=1e-12, atol=1e-12)
+    assert np.allclose(a.theta_posterior()[0], b.theta_posterior()[0], rtol=1e-12)
