@@ -1,0 +1,178 @@
+"""PITC / PIC block EP over inducing values, plain dense FP64.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests and the benchmark's CPU leg,
+never by the library.
+
+What it computes (Sale & Magorrian, arXiv:1708.09705):
+
+* Sec. 4.1 (simplified case): stars are split into sub-catalogues k; the
+  observed log-extinctions are Gaussian, a~_n | a_n ~ N(a_n, sigma_n^2); the
+  joint prior of (a, u) is approximated by PITC, blocks independent given the
+  values u of the field at R inducing points (App. A.1);
+* EP over u with one Gaussian site per sub-catalogue (Sec. 4.1 algorithm,
+  App. A.2 parallel form), the tilted distribution built as in App. B:
+  p(u | a~_k) = N(m'_k, C'_k) times the reduced cavity;
+* the PIC predictive of the field at the grid nodes, node by node from the
+  block it is assigned to (App. A.1 PIC, App. C), integrated over q(u);
+* the PITC log marginal likelihood ln p(a~) (App. A.1).
+
+The field and the data are the library's: f = ln(rho kappa) at the grid nodes
+with prior N(m0 1, K), K the tapered Matern covariance between nodes, and a_n =
+c_n + g_n . f, the sightline linearised at the prior mean (the gauss_linear
+likelihood), so a and u are jointly Gaussian: mu_k = c_k + G_k m0 1, Sigma_k =
+G_k K G_k^T, rho_k = G_k K[:, u], C = K[u, u], m = m0 1.
+
+Readings (where the paper is silent or garbled):
+
+* App. B prints C'_k with a plus sign and rho_n^T; the Gaussian conditional
+  covariance is C - rho_k^T (Sigma_k + S_k)^{-1} rho_k, used here (and the
+  mean term rho_k^T (.)^{-1} (a~_k - mu_k)).  The same holds for C'_{-k}.
+* The hyper-parameters Theta are fixed (no site carries Theta), so the
+  reduced cavity is a Gaussian in u alone, kept in natural parameters (it is
+  improper before every site has been set once); each block's tilted
+  distribution is then Gaussian and one undamped parallel sweep reaches the
+  fixed point.
+* The predictive integrates over q(u) rather than each block's tilted
+  distribution; App. C replaces one by the other at convergence, and for this
+  model they are equal at the fixed point.
+* sigma_n is a standard deviation (S_k = diag sigma_k^2).
+
+The linear algebra is the plain definition (dense numpy inverse/solve); use it
+on small grids only.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import epo
+
+
+def node_cov(cfg: dict) -> np.ndarray:
+    """K[i, j] = C(|x_i - x_j|) W(|x_i - x_j|) between all grid nodes."""
+    g = epo.Grid(cfg)
+    n = g.n
+    p = np.arange(g.N)
+    ijk = np.stack([p % n, (p // n) % n, p // (n * n)], axis=1).astype(np.int64)
+    d2 = ((ijk[:, None, :] - ijk[None, :, :]) ** 2).sum(axis=2)
+    uniq, inv = np.unique(d2, return_inverse=True)
+    var, ell, rs = float(cfg["prior_var"]), float(cfg["outer_scale_pc"]), float(cfg["support_pc"])
+    vals = np.array([epo.cov(var, ell, rs, g.h * math.sqrt(float(u))) for u in uniq])
+    return vals[inv].reshape(g.N, g.N)
+
+
+class DensePITC:
+    """State: the natural parameters (Lam_k, eta_k) of every block's site on u.
+
+    blocks: sub-catalogue of every star (0..K-1); inducing: node ids of u;
+    node_block: the block each node's prediction conditions on."""
+
+    def __init__(self, cfg: dict, xyz, a_obs, sigma, blocks, inducing, node_block=None,
+                 sightlines: epo.Sightlines | None = None, K: np.ndarray | None = None):
+        self.cfg = dict(cfg)
+        self.m0 = float(cfg["prior_mean"])
+        self.sl = sightlines or epo.Sightlines(cfg, xyz)
+        self.grid = self.sl.grid
+        N = self.grid.N
+        self.K = node_cov(cfg) if K is None else K
+        gval, _, c = self.sl.linearise(np.full(N, self.m0))
+        self.G = self.sl.G_dense(gval)
+        self.a_obs = np.asarray(a_obs, dtype=np.float64)
+        self.s2 = np.asarray(sigma, dtype=np.float64) ** 2
+        self.mu_a = c + self.G @ np.full(N, self.m0)
+        self.blocks = np.asarray(blocks)
+        self.nblk = int(self.blocks.max()) + 1 if self.blocks.size else 0
+        self.members = [np.nonzero(self.blocks == k)[0] for k in range(self.nblk)]
+        self.u = np.asarray(inducing, dtype=np.int64)
+        self.node_block = None if node_block is None else np.asarray(node_block)
+        R = len(self.u)
+        self.m_u = np.full(R, self.m0)
+        self.C = self.K[np.ix_(self.u, self.u)]
+        self.Cinv = np.linalg.inv(self.C) if R else np.zeros((0, 0))
+        self.Lam = np.zeros((self.nblk, R, R))
+        self.eta = np.zeros((self.nblk, R))
+
+    # -- the Gaussian pieces of App. B --------------------------------------
+    def block_joint(self, k):
+        """(mu_k, Sigma_k + S_k, rho_k) of (a~_k, u)."""
+        idx = self.members[k]
+        Gk = self.G[idx]
+        Sig = Gk @ self.K @ Gk.T + np.diag(self.s2[idx])
+        rho = Gk @ self.K[:, self.u]
+        return self.mu_a[idx], Sig, rho
+
+    def u_given_block(self, k):
+        """p(u | a~_k) = N(m'_k, C'_k) (App. B, minus sign in C'_k)."""
+        idx = self.members[k]
+        mu, A, rho = self.block_joint(k)
+        Ainv = np.linalg.inv(A)
+        m1 = self.m_u + rho.T @ Ainv @ (self.a_obs[idx] - mu)
+        C1 = self.C - rho.T @ Ainv @ rho
+        return m1, 0.5 * (C1 + C1.T)
+
+    # -- EP -------------------------------------------------------------------
+    def sweep(self, damping: float = 1.0):
+        """One parallel pass: every block from the same q (App. A.2).
+
+        For block k: reduced cavity q'_{-k} = prod_{l != k} q_l; tilted
+        q_{\\k} proportional to q'_{-k}(u) p(u | a~_k) (the q-bar_k of App. B);
+        the new site is the tilted divided by the full cavity p(u) q'_{-k};
+        damped in natural parameters."""
+        Lam_tot, eta_tot = self.Lam.sum(axis=0), self.eta.sum(axis=0)
+        new_L, new_e = np.zeros_like(self.Lam), np.zeros_like(self.eta)
+        for k in range(self.nblk):
+            m1, C1 = self.u_given_block(k)
+            C1inv = np.linalg.inv(C1)
+            Lc, ec = Lam_tot - self.Lam[k], eta_tot - self.eta[k]          # reduced cavity
+            Lbar, ebar = C1inv + Lc, C1inv @ m1 + ec                        # q-bar_k
+            new_L[k] = Lbar - (self.Cinv + Lc)                              # tilted / cavity
+            new_e[k] = ebar - (self.Cinv @ self.m_u + ec)
+        d = float(damping)
+        self.Lam = (1.0 - d) * self.Lam + d * new_L
+        self.eta = (1.0 - d) * self.eta + d * new_e
+
+    def posterior_u(self):
+        """(mean, cov) of q(u) = p(u) prod_k q_k(u)."""
+        P = self.Cinv + self.Lam.sum(axis=0)
+        V = np.linalg.inv(P)
+        V = 0.5 * (V + V.T)
+        return V @ (self.Cinv @ self.m_u + self.eta.sum(axis=0)), V
+
+    def log_evidence(self) -> float:
+        """ln p(a~) under PITC: a~ ~ N(mu, Q + S) with Q = rho C^{-1} rho^T
+        off the diagonal blocks and Sigma_k on them (App. A.1)."""
+        S = len(self.a_obs)
+        rho = self.G @ self.K[:, self.u]
+        Q = rho @ self.Cinv @ rho.T
+        for k in range(self.nblk):
+            idx = self.members[k]
+            Q[np.ix_(idx, idx)] = self.G[idx] @ self.K @ self.G[idx].T
+        Q += np.diag(self.s2)
+        r = self.a_obs - self.mu_a
+        sign, logdet = np.linalg.slogdet(Q)
+        return float(-0.5 * (S * math.log(2 * math.pi) + logdet + r @ np.linalg.solve(Q, r)))
+
+    # -- prediction -------------------------------------------------------------
+    def predict(self):
+        """PIC predictive (mean, var) of f at every node: f_p | a~_i, u from the
+        joint Gaussian of (f_p, a~_i, u), i = node_block[p], integrated over
+        q(u) (App. A.1 PIC, App. C)."""
+        N = self.grid.N
+        mean, var = np.zeros(N), np.zeros(N)
+        mu_u, V_u = self.posterior_u()
+        R = len(self.u)
+        for i in range(self.nblk):
+            nodes = np.nonzero(self.node_block == i)[0]
+            if nodes.size == 0:
+                continue
+            idx = self.members[i]
+            mu, A, rho = self.block_joint(i)
+            J = np.block([[A, rho], [rho.T, self.C]])
+            kst = np.vstack([self.G[idx] @ self.K[:, nodes], self.K[np.ix_(self.u, nodes)]])
+            w = np.linalg.solve(J, kst)
+            wa, wu = w[: len(idx)], w[len(idx):]
+            mean[nodes] = self.m0 + wa.T @ (self.a_obs[idx] - mu) + wu.T @ (mu_u - self.m_u)
+            var[nodes] = (np.diag(self.K)[nodes] - np.einsum("ij,ij->j", kst, w)
+                          + np.einsum("ij,ij->j", wu, V_u @ wu))
+        return mean, var

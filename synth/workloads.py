@@ -201,3 +201,46 @@ def gmm_catalogue(w: Workload, xyz_true: np.ndarray, a_true: np.ndarray, weight_
     dmax = np.min(tmax, axis=1)
     dref = np.clip(np.exp(comps[:, 0, 1]), 1.0, 0.999 * dmax)
     return dict(xyz=np.ascontiguousarray(o + u * dref[:, None]), comps=np.ascontiguousarray(comps))
+
+
+def sky_cells(w: Workload, xyz: np.ndarray, n_lon: int, n_lat: int) -> np.ndarray:
+    """On-sky cell of each point, as the sub-catalogue partition (Sec. 4.1):
+    equal-angle cells in longitude (-90, 90) deg about the +y axis and in
+    latitude (-b_max, b_max), cell = i_lon * n_lat + i_lat, points outside
+    the latitude band clamped to the nearest cell (the observer itself to
+    latitude 0)."""
+    o = np.asarray(w.observer)
+    v = np.asarray(xyz, dtype=np.float64) - o
+    d = np.sqrt((v ** 2).sum(axis=1))
+    lon = np.degrees(np.arctan2(v[:, 0], v[:, 1]))
+    lat = np.degrees(np.arcsin(np.divide(v[:, 2], d, out=np.zeros_like(d), where=d > 0)))
+    il = np.clip(np.floor((lon + 90.0) / 180.0 * n_lon), 0, n_lon - 1).astype(np.int64)
+    bm = w.b_max_deg
+    ib = np.clip(np.floor((lat + bm) / (2 * bm) * n_lat), 0, n_lat - 1).astype(np.int64)
+    return (il * n_lat + ib).astype(np.int32)
+
+
+def node_positions(w: Workload) -> np.ndarray:
+    p = np.arange(w.N)
+    return np.stack([p % w.n, (p // w.n) % w.n, p // (w.n * w.n)], axis=1) * w.h
+
+
+def boundary_inducing(w: Workload, n_lon: int, n_lat: int, dists_pc) -> np.ndarray:
+    """Inducing points on the sub-catalogue boundaries at fixed distances
+    (Sec. 5 places them on the boundaries between sub-catalogues at 1-4 kpc):
+    the corner directions of the on-sky cells times each distance, snapped
+    to the nearest grid node; points outside the cube dropped, duplicates
+    removed (sorted node ids)."""
+    o = np.asarray(w.observer)
+    lons = np.radians(np.linspace(-90.0, 90.0, n_lon + 1))
+    lats = np.radians(np.linspace(-w.b_max_deg, w.b_max_deg, n_lat + 1))
+    pts = []
+    for d in dists_pc:
+        for lo in lons:
+            for la in lats:
+                pts.append(o + d * np.array([math.cos(la) * math.sin(lo), math.cos(la) * math.cos(lo), math.sin(la)]))
+    pts = np.array(pts)
+    inside = np.all((pts >= 0.0) & (pts <= w.box_pc), axis=1)
+    ijk = np.rint(pts[inside] / w.h).astype(np.int64)
+    ids = ijk[:, 0] + w.n * (ijk[:, 1] + w.n * ijk[:, 2])
+    return np.unique(ids).astype(np.int32)

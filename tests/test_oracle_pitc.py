@@ -1,0 +1,176 @@
+"""Pins of the PITC / PIC block-EP oracle against what the mathematics fixes.
+
+The oracle follows App. B in covariance form (conditionals through
+(Sigma_k + S_k)^{-1}); every reference below is computed another way: the
+information form K^{-1} + G^T S^{-1} G of the exact Gaussian posterior, the
+determinant lemma, and the Snelson-Ghahramani closed form of the PITC
+posterior (Woodbury in the other direction)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import epo, pitc
+from synth import Workload, draw
+from synth.workloads import node_positions, sky_cells
+
+
+def _case(n=6, L=500.0, stars=60, n_lon=3, n_lat=1, R=12, seed=5, law="uniform"):
+    w = Workload("pitc", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law=law, d_max_pc=L,
+                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood="gauss_linear", seed_id=seed)
+    cfg = w.ep_fields()
+    raw = draw(w)
+    f_true, a_obs, sl = epo.simulate(cfg, raw)
+    blocks = sky_cells(w, raw["xyz"], n_lon, n_lat)
+    node_block = sky_cells(w, node_positions(w), n_lon, n_lat)
+    rng = np.random.default_rng(seed)
+    u = np.sort(rng.choice(w.N, size=R, replace=False)) if R < w.N else np.arange(w.N)
+    return w, cfg, raw, a_obs, sl, blocks, node_block, u
+
+
+def _exact(o):
+    """Exact GP posterior of f from all stars, information form."""
+    S = o.s2
+    Kinv = np.linalg.inv(o.K)
+    P = Kinv + o.G.T @ (o.G / S[:, None])
+    V = np.linalg.inv(P)
+    m = np.full(o.grid.N, o.m0)
+    mean = m + V @ (o.G.T @ ((o.a_obs - o.mu_a) / S))
+    return mean, 0.5 * (V + V.T), P, Kinv
+
+
+def _exact_lnZ(o, P):
+    """ln N(a~; mu, G K G^T + S) by the determinant lemma and Woodbury."""
+    S = o.s2
+    r = o.a_obs - o.mu_a
+    _, ldP = np.linalg.slogdet(P)
+    _, ldK = np.linalg.slogdet(o.K)
+    logdet = ldP + ldK + np.log(S).sum()
+    t = o.G.T @ (r / S)
+    quad = r @ (r / S) - t @ np.linalg.solve(P, t)
+    return -0.5 * (len(r) * math.log(2 * math.pi) + logdet + quad)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_u_given_block_matches_information_form():
+    w, cfg, raw, a, sl, blocks, nb, u = _case(R=15)
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    Kinv = np.linalg.inv(o.K)
+    for k in range(o.nblk):
+        idx = o.members[k]
+        Gk = o.G[idx]
+        P = Kinv + Gk.T @ (Gk / o.s2[idx][:, None])
+        V = np.linalg.inv(P)
+        mean = o.m0 + V @ (Gk.T @ ((a[idx] - o.mu_a[idx]) / o.s2[idx]))
+        m1, C1 = o.u_given_block(k)
+        assert _rel(m1, mean[u]) < 1e-9
+        assert _rel(C1, V[np.ix_(u, u)]) < 1e-9
+        # the conditional covariance shrinks: C - C'_k is positive semi-definite
+        assert np.linalg.eigvalsh(o.C - C1).min() > -1e-12
+
+
+def test_one_block_is_the_exact_gp():
+    w, cfg, raw, a, sl, blocks, nb, u = _case(n_lon=1, R=10)
+    assert blocks.max() == 0
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    mean, V, P, _ = _exact(o)
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, mean[u]) < 1e-9 and _rel(V_u, V[np.ix_(u, u)]) < 1e-9
+    pm, pv = o.predict()
+    assert _rel(pm, mean) < 1e-9 and _rel(pv, np.diag(V)) < 1e-8
+    assert abs(o.log_evidence() - _exact_lnZ(o, P)) < 1e-8 * abs(_exact_lnZ(o, P))
+
+
+def test_every_node_inducing_is_exact_for_any_blocking():
+    w, cfg, raw, a, sl, blocks, nb, u = _case(n=5, stars=50, n_lon=4, n_lat=2, R=125)
+    assert blocks.max() >= 3 and len(u) == w.N
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    mean, V, P, _ = _exact(o)
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, mean) < 1e-8 and _rel(V_u, V) < 1e-7
+    pm, pv = o.predict()
+    assert _rel(pm, mean) < 1e-8 and _rel(pv, np.diag(V)) < 1e-6
+    assert abs(o.log_evidence() - _exact_lnZ(o, P)) < 1e-8 * abs(_exact_lnZ(o, P))
+
+
+def test_sweep_gives_the_pitc_closed_form():
+    """Snelson & Ghahramani: Sigma_u = C (C + rho^T Lam^{-1} rho)^{-1} C,
+    mu_u = m + C (C + rho^T Lam^{-1} rho)^{-1} rho^T Lam^{-1} r with
+    Lam = blockdiag(Sigma_k + S_k - rho_k C^{-1} rho_k^T)."""
+    w, cfg, raw, a, sl, blocks, nb, u = _case(stars=80, n_lon=3, n_lat=2, R=20, seed=8)
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    S = len(a)
+    rho = o.G @ o.K[:, u]
+    Lam = np.zeros((S, S))
+    for k in range(o.nblk):
+        idx = o.members[k]
+        Gk = o.G[idx]
+        Lam[np.ix_(idx, idx)] = (Gk @ o.K @ Gk.T + np.diag(o.s2[idx])
+                                 - rho[idx] @ np.linalg.solve(o.C, rho[idx].T))
+    M = o.C + rho.T @ np.linalg.solve(Lam, rho)
+    r = a - o.mu_a
+    V_ref = o.C @ np.linalg.solve(M, o.C)
+    m_ref = o.m_u + o.C @ np.linalg.solve(M, rho.T @ np.linalg.solve(Lam, r))
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, m_ref) < 1e-9 and _rel(V_u, V_ref) < 1e-8
+    # evidence: |Lam + rho C^-1 rho^T| = |Lam| |M| / |C|, quadratic form by Woodbury
+    _, l1 = np.linalg.slogdet(Lam)
+    _, l2 = np.linalg.slogdet(M)
+    _, l3 = np.linalg.slogdet(o.C)
+    t = rho.T @ np.linalg.solve(Lam, r)
+    quad = r @ np.linalg.solve(Lam, r) - t @ np.linalg.solve(M, t)
+    ref = -0.5 * (S * math.log(2 * math.pi) + l1 + l2 - l3 + quad)
+    assert abs(o.log_evidence() - ref) < 1e-9 * abs(ref)
+
+
+def test_damped_sweeps_and_the_fixed_point():
+    w, cfg, raw, a, sl, blocks, nb, u = _case(stars=50, n_lon=2, n_lat=2, R=10, seed=9)
+    full = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    full.sweep(1.0)
+    L1, e1 = full.Lam.copy(), full.eta.copy()
+    full.sweep(1.0)                                    # already at the fixed point
+    assert _rel(full.Lam, L1) < 1e-12 and _rel(full.eta, e1) < 1e-11
+    half = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl, K=full.K)
+    for t in range(1, 4):
+        half.sweep(0.5)
+        c = 1.0 - 0.5 ** t
+        assert _rel(half.Lam, c * L1) < 1e-10 and _rel(half.eta, c * e1) < 1e-10
+
+
+def test_no_inducing_points_is_the_local_gp():
+    """R = 0: blocks independent (the local-GP special case, Sec. 4.1)."""
+    w, cfg, raw, a, sl, blocks, nb, u = _case(stars=60, n_lon=3, n_lat=1, R=0, seed=4)
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u[:0], nb, sightlines=sl)
+    o.sweep()
+    Kinv = np.linalg.inv(o.K)
+    pm, pv = o.predict()
+    ref = 0.0
+    for k in range(o.nblk):
+        idx = o.members[k]
+        Gk = o.G[idx]
+        P = Kinv + Gk.T @ (Gk / o.s2[idx][:, None])
+        V = np.linalg.inv(P)
+        mean = o.m0 + V @ (Gk.T @ ((a[idx] - o.mu_a[idx]) / o.s2[idx]))
+        nodes = nb == k
+        assert _rel(pm[nodes], mean[nodes]) < 1e-9 and _rel(pv[nodes], np.diag(V)[nodes]) < 1e-8
+        A = Gk @ o.K @ Gk.T + np.diag(o.s2[idx])
+        r = a[idx] - o.mu_a[idx]
+        ref += -0.5 * (len(idx) * math.log(2 * math.pi) + np.linalg.slogdet(A)[1] + r @ np.linalg.solve(A, r))
+    assert abs(o.log_evidence() - ref) < 1e-9 * abs(ref)
+
+
+def test_paper_sign_of_the_conditional_covariance_fails():
+    """The printed '+' in C'_k would give a covariance larger than the prior's,
+    contradicting the information-form conditional pinned above."""
+    w, cfg, raw, a, sl, blocks, nb, u = _case(R=8)
+    o = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    mu, A, rho = o.block_joint(0)
+    plus = o.C + rho.T @ np.linalg.solve(A, rho)
+    _, C1 = o.u_given_block(0)
+    assert np.trace(plus) > np.trace(o.C) > np.trace(C1)
