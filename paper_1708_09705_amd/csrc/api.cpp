@@ -18,6 +18,7 @@
 
 #include "../../include/ep.h"
 #include "kernels.h"
+#include "pitc.h"
 #include "prior.h"
 #include "surrogate.h"
 #include "symbolic.h"
@@ -115,7 +116,7 @@ struct ep_ctx {
     int32_t *d_fb_list = nullptr, *d_fb_count = nullptr;
     // map prediction (allocated at first use)
     int32_t *d_iperm = nullptr, *d_mapT = nullptr;
-    double *d_cellS = nullptr, *d_fk = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_mapmean = nullptr;
+    double *d_cellS = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_mapmean = nullptr;
     double* d_pts = nullptr;
     int64_t pts_cap = 0;
     int* d_mapbad = nullptr;
@@ -130,6 +131,10 @@ struct ep_ctx {
     // unknown distances (likelihood GMM): per-star mixtures (ep_set_gmm), beta_n, ln of the catalogue distance
     int gmm_K = 0;
     double *d_gmm = nullptr, *d_beta = nullptr, *d_lref = nullptr;
+    // multi-vector solves (border columns, batches of posterior draws): MR_MAX x N each, at first use
+    double *d_ymr = nullptr, *d_tmr = nullptr, *d_xmr = nullptr, *d_omr = nullptr;
+    // PITC sub-catalogue pass (ep_pitc_setup)
+    PitcState* pitc = nullptr;
 
     std::vector<LevelPlan> levels;
     Launch zero_lower;                       // lower tiles of all fronts
@@ -1088,6 +1093,47 @@ static void enqueue_tri_solve(ep_ctx* ctx, double* out) {
     launch_scatter_perm(st, ctx->d_perm, ctx->d_x, out, ctx->g.N());
 }
 
+static int ensure_mr(ep_ctx* ctx) {
+    if (ctx->d_ymr) return EP_OK;
+    const int64_t N = ctx->g.N();
+    for (double** p : {&ctx->d_ymr, &ctx->d_tmr, &ctx->d_xmr, &ctx->d_omr}) TRY(dev_alloc(ctx, p, MR_MAX * N));
+    return EP_OK;
+}
+
+// backward half for nrhs <= MR_MAX vectors: x = L^{-T} z with the columns of
+// z (elimination order, leading dimension N) in d_ymr; x to out (node order,
+// leading dimension N).  Each tile of the factor is read once per batch.
+static void enqueue_bwd_mr(ep_ctx* ctx, int nrhs, double* out) {
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->g.N();
+    for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
+        auto& P = ctx->levels[l];
+        Bufs b = level_bufs(ctx, l);
+        launch_bwd_t_mr(st, ctx->d_batches + P.bwd_t.be_off, P.bwd_t.nbe, P.bwd_t.ntasks, ctx->F, b, ctx->d_ymr,
+                        ctx->d_xmr, ctx->d_tmr, nrhs, N);
+        launch_bwd_x_mr(st, ctx->d_batches + P.bwd_x.be_off, P.bwd_x.nbe, P.bwd_x.ntasks, ctx->F, b, ctx->d_tmr,
+                        ctx->d_xmr, nrhs, N);
+    }
+    launch_scatter_perm_mr(st, ctx->d_perm, ctx->d_xmr, N, out, N, nrhs, N);
+}
+
+// L L^T X = Y for nrhs <= MR_MAX columns of Y in d_ymr (elimination order,
+// consumed); X to out (node order), leading dimension N throughout
+static void enqueue_tri_solve_mr(ep_ctx* ctx, int nrhs, double* out) {
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->g.N();
+    for (int lvl = 0; lvl < (int)ctx->levels.size(); lvl++) {
+        auto& P = ctx->levels[lvl];
+        Bufs b = level_bufs(ctx, lvl);
+        launch_fwd_xv_mr(st, ctx->d_batches + P.fwd_xv.be_off, P.fwd_xv.nbe, P.fwd_xv.ntasks, ctx->F, b, ctx->d_ymr,
+                         ctx->d_tmr, nrhs, N);
+        launch_fwd_r_mr(st, ctx->d_batches + P.fwd_r.be_off, P.fwd_r.nbe, P.fwd_r.ntasks, ctx->F, b, ctx->d_tmr,
+                        ctx->d_ymr, nrhs, N);
+        launch_copy_v_mr(st, ctx->d_flists + P.fronts.off, P.fronts.n, ctx->F, ctx->d_tmr, ctx->d_ymr, nrhs, N);
+    }
+    enqueue_bwd_mr(ctx, nrhs, out);
+}
+
 static double host_norm(const std::vector<double>& v) {
     double s = 0;
     for (double x : v) s += x * x;
@@ -1167,10 +1213,10 @@ static int border_solve(ep_ctx* ctx) {
     constexpr int NP = NTHETA * (NTHETA + 1), NS = NTHETA * (NTHETA + 1) / 2 + NTHETA;
     launch_fill(st, ctx->d_R, NTHETA * N, 0.0);
     launch_border_rhs(st, ctx->SD, ctx->d_h, ctx->d_R, N);
-    for (int j = 0; j < NTHETA; j++) {
-        launch_gather_perm(st, ctx->d_perm, ctx->d_R + j * N, ctx->d_y, N);
-        enqueue_tri_solve(ctx, ctx->d_Wb + j * N);
-    }
+    static_assert(NTHETA <= MR_MAX, "the border columns are solved as one batch");
+    TRY(ensure_mr(ctx));
+    launch_gather_perm_mr(st, ctx->d_perm, ctx->d_R, N, ctx->d_ymr, N, NTHETA, N);
+    enqueue_tri_solve_mr(ctx, NTHETA, ctx->d_Wb);
     double* y = ctx->d_Wb + NTHETA * N;
     HIPCHK(hipMemcpyAsync(y, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     launch_dots_5x6(st, ctx->d_R, ctx->d_Wb, N, ctx->d_part);
@@ -1413,7 +1459,7 @@ static int ensure_maps(ep_ctx* ctx) {
     TRY(upload(ctx, &ctx->d_iperm, ctx->sym.iperm));
     const int64_t ncell = (int64_t)(n - 1) * (n - 1) * (n - 1);
     TRY(dev_alloc(ctx, &ctx->d_cellS, 36 * ncell));
-    for (double** q : {&ctx->d_fk, &ctx->d_s1, &ctx->d_s2, &ctx->d_mapmean}) TRY(dev_alloc(ctx, q, N));
+    for (double** q : {&ctx->d_s1, &ctx->d_s2, &ctx->d_mapmean}) TRY(dev_alloc(ctx, q, N));
     TRY(dev_alloc(ctx, &ctx->d_mapbad, 1));
     return EP_OK;
 }
@@ -1424,21 +1470,6 @@ static int maps_factor_and_mean(ep_ctx* ctx) {
     TRY(run_factor(ctx, nullptr));
     TRY(run_solve(ctx));
     return EP_OK;
-}
-
-// x = L^{-T} z for z in elimination order (in d_y), into out (node order):
-// the backward half of the triangular solve
-static void enqueue_bwd_only(ep_ctx* ctx, double* out) {
-    hipStream_t st = ctx->stream;
-    for (int l = (int)ctx->levels.size() - 1; l >= 0; l--) {
-        auto& P = ctx->levels[l];
-        Bufs b = level_bufs(ctx, l);
-        launch_bwd_t(st, ctx->d_batches + P.bwd_t.be_off, P.bwd_t.nbe, P.bwd_t.ntasks, ctx->F, b, ctx->d_y, ctx->d_x,
-                     ctx->d_t);
-        launch_bwd_x(st, ctx->d_batches + P.bwd_x.be_off, P.bwd_x.nbe, P.bwd_x.ntasks, ctx->F, b, ctx->d_t,
-                     ctx->d_x);
-    }
-    launch_scatter_perm(st, ctx->d_perm, ctx->d_x, out, ctx->g.N());
 }
 
 // Sigma on the fronts (selected inversion of the current factor), then the
@@ -1520,6 +1551,7 @@ void ep_config_default(ep_config* c) {
 void ep_free(ep_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    pitc_free(ctx->pitc);
     for (void* p : ctx->allocs) (void)hipFree(p);
     for (hipEvent_t e : ctx->kt_ev) (void)hipEventDestroy(e);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1688,12 +1720,17 @@ int ep_extinction_map(ep_ctx* ctx, int32_t n_samples, const double* z, double* m
         launch_ext_plugin(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_mu, ctx->d_mapmean, N);
         launch_fill(ctx->stream, ctx->d_s1, N, 0.0);
         launch_fill(ctx->stream, ctx->d_s2, N, 0.0);
-        for (int k = 0; k < n_samples; k++) {
-            HIPCHK(hipMemcpyAsync(ctx->d_y, z + (int64_t)k * N, sizeof(double) * N, hipMemcpyHostToDevice,
+        TRY(ensure_mr(ctx));
+        for (int k0 = 0; k0 < n_samples; k0 += MR_MAX) {
+            const int nb = std::min(MR_MAX, n_samples - k0);
+            HIPCHK(hipMemcpyAsync(ctx->d_ymr, z + (int64_t)k0 * N, sizeof(double) * N * nb, hipMemcpyHostToDevice,
                                   ctx->stream));   // z is host memory here (staged if need be)
-            enqueue_bwd_only(ctx, ctx->d_fk);
-            launch_sum2(ctx->stream, ctx->d_fk, ctx->d_mu, ctx->d_fk, N);
-            launch_ext_sample(ctx->stream, ctx->GD, ctx->d_mapT, ctx->d_fk, ctx->d_mapmean, ctx->d_s1, ctx->d_s2, N);
+            enqueue_bwd_mr(ctx, nb, ctx->d_omr);
+            for (int q = 0; q < nb; q++) {
+                double* fk = ctx->d_omr + (int64_t)q * N;
+                launch_sum2(ctx->stream, fk, ctx->d_mu, fk, N);
+                launch_ext_sample(ctx->stream, ctx->GD, ctx->d_mapT, fk, ctx->d_mapmean, ctx->d_s1, ctx->d_s2, N);
+            }
         }
         launch_sample_var(ctx->stream, ctx->d_s1, ctx->d_s2, ctx->d_t, n_samples, N);
         HIPCHK(hipMemcpyAsync(var, ctx->d_t, sizeof(double) * N, kind_out(ctx), ctx->stream));
@@ -2059,6 +2096,111 @@ int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const 
         }
         A_obs[s] = base + sigma[s] * eps[s];
     }
+    return EP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PITC sub-catalogue EP and the PIC predictive (pitc.cpp)
+// ---------------------------------------------------------------------------
+static PitcBorrow pitc_borrow(ep_ctx* ctx) {
+    PitcBorrow b{};
+    b.st = ctx->stream;
+    b.g = &ctx->g;
+    b.pp = &ctx->pp;
+    b.S = ctx->S;
+    b.h_sptr = ctx->sup.ptr.data();
+    b.h_snodes = ctx->sup.nodes.data();
+    b.d_sptr = ctx->d_sptr;
+    b.d_g = ctx->d_g;
+    b.d_c = ctx->d_c;
+    b.d_A = ctx->d_A;
+    b.d_sigma = ctx->d_sigma;
+    return b;
+}
+
+static int pitc_status(ep_ctx* ctx, int rc, const std::string& err) {
+    if (rc != EP_OK) {
+        ctx->err = err;
+        g_tls_err = err;
+    }
+    return rc;
+}
+
+int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int64_t n_inducing,
+                  const int32_t* inducing, const int32_t* node_block) {
+    if (!ctx) {
+        g_tls_err = "ep_pitc_setup: null context";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (ctx->cfg.likelihood != EP_LIK_GAUSS_LINEAR || ctx->M) {
+        ctx->err = "ep_pitc_setup: needs likelihood GAUSS_LINEAR and mean_fn CONSTANT";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (n_blocks < 1 || n_inducing < 1 || !star_block || !inducing || !node_block) {
+        ctx->err = "ep_pitc_setup: bad arguments";
+        return EP_ERR_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::vector<int32_t> hb, hu, hn;
+    const bool dev = ctx->cfg.pointers_on_device != 0;
+    HIPCHK(host_view(dev, star_block, ctx->S, hb));
+    HIPCHK(host_view(dev, inducing, n_inducing, hu));
+    HIPCHK(host_view(dev, node_block, ctx->g.N(), hn));
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    enqueue_linearise(ctx);   // the frozen sightline weights at the prior mean
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    pitc_free(ctx->pitc);
+    ctx->pitc = nullptr;
+    std::string err;
+    PitcState* s = nullptr;
+    const int rc = pitc_setup(&s, pitc_borrow(ctx), n_blocks, star_block, n_inducing, inducing, node_block, err);
+    if (rc == EP_OK) ctx->pitc = s;
+    return pitc_status(ctx, rc, err);
+}
+
+int ep_pitc_sweep(ep_ctx* ctx, double damping, double* lnZ) {
+    if (!ctx || !ctx->pitc) {
+        if (ctx) ctx->err = "ep_pitc_sweep: no ep_pitc_setup";
+        return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::string err;
+    double lz = 0;
+    const int rc = pitc_sweep(ctx->pitc, pitc_borrow(ctx), damping, &lz, err);
+    if (rc == EP_OK && lnZ) *lnZ = lz;
+    return pitc_status(ctx, rc, err);
+}
+
+int ep_pitc_inducing(ep_ctx* ctx, double* mean, double* cov) {
+    if (!ctx || !ctx->pitc) {
+        if (ctx) ctx->err = "ep_pitc_inducing: no ep_pitc_setup";
+        return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::string err;
+    return pitc_status(ctx, pitc_inducing(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
+}
+
+int ep_pitc_predict(ep_ctx* ctx, double* mean, double* var) {
+    if (!ctx || !ctx->pitc) {
+        if (ctx) ctx->err = "ep_pitc_predict: no ep_pitc_setup";
+        return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::string err;
+    return pitc_status(ctx, pitc_predict(ctx->pitc, pitc_borrow(ctx), mean, var, kind_out(ctx), err), err);
+}
+
+int ep_pitc_info(const ep_ctx* ctx, ep_pitc_stats* out) {
+    if (!ctx || !out) {
+        g_tls_err = "ep_pitc_info: bad arguments";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (!ctx->pitc) {
+        g_tls_err = "ep_pitc_info: no ep_pitc_setup";
+        return EP_ERR_STATE;
+    }
+    pitc_stats(ctx->pitc, out);
     return EP_OK;
 }
 

@@ -104,6 +104,22 @@ void launch_bwd_t(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, F
                   const double* y, const double* x, double* t);
 void launch_bwd_x(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                   const double* t, double* x);
+// the same for nrhs <= MR_MAX vectors at once, column q at q * ld
+constexpr int MR_MAX = 8;
+void launch_fwd_xv_mr(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                      const double* y, double* t, int nrhs, int64_t ld);
+void launch_fwd_r_mr(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                     const double* t, double* y, int nrhs, int64_t ld);
+void launch_copy_v_mr(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y, int nrhs,
+                      int64_t ld);
+void launch_bwd_t_mr(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                     const double* y, const double* x, double* t, int nrhs, int64_t ld);
+void launch_bwd_x_mr(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
+                     const double* t, double* x, int nrhs, int64_t ld);
+void launch_gather_perm_mr(hipStream_t st, const int32_t* perm, const double* src, int64_t lds, double* dst,
+                           int64_t ldd, int nrhs, int64_t n);
+void launch_scatter_perm_mr(hipStream_t st, const int32_t* perm, const double* src, int64_t lds, double* dst,
+                            int64_t ldd, int nrhs, int64_t n);
 
 // star kernels
 struct StarsDev {

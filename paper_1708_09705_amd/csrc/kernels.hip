@@ -437,15 +437,19 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
         A[i + (int64_t)c * m] = v;
         T[i * LDP + c] = v;
     }
+    __shared__ double dinv[TS];
+    dinv[i] = 1.0 / T[i * LDP + i];
     __syncthreads();
-    // X = L^{-1}: lane j solves L x = e_j
+    // X = L^{-1}: lane j solves L x = e_j column by column, so the updates of
+    // one step are independent (no chain of dependent FMAs through a sum)
     double x[TS];
 #pragma unroll
-    for (int r = 0; r < TS; r++) {
-        double s = (i == r) ? 1.0 : 0.0;
+    for (int r = 0; r < TS; r++) x[r] = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < r; q++) s -= T[r * LDP + q] * x[q];
-        x[r] = s / T[r * LDP + r];
+    for (int q = 0; q < TS; q++) {
+        x[q] *= dinv[q];
+#pragma unroll
+        for (int r = q + 1; r < TS; r++) x[r] -= T[r * LDP + q] * x[q];
     }
     __syncthreads();
 #pragma unroll
