@@ -364,6 +364,57 @@ int ep_extinction_map(ep_ctx *ctx, int32_t n_samples, const double *z, double *m
  * a Sigma entry came out non-finite. */
 int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *out5);
 
+/* ---- The paper's sparse approximation: PITC sub-catalogue EP with a PIC
+ * predictive (Sec. 4.1, App. A.1, App. B, App. C) ----
+ * Needs a context with likelihood GAUSS_LINEAR and mean_fn CONSTANT: the
+ * observed log-extinctions a~_n ~ N(a_n, sigma_n^2) with a_n = c_n + g_n . f
+ * the sightline linearised at the prior mean (Sec. 4.1's Gaussian case),
+ * f ~ N(m0 1, K), K the tapered covariance between nodes (not the Vecchia
+ * precision: this path is the paper's alternative to it).  Stars are split
+ * into sub-catalogues k; u = f at R inducing nodes.  Blocks are independent
+ * given u (PITC); EP keeps one Gaussian site on u per sub-catalogue, the
+ * site of p(u | a~_k) / p(u) (the conditional with the minus sign the
+ * Gaussian conditional needs; App. B prints a plus).  The hyper-parameters
+ * are fixed, so every block's tilted distribution is Gaussian and one
+ * undamped sweep reaches the fixed point.
+ * Memory: per sub-catalogue O((N_k + R + P_k) N_k + V_k (V_k + R + P_k))
+ * doubles, V_k the nodes its sightlines touch and P_k the nodes it predicts.
+ *
+ * ep_pitc_setup: star_block (n_stars int32, values 0..n_blocks-1, every
+ * block non-empty), inducing (n_inducing >= 1 distinct node ids),
+ * node_block (n^3 int32: the sub-catalogue whose stars each node's
+ * prediction conditions on).  Plans and allocates; replaces an earlier set-up
+ * and its sites.  Errors: INVALID_ARG (ranges, empty block, duplicate
+ * inducing node, wrong likelihood or mean), OOM/DEVICE.
+ * ep_pitc_sweep: one parallel pass over the sub-catalogues from the same
+ * q(u); sites damped by 'damping' in (0, 1] in natural parameters (the first
+ * sweep starts from zero sites).  lnZ (may be NULL): the PITC log marginal
+ * likelihood ln p(a~) = ln int p(u) prod_k p(a~_k | u) du.  Errors: STATE (no
+ * set-up), INVALID_ARG (damping), NOT_PD (a block or K_uu not positive
+ * definite), DEVICE.
+ * ep_pitc_inducing: mean (R) and covariance (R x R, row-major) of q(u), in
+ * the order of 'inducing'.  ep_pitc_predict: PIC predictive mean and
+ * variance of f at every node (N each), f_p | a~_i, u from the joint
+ * Gaussian of (f_p, a~_i, u) for i = node_block[p], integrated over q(u).
+ * Both: STATE before the first sweep.  Arrays are caller-owned, host or
+ * device per pointers_on_device. */
+typedef struct ep_pitc_stats {
+    int64_t n_blocks, n_inducing;
+    int64_t max_block_stars;   /* largest N_k */
+    int64_t max_block_nodes;   /* largest V_k */
+    double sweep_flops;        /* algorithmic flops of one ep_pitc_sweep (unpadded sizes) */
+    double predict_flops;      /* of one ep_pitc_predict */
+    int64_t device_bytes;      /* the block pass's device memory */
+} ep_pitc_stats;
+
+int ep_pitc_setup(ep_ctx *ctx, int32_t n_blocks, const int32_t *star_block, int64_t n_inducing,
+                  const int32_t *inducing, const int32_t *node_block);
+int ep_pitc_sweep(ep_ctx *ctx, double damping, double *lnZ);
+int ep_pitc_inducing(ep_ctx *ctx, double *mean, double *cov);
+int ep_pitc_predict(ep_ctx *ctx, double *mean, double *var);
+/* Sizes and algorithmic flop counts of the current set-up (STATE without one). */
+int ep_pitc_info(const ep_ctx *ctx, ep_pitc_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,11 +83,18 @@ class ep_structure_stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class ep_pitc_stats(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("n_inducing", ctypes.c_int64), ("max_block_stars", ctypes.c_int64),
+                ("max_block_nodes", ctypes.c_int64), ("sweep_flops", ctypes.c_double),
+                ("predict_flops", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
 EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_free",
            "ep_last_error", "ep_get_sites", "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint",
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
-           "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm")
+           "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
+           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info")
 MLP_NPARAM = 34065
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
@@ -149,11 +156,17 @@ def load(path: str | None = None):
     L.ep_point_predict.argtypes = [vp, i64, vp, vp]
     L.ep_theta.argtypes = [vp, vp, vp]
     L.ep_set_gmm.argtypes = [vp, i32, vp]
+    L.ep_pitc_setup.argtypes = [vp, i32, vp, i64, vp, vp]
+    L.ep_pitc_sweep.argtypes = [vp, ctypes.c_double, vp]
+    L.ep_pitc_inducing.argtypes = [vp, vp, vp]
+    L.ep_pitc_predict.argtypes = [vp, vp, vp]
+    L.ep_pitc_info.argtypes = [vp, ctypes.POINTER(ep_pitc_stats)]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
-                 "ep_point_predict", "ep_theta", "ep_set_gmm"):
+                 "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
+                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -415,6 +428,40 @@ class EP:
         (m, pm), (c, pc) = self._out(N_THETA), self._out((N_THETA, N_THETA))
         _check(self.L, self.L.ep_theta(self.ctx, pm, pc), self.ctx)
         return m, c
+
+    def pitc_setup(self, star_block, inducing, node_block) -> None:
+        """PITC sub-catalogues (star_block: S ints 0..K-1), inducing node ids
+        (R), and the sub-catalogue each node's prediction conditions on
+        (node_block: N ints)."""
+        sb = np.asarray(star_block.cpu() if hasattr(star_block, "cpu") else star_block)
+        K = int(sb.max()) + 1 if sb.size else 0
+        R = int(np.prod(np.shape(inducing)))
+        keep = [self._in(a, n, np.int32) for a, n in ((star_block, self.S), (inducing, R), (node_block, self.N))]
+        _check(self.L, self.L.ep_pitc_setup(self.ctx, K, keep[0][1], R, keep[1][1], keep[2][1]), self.ctx)
+        self.n_inducing = R
+
+    def pitc_sweep(self, damping: float = 1.0) -> float:
+        """One parallel pass over the sub-catalogues; returns ln p(a~) under PITC."""
+        lz = ctypes.c_double(0.0)
+        _check(self.L, self.L.ep_pitc_sweep(self.ctx, float(damping), ctypes.byref(lz)), self.ctx)
+        return lz.value
+
+    def pitc_inducing(self):
+        """Mean (R) and covariance (R x R) of q(u)."""
+        (m, pm), (c, pc) = self._out(self.n_inducing), self._out((self.n_inducing, self.n_inducing))
+        _check(self.L, self.L.ep_pitc_inducing(self.ctx, pm, pc), self.ctx)
+        return m, c
+
+    def pitc_info(self) -> dict:
+        st = ep_pitc_stats()
+        _check(self.L, self.L.ep_pitc_info(self.ctx, ctypes.byref(st)), self.ctx)
+        return {k: getattr(st, k) for k, _ in ep_pitc_stats._fields_}
+
+    def pitc_predict(self):
+        """PIC predictive mean and variance of f at every node."""
+        (m, pm), (v, pv) = self._out(self.N), self._out(self.N)
+        _check(self.L, self.L.ep_pitc_predict(self.ctx, pm, pv), self.ctx)
+        return m, v
 
     def star_state(self) -> dict:
         keys = ("lnA", "cav_mu", "cav_var", "lnZ", "tilted_mean", "tilted_var")

@@ -1,0 +1,177 @@
+"""GPU parity of the PITC sub-catalogue EP and the PIC predictive (Sec. 4.1,
+App. A.1, App. B, App. C) against the dense FP64 oracle, through the C ABI:
+q(u) (mean and covariance), the PITC log evidence, and the predictive mean
+and variance of the field at every node.  FP64 throughout; the two sides
+differ only in rounding order (covariance form with explicit inverses in the
+oracle, whitened Cholesky form on the GPU): 1e-8 relative."""
+import numpy as np
+import pytest
+
+from oracle import pitc
+
+from gpu_common import relerr
+from synth import Workload, draw, preset
+from synth.workloads import boundary_inducing, node_positions, sky_cells
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def _case(n, L, stars, n_lon, n_lat, R, law="uniform", seed=31, inducing="random"):
+    w = Workload("pitc", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law=law, d_max_pc=L,
+                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood="gauss_linear", seed_id=seed)
+    cfg = w.ep_fields()
+    raw = draw(w)
+    from oracle import epo
+    f_true, a_obs, sl = epo.simulate(cfg, raw)
+    blocks = sky_cells(w, raw["xyz"], n_lon, n_lat)
+    # relabel to drop empty cells: every sub-catalogue holds stars
+    used, blocks = np.unique(blocks, return_inverse=True)
+    node_cell = sky_cells(w, node_positions(w), n_lon, n_lat)
+    lut = np.full(n_lon * n_lat, -1)
+    lut[used] = np.arange(len(used))
+    # nodes of an empty cell go to the nearest used cell by index
+    for c in range(n_lon * n_lat):
+        if lut[c] < 0:
+            lut[c] = int(np.argmin(np.abs(used - c)))
+    node_block = lut[node_cell].astype(np.int32)
+    if inducing == "random":
+        u = np.sort(np.random.default_rng(seed).choice(w.N, size=R, replace=False)).astype(np.int32)
+    else:
+        u = boundary_inducing(w, n_lon, n_lat, inducing)
+    return w, cfg, raw, a_obs, sl, blocks.astype(np.int32), u, node_block
+
+
+def _pair(case, damping=(1.0,)):
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, a, sl, blocks, u, nb = case
+    ora = pitc.DensePITC(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    g = E.EP(dict(cfg, leaf_size=48), raw["xyz"], a, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    lz = None
+    for d in damping:
+        ora.sweep(d)
+        lz = g.pitc_sweep(d)
+    return ora, g, lz
+
+
+# sub-catalogues of 1-3 row tiles with ragged tails, R of 1-3 tiles, prediction
+# sets of several tiles; the last case has the paper's layout (disc stars,
+# inducing points on the cell boundaries at fixed distances)
+CASES = [
+    dict(n=8, L=600.0, stars=150, n_lon=3, n_lat=2, R=40),
+    dict(n=9, L=800.0, stars=400, n_lon=3, n_lat=1, R=150, seed=33),
+    dict(n=10, L=1000.0, stars=500, n_lon=4, n_lat=2, R=0, law="disc", seed=35,
+         inducing=(250.0, 500.0, 750.0, 1000.0)),
+]
+
+
+@pytest.mark.parametrize("kw", CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary"])
+def test_pitc_matches_oracle(kw):
+    case = _case(**kw)
+    w, cfg, raw, a, sl, blocks, u, nb = case
+    print(f"case n={kw['n']} stars={kw['stars']} blocks={blocks.max() + 1} R={len(u)} "
+          f"block sizes {np.bincount(blocks).min()}-{np.bincount(blocks).max()}", flush=True)
+    ora, g, lz = _pair(case)
+    om, oV = ora.posterior_u()
+    gm, gV = g.pitc_inducing()
+    olz = ora.log_evidence()
+    print(f"q(u): mean {relerr(gm, om):.2e} cov {_rel(gV, oV):.2e}; lnZ {lz:.6f} vs {olz:.6f}", flush=True)
+    assert relerr(gm, om) < 1e-8 and _rel(gV, oV) < 1e-8
+    assert abs(lz - olz) < 1e-8 * abs(olz)
+    pm, pv = g.pitc_predict()
+    qm, qv = ora.predict()
+    print(f"predictive: mean {relerr(pm, qm):.2e} var {relerr(pv, qv):.2e}", flush=True)
+    assert relerr(pm, qm) < 1e-8 and relerr(pv, qv) < 1e-8
+    g.close()
+
+
+def test_pitc_damped_sweeps_match_oracle():
+    case = _case(n=8, L=600.0, stars=200, n_lon=2, n_lat=2, R=70, seed=37)
+    ora, g, lz = _pair(case, damping=(0.5, 0.5, 0.7))
+    om, oV = ora.posterior_u()
+    gm, gV = g.pitc_inducing()
+    assert relerr(gm, om) < 1e-8 and _rel(gV, oV) < 1e-8
+    assert abs(lz - ora.log_evidence()) < 1e-8 * abs(ora.log_evidence())
+    pm, pv = g.pitc_predict()
+    qm, qv = ora.predict()
+    assert relerr(pm, qm) < 1e-8 and relerr(pv, qv) < 1e-8
+    g.close()
+
+
+def test_pitc_errors():
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, a, sl, blocks, u, nb = _case(n=8, L=600.0, stars=100, n_lon=2, n_lat=1, R=20)
+    g = E.EP(dict(cfg, leaf_size=48), raw["xyz"], a, raw["sigma"])
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_sweep(1.0)
+    assert ei.value.code == -5
+    bad = blocks.copy()
+    bad[:] = 0
+    bad[0] = 2                                     # block 1 empty
+    for sb, uu, nbk in ((bad, u, nb), (blocks, np.r_[u, u[:1]].astype(np.int32), nb),
+                        (blocks, u, np.full_like(nb, 7))):
+        with pytest.raises(E.EPError) as ei:
+            g.pitc_setup(sb, uu, nbk)
+        assert ei.value.code == -1
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_info()
+    assert ei.value.code == -5
+    g.pitc_setup(blocks, u, nb)
+    info = g.pitc_info()
+    assert info["n_blocks"] == blocks.max() + 1 and info["n_inducing"] == len(u)
+    assert info["max_block_stars"] == np.bincount(blocks).max() and info["sweep_flops"] > 0
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_inducing()
+    assert ei.value.code == -5
+    for d in (0.0, 1.5, float("nan")):
+        with pytest.raises(E.EPError) as ei:
+            g.pitc_sweep(d)
+        assert ei.value.code == -1
+    g.pitc_sweep(1.0)
+    assert np.all(np.isfinite(g.pitc_predict()[1]))
+    g.close()
+    ge = E.EP(dict(cfg, likelihood="extinction", leaf_size=48), raw["xyz"], np.exp(a), raw["sigma"])
+    with pytest.raises(E.EPError) as ei:
+        ge.pitc_setup(blocks, u, nb)
+    assert ei.value.code == -1
+    ge.close()
+
+
+def test_pitc_full_size_properties():
+    """The bench shape (64^3 grid, 100,000 disc stars, 40 x 4 on-sky
+    sub-catalogues, inducing nodes on their boundaries at 1-4 kpc): what holds
+    at any size: the fixed point after one undamped sweep, a symmetric
+    positive definite q(u) covariance, predictive variances in (0, prior
+    variance], finite evidence."""
+    from paper_1708_09705_amd import ep as E
+    w = preset(2, likelihood="gauss_linear")
+    cfg = w.ep_fields()
+    raw = draw(w)
+    # observations from the library's own simulator (the GAUSS_LINEAR forward
+    # model at the prior mean); the checks below need no expected values
+    _, a_obs = E.ep_simulate(E.make_config(cfg), raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+    blocks = sky_cells(w, raw["xyz"], 40, 4)
+    assert np.bincount(blocks, minlength=160).min() > 0
+    u = boundary_inducing(w, 40, 4, (1000.0, 2000.0, 3000.0, 4000.0))
+    nb = sky_cells(w, node_positions(w), 40, 4)
+    g = E.EP(dict(cfg), raw["xyz"], a_obs, raw["sigma"])
+    print(f"full size: blocks 160 R={len(u)}", flush=True)
+    g.pitc_setup(blocks, u, nb)
+    lz1 = g.pitc_sweep(1.0)
+    m1, V1 = g.pitc_inducing()
+    lz2 = g.pitc_sweep(1.0)
+    m2, V2 = g.pitc_inducing()
+    assert np.isfinite(lz1) and abs(lz2 - lz1) <= 1e-12 * abs(lz1)
+    assert relerr(m2, m1) < 1e-12 and _rel(V2, V1) < 1e-12
+    assert _rel(V1, V1.T) < 1e-12
+    assert np.linalg.eigvalsh(0.5 * (V1 + V1.T)).min() > 0
+    pm, pv = g.pitc_predict()
+    k0 = float(cfg["prior_var"])
+    print(f"lnZ {lz1:.3f}; predictive var in [{pv.min():.3e}, {pv.max():.3e}]", flush=True)
+    assert np.all(np.isfinite(pm)) and np.all(pv > 0) and np.all(pv <= k0 * (1 + 1e-9))
+    g.close()
