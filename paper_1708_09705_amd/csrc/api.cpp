@@ -19,6 +19,7 @@
 #include "../../include/ep.h"
 #include "kernels.h"
 #include "pitc.h"
+#include "task_order.h"
 #include "prior.h"
 #include "surrogate.h"
 #include "symbolic.h"
@@ -216,41 +217,7 @@ static GemmSeg mkseg(int bufA, int64_t a, int64_t sa, int lda, bool ta, bool neg
     return s;
 }
 
-// Reorder the tasks of one launch for the XCD-contiguous block mapping (the
-// k_gemm_tasks blocks of XCD x run tasks [x per, (x + 1) per) in order): cut
-// the emission order, which keeps operand-sharing tasks together, into eight
-// contiguous pieces of equal work, put each piece longest task first, and pad
-// the pieces to equal length with empty tasks.
-static void balance_range(std::vector<GemmTask>& tasks, TaskRange& r) {
-    if (r.n <= 0) return;
-    auto work = [](const GemmTask& t) {
-        int64_t w = 1;
-        for (int q = 0; q < ((t.flags >> 4) & 3); q++) w += t.s[q].nk;
-        return w;
-    };
-    std::vector<GemmTask> src(tasks.begin() + r.off, tasks.begin() + r.off + r.n);
-    int64_t total = 0;
-    for (const GemmTask& t : src) total += work(t);
-    std::vector<int64_t> cut(9, (int64_t)src.size());
-    cut[0] = 0;
-    int64_t acc = 0;
-    int c = 1;
-    for (int64_t i = 0; i < (int64_t)src.size() && c < 8; i++) {
-        acc += work(src[i]);
-        while (c < 8 && acc * 8 >= total * c) cut[c++] = i + 1;
-    }
-    int64_t per = 0;
-    for (int x = 0; x < 8; x++) per = std::max(per, cut[x + 1] - cut[x]);
-    std::vector<GemmTask> out((size_t)(8 * per), GemmTask{});
-    for (int x = 0; x < 8; x++) {
-        std::stable_sort(src.begin() + cut[x], src.begin() + cut[x + 1],
-                         [&](const GemmTask& a, const GemmTask& b) { return work(a) > work(b); });
-        std::copy(src.begin() + cut[x], src.begin() + cut[x + 1], out.begin() + x * per);
-    }
-    tasks.resize((size_t)r.off);
-    tasks.insert(tasks.end(), out.begin(), out.end());
-    r.n = 8 * per;
-}
+static void balance_range(std::vector<GemmTask>& tasks, TaskRange& r) { balance_xcd(tasks, r.off, r.n); }
 
 // ---------------------------------------------------------------------------
 // Schedules.  All tile addresses are absolute element offsets into their

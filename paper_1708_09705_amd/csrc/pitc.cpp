@@ -27,6 +27,7 @@
 #include "../../include/ep.h"
 #include "kernels.h"
 #include "pitc.h"
+#include "task_order.h"
 
 namespace ep {
 
@@ -169,18 +170,45 @@ void plan_factor(const std::vector<int>& fronts, const std::vector<int64_t>& off
                  std::vector<BatchEnt>& be, FactorPlan& P, double& flops) {
     int Tmax = 0;
     for (int f : fronts) Tmax = std::max(Tmax, nvpad[f] / TS);
-    Gemm gemm{tasks, flops};
+    (void)flops;
     for (int j = 0; j < Tmax; j++) {
         Range u;
         u.off = (int64_t)tasks.size();
-        if (j > 0)
+        if (j > 0) {
+            // late columns have few row blocks and a long K: cut K into
+            // pieces of at least 8 tiles that add into the column atomically
+            // until the launch has ~512 blocks
+            int64_t nb = 0;
+            for (int f : fronts)
+                if (nvpad[f] / TS > j) nb += (m[f] - TS * j + 255) / 256;
+            const int split = (int)std::max<int64_t>(1, std::min<int64_t>((512 + nb - 1) / std::max<int64_t>(nb, 1),
+                                                                          std::max(1, j / 8)));
             for (int f : fronts) {
                 if (nvpad[f] / TS <= j) continue;
-                const int64_t o = off[f];
-                gemm(o + TS * j + (int64_t)TS * j * m[f], m[f], m[f] - TS * j, TS, false, false, false,
-                     Op{o + TS * j, m[f], false}, Op{o + TS * j, m[f], true}, TS * j, true, nullptr, nullptr, 0, false,
-                     0, 0, 0, 0);
+                const int64_t o = off[f], mf = m[f];
+                for (int i0 = TS * j; i0 < mf; i0 += 256)
+                    for (int sp = 0; sp < split; sp++) {
+                        const int a0 = (int)((int64_t)j * sp / split), a1 = (int)((int64_t)j * (sp + 1) / split);
+                        if (a1 <= a0) continue;
+                        GemmTask t{};
+                        t.c = o + i0 + (int64_t)TS * j * mf;
+                        t.ldc = (int32_t)mf;
+                        t.flags = (split > 1 ? 2 : 0) | (1 << 4) | (BUF_FRONTS << 8) |
+                                  gt_shape((int)std::min<int64_t>(4, (mf - i0) / TS), false, false, 0, false);
+                        GemmSeg g{};
+                        g.a = o + i0 + (int64_t)TS * a0 * mf;   // L(i0.., a0..)
+                        g.sa = (int64_t)TS * mf;
+                        g.lda = (int32_t)mf;
+                        g.b = o + TS * j + (int64_t)TS * a0 * mf;   // L(j, a0..)^T
+                        g.sb = (int64_t)TS * mf;
+                        g.ldb = (int32_t)mf;
+                        g.nk = a1 - a0;
+                        g.flags = 2 | 4 | (BUF_FRONTS << 8) | (BUF_FRONTS << 10);
+                        t.s[0] = g;
+                        tasks.push_back(t);
+                    }
             }
+        }
         u.n = (int64_t)tasks.size() - u.off;
         P.upd.push_back(u);
         Range fl;
@@ -503,11 +531,13 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         gs(B.M1, B.npad, B.npad, B.vpad + rpad, true, false, false, Op{B.G, B.npad, false}, Op{B.KV, B.vpad, false},
            B.vpad, false, nullptr, nullptr, 0, false, B.nst, B.nv + R, B.nv, 0);
     end(s->tM1);
+    balance_xcd(tasks, s->tM1.off, s->tM1.n);
     begin(s->tZt);
     for (const Blk& B : s->blk)   // Z^T = L_C^{-1} rho^T
         gs(B.F + B.npad, B.m, rpad, B.npad, true, false, false, XCtT, Op{B.M1 + (int64_t)B.vpad * B.npad, B.npad, true},
            rpad, false, nullptr, nullptr, 0, false, R, B.nst, R, 0);
     end(s->tZt);
+    balance_xcd(tasks, s->tZt.off, s->tZt.n);
     begin(s->tB);
     for (const Blk& B : s->blk) {   // B = (G K_VV) G^T - Z Z^T (lower tiles)
         const Op Zt{B.F + B.npad, B.m, true}, Zn{B.F + B.npad, B.m, false};
@@ -515,11 +545,13 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
            &Zt, &Zn, rpad, true, B.nst, B.nst, B.nv, R);
     }
     end(s->tB);
+    balance_xcd(tasks, s->tB.off, s->tB.n);
     begin(s->tKt);
     for (const Blk& B : s->blk)   // Kt = (L_C^{-1} K_uP)^T = K_uP^T L_C^{-T}
         gs(B.Kt, B.ppad, B.ppad, rpad, true, false, false, Op{B.KuP, rpad, true}, XCt, rpad, false, nullptr, nullptr,
            0, false, B.np, R, R, 0);
     end(s->tKt);
+    balance_xcd(tasks, s->tKt.off, s->tKt.n);
     begin(s->tD);
     for (const Blk& B : s->blk) {   // D = G K_VP - Z (L_C^{-1} K_uP), stored transposed under the residual tile
         const Op Zt{B.F + B.npad, B.m, true}, KtT{B.Kt, B.ppad, true};
@@ -528,6 +560,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
            B.np, B.nv, R);
     }
     end(s->tD);
+    balance_xcd(tasks, s->tD.off, s->tD.n);
     {
         std::vector<int> blks(n_blocks);
         std::iota(blks.begin(), blks.end(), 0);
@@ -544,6 +577,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
            R + 1, B.nst, 0);
     }
     end(s->tLam);
+    balance_xcd(tasks, s->tLam.off, s->tLam.n);
     {
         std::vector<int> qe{n_blocks + 1, n_blocks + 2};
         double ff = 0;
@@ -579,11 +613,13 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
            true, B.np, R, R, B.nst);
     }
     end(s->tAt);
+    balance_xcd(tasks, s->tAt.off, s->tAt.n);
     begin(s->tSAt);
     for (const Blk& B : s->blk)   // (Sigma~ A)^T = A^T Sigma~
         gp(B.SAt, B.ppad, B.ppad, rpad, true, false, false, Op{B.At, B.ppad, false}, Op{s->offSig, rpad, false}, rpad,
            false, nullptr, nullptr, 0, false, B.np, R, R, 0);
     end(s->tSAt);
+    balance_xcd(tasks, s->tSAt.off, s->tSAt.n);
     s->flops_sweep = fs;
     s->flops_pred = fp;
 

@@ -67,10 +67,12 @@ CASES = [
     dict(n=9, L=800.0, stars=400, n_lon=3, n_lat=1, R=150, seed=33),
     dict(n=10, L=1000.0, stars=500, n_lon=4, n_lat=2, R=0, law="disc", seed=35,
          inducing=(250.0, 500.0, 750.0, 1000.0)),
+    # one sub-catalogue of 21 row tiles: its late column updates are cut in K
+    dict(n=8, L=600.0, stars=1300, n_lon=1, n_lat=1, R=60, seed=39),
 ]
 
 
-@pytest.mark.parametrize("kw", CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary"])
+@pytest.mark.parametrize("kw", CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary", "n8-1blk-21tiles"])
 def test_pitc_matches_oracle(kw):
     case = _case(**kw)
     w, cfg, raw, a, sl, blocks, u, nb = case
