@@ -86,3 +86,34 @@ def test_device_pointers_match_host_pointers():
     assert ei.value.code == -1
     gh.close()
     gd.close()
+
+
+def test_device_pointers_pitc():
+    """The PITC entry points with device arrays (int32 inputs, FP64 outputs)."""
+    import torch
+    from paper_1708_09705_amd import ep as E
+    from synth.workloads import node_positions, sky_cells
+    from synth import Workload
+    cfg, gcfg, raw, f, a, sl = small_case(n=8, L=600.0, stars=150, leaf=48, lik="gauss_linear")
+    w = Workload("p", n=8, box_pc=600.0, n_stars=150, sweeps=1)
+    blocks = sky_cells(w, raw["xyz"], 2, 1)
+    nb = sky_cells(w, node_positions(w), 2, 1)
+    u = np.arange(0, 512, 9, dtype=np.int32)
+    dev = lambda x, t=torch.float64: torch.as_tensor(np.asarray(x), dtype=t, device="cuda:0")
+    gh = E.EP(gcfg, raw["xyz"], a, raw["sigma"])
+    gd = E.EP(dict(gcfg, pointers_on_device=1, device=0), dev(raw["xyz"]), dev(a), dev(raw["sigma"]))
+    gh.pitc_setup(blocks, u, nb)
+    gd.pitc_setup(dev(blocks, torch.int32), dev(u, torch.int32), dev(nb, torch.int32))
+    lh, ld = gh.pitc_sweep(0.8), gd.pitc_sweep(0.8)
+    assert abs(lh - ld) <= 1e-12 * abs(lh)
+    outs = [("u mean", gh.pitc_inducing()[0], gd.pitc_inducing()[0]),
+            ("u cov", gh.pitc_inducing()[1], gd.pitc_inducing()[1]),
+            ("pic mean", gh.pitc_predict()[0], gd.pitc_predict()[0]),
+            ("pic var", gh.pitc_predict()[1], gd.pitc_predict()[1])]
+    for name, x, y in outs:
+        assert isinstance(y, torch.Tensor) and y.device.type == "cuda", name
+        err = relerr(_np(y), x)
+        print(f"{name}: {err:.2e}", flush=True)
+        assert err < 1e-12, name
+    gh.close()
+    gd.close()
