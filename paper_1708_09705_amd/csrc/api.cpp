@@ -2082,6 +2082,8 @@ static PitcBorrow pitc_borrow(ep_ctx* ctx) {
     b.d_c = ctx->d_c;
     b.d_A = ctx->d_A;
     b.d_sigma = ctx->d_sigma;
+    // what hbm_cap_bytes leaves after the context's own allocations
+    b.cap_bytes = ctx->cfg.hbm_cap_bytes > 0 ? std::max<int64_t>(ctx->cfg.hbm_cap_bytes - ctx->dev_bytes, 1) : 0;
     return b;
 }
 

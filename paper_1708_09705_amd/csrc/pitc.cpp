@@ -91,20 +91,26 @@ struct PitcState {
     double m0 = 0, k0 = 0;
     bool swept = false;
     double flops_sweep = 0, flops_pred = 0;
-    int64_t dev_bytes = 0;
+    int64_t dev_bytes = 0, cap_bytes = 0;
 };
 
 namespace {
 
 template <typename T>
 int dalloc(PitcState* s, T** p, int64_t n, std::string& err) {
+    const int64_t bytes = (int64_t)sizeof(T) * std::max<int64_t>(n, 1);
+    if (s->cap_bytes > 0 && s->dev_bytes + bytes > s->cap_bytes) {
+        err = "pitc: device allocation of " + std::to_string(bytes) + " bytes exceeds hbm_cap_bytes";
+        return EP_ERR_OOM;
+    }
     void* q = nullptr;
-    if (hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
-        err = "pitc: device allocation failed";
+    if (hipMalloc(&q, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "pitc: hipMalloc of " + std::to_string(bytes) + " bytes failed";
         return EP_ERR_OOM;
     }
     s->allocs.push_back(q);
-    s->dev_bytes += (int64_t)(sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    s->dev_bytes += bytes;
     *p = (T*)q;
     return EP_OK;
 }
@@ -323,6 +329,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         pitc_free(s);
         return rc;
     };
+    s->cap_bytes = b.cap_bytes;
     s->K = n_blocks;
     s->R = (int)R;
     s->rpad = (int)pad64(R);

@@ -72,6 +72,7 @@ struct PitcBorrow {
     const double* d_c;
     const double* d_A;
     const double* d_sigma;
+    int64_t cap_bytes;         // device bytes the pass may allocate (0: no cap)
 };
 
 struct PitcState;

@@ -137,6 +137,16 @@ def test_pitc_errors():
     g.pitc_sweep(1.0)
     assert np.all(np.isfinite(g.pitc_predict()[1]))
     g.close()
+    # the block pass's allocations count against hbm_cap_bytes
+    need = E.EP(dict(cfg, leaf_size=48), raw["xyz"], a, raw["sigma"])
+    cap = need.structure()["device_bytes"] + (1 << 20)
+    need.close()
+    gc = E.EP(dict(cfg, leaf_size=48, hbm_cap_bytes=cap), raw["xyz"], a, raw["sigma"])
+    with pytest.raises(E.EPError) as ei:
+        gc.pitc_setup(blocks, u, nb)
+    assert ei.value.code == -2
+    gc.sweep()                                     # the context is still usable
+    gc.close()
     ge = E.EP(dict(cfg, likelihood="extinction", leaf_size=48), raw["xyz"], np.exp(a), raw["sigma"])
     with pytest.raises(E.EPError) as ei:
         ge.pitc_setup(blocks, u, nb)
