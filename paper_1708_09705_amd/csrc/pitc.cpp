@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -129,9 +130,17 @@ int dupload(PitcState* s, T** p, const std::vector<T>& v, std::string& err) {
 // [+]= up to two segments +-op(A) op(B), as 256 x 128 block tasks of
 // k_gemm_tasks; with lower, only the quadrants on or below the diagonal
 // are stored; with tstore, element (i, j) goes to C[j + i ldc].
+// Rows [r0, r1) of the K dimension that can be non-zero for one 128-column
+// output block (the taper zeroes the rest); real = its non-padding columns.
+struct Win {
+    int64_t r0 = 0, r1 = 0;
+    int real = 0;
+};
+
 struct Gemm {
     std::vector<GemmTask>& T;
     double& flops;
+    const std::vector<Win>* win = nullptr;   // K windows of the first segment, per 128-column block
     void operator()(int64_t c, int ldc, int M, int N, bool over, bool lower, bool tstore, Op A, Op B, int K, bool neg,
                     const Op* A2, const Op* B2, int K2, bool neg2, double mr, double nr, double kr, double kr2) {
         for (int i0 = 0; i0 < M; i0 += 256)
@@ -156,14 +165,33 @@ struct Gemm {
                     g.flags = (a.t ? 1 : 0) | (b.t ? 2 : 0) | (ng ? 4 : 0) | (BUF_FRONTS << 8) | (BUF_FRONTS << 10);
                     t.s[nseg++] = g;
                 };
-                if (K > 0) seg(A, B, K, neg);
+                if (K > 0) {
+                    if (win) {
+                        // every K tile outside the window multiplies zeros; keep at least one tile so that an
+                        // overwriting task still writes its (zero) block
+                        const Win& w = (*win)[j0 / 128];
+                        const int t0 = (int)std::min<int64_t>(w.r0 / TS, K / TS - 1);
+                        const int t1 = (int)std::max<int64_t>(std::min<int64_t>((w.r1 + TS - 1) / TS, K / TS), t0 + 1);
+                        Op a = A, b = B;
+                        a.off += a.t ? (int64_t)TS * t0 : (int64_t)TS * t0 * a.ld;
+                        b.off += b.t ? (int64_t)TS * t0 * b.ld : (int64_t)TS * t0;
+                        seg(a, b, TS * (t1 - t0), neg);
+                    } else {
+                        seg(A, B, K, neg);
+                    }
+                }
                 if (A2 && K2 > 0) seg(*A2, *B2, K2, neg2);
                 if (nseg == 0) continue;
                 t.flags = (over ? 1 : 0) | (nseg << 4) | (BUF_FRONTS << 8) | gt_shape(nq, cols2, lower, d, tstore);
                 T.push_back(t);
             }
         const double area = lower ? 0.5 * mr * (mr + 1.0) : mr * nr;
-        flops += 2.0 * area * (kr + kr2);
+        if (win) {
+            for (const Win& w : *win) flops += 2.0 * mr * w.real * (double)(w.r1 - w.r0);
+            flops += 2.0 * area * kr2;
+        } else {
+            flops += 2.0 * area * (kr + kr2);
+        }
     }
 };
 
@@ -533,10 +561,40 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         plan_factor(one, foff, fm, fnv, tasks, flists, be, s->facC, fs);
     }
     fs += (double)R * R * R / 3.0 + (double)R * R * R;
+    // K windows: rows of V_k (ascending ids) that can lie within the taper of
+    // a column block's nodes (node ids within w n^2 + w n + w of them)
+    const int64_t nn = b.g->n, dwin = (int64_t)wmax * (nn * nn + nn + 1);
+    auto windows = [&](const Blk& B, const std::vector<int32_t>& col) {
+        std::vector<Win> out;
+        const int32_t* V = ids.data() + B.v0;
+        for (size_t j0 = 0; j0 < col.size(); j0 += 128) {
+            int64_t lo = INT64_MAX, hi = INT64_MIN;
+            Win wd;
+            for (size_t q = j0; q < std::min(col.size(), j0 + 128); q++)
+                if (col[q] >= 0) {
+                    lo = std::min<int64_t>(lo, col[q]);
+                    hi = std::max<int64_t>(hi, col[q]);
+                    wd.real++;
+                }
+            if (wd.real) {
+                wd.r0 = std::lower_bound(V, V + B.nv, lo - dwin) - V;
+                wd.r1 = std::upper_bound(V, V + B.nv, hi + dwin) - V;
+            }
+            out.push_back(wd);
+        }
+        return out;
+    };
     begin(s->tM1);
-    for (const Blk& B : s->blk)   // [G K_VV | rho] = G [K_VV | K_Vu]
+    for (const Blk& B : s->blk) {   // [G K_VV | rho] = G [K_VV | K_Vu]
+        std::vector<int32_t> col((size_t)B.vpad + rpad, -1);
+        std::copy(ids.begin() + B.v0, ids.begin() + B.v0 + B.nv, col.begin());
+        std::copy(inducing, inducing + R, col.begin() + B.vpad);
+        const std::vector<Win> w = windows(B, col);
+        gs.win = &w;
         gs(B.M1, B.npad, B.npad, B.vpad + rpad, true, false, false, Op{B.G, B.npad, false}, Op{B.KV, B.vpad, false},
            B.vpad, false, nullptr, nullptr, 0, false, B.nst, B.nv + R, B.nv, 0);
+        gs.win = nullptr;
+    }
     end(s->tM1);
     balance_xcd(tasks, s->tM1.off, s->tM1.n);
     begin(s->tZt);
@@ -562,9 +620,14 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     begin(s->tD);
     for (const Blk& B : s->blk) {   // D = G K_VP - Z (L_C^{-1} K_uP), stored transposed under the residual tile
         const Op Zt{B.F + B.npad, B.m, true}, KtT{B.Kt, B.ppad, true};
+        std::vector<int32_t> col((size_t)B.ppad, -1);
+        std::copy(ids.begin() + B.p0, ids.begin() + B.p0 + B.np, col.begin());
+        const std::vector<Win> w = windows(B, col);
+        gs.win = &w;
         gs(B.F + B.npad + rpad + TS, B.m, B.npad, B.ppad, true, false, true, Op{B.G, B.npad, false},
            Op{B.KV + (int64_t)B.vpad * (B.vpad + rpad), B.vpad, false}, B.vpad, false, &Zt, &KtT, rpad, true, B.nst,
            B.np, B.nv, R);
+        gs.win = nullptr;
     }
     end(s->tD);
     balance_xcd(tasks, s->tD.off, s->tD.n);

@@ -69,10 +69,14 @@ CASES = [
          inducing=(250.0, 500.0, 750.0, 1000.0)),
     # one sub-catalogue of 21 row tiles: its late column updates are cut in K
     dict(n=8, L=600.0, stars=1300, n_lon=1, n_lat=1, R=60, seed=39),
+    # a taper of one spacing in a 12^3 grid: the covariance products skip
+    # the K tiles the taper zeroes
+    dict(n=12, L=2000.0, stars=400, n_lon=2, n_lat=1, R=90, seed=41),
 ]
 
 
-@pytest.mark.parametrize("kw", CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary", "n8-1blk-21tiles"])
+@pytest.mark.parametrize("kw", CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary", "n8-1blk-21tiles",
+                                    "n12-narrow-taper"])
 def test_pitc_matches_oracle(kw):
     case = _case(**kw)
     w, cfg, raw, a, sl, blocks, u, nb = case
