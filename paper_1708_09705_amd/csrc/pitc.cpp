@@ -70,6 +70,7 @@ struct PitcState {
     std::vector<Blk> blk;
     int64_t ws_n = 0, wx_n = 0;
     double *ws = nullptr, *wx = nullptr;
+    int64_t offKt = 0, offAt = 0, nKt = 0;
     int64_t offC = 0, offQ = 0, offE = 0, offSnew = 0, offSsites = 0, offSig = 0, offMu = 0, offT1 = 0, offSigU = 0,
             offMuU = 0, offLam = 0, offLnz = 0, offG = 0, nG = 0;
     int mC = 0, mQ = 0, mE = 0;
@@ -433,13 +434,18 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         w += (int64_t)B.npad * (B.vpad + rpad);
         B.F = w;
         w += (int64_t)B.m * B.npad;
-        B.Kt = w;
-        w += (int64_t)B.ppad * rpad;
-        B.At = w;
-        w += (int64_t)B.ppad * rpad;
-        B.SAt = w;
-        w += (int64_t)B.ppad * rpad;
     }
+    // K~^T, A^T and (Sigma~ A)^T of all blocks as three regions with the same
+    // block offsets, so that A^T starts as one copy of K~^T
+    for (int q = 0; q < 3; q++) {
+        if (q == 0) s->offKt = w;
+        if (q == 1) s->offAt = w;
+        for (auto& B : s->blk) {
+            (q == 0 ? B.Kt : (q == 1 ? B.At : B.SAt)) = w;
+            w += (int64_t)B.ppad * rpad;
+        }
+    }
+    s->nKt = s->offAt - s->offKt;
     s->offLam = w;
     w += (int64_t)n_blocks * e1 * e1;
     s->mC = 2 * rpad;
@@ -677,10 +683,10 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
        false, R, 1, R, 0);
     end(s->tMuU);
     begin(s->tAt);
-    for (const Blk& B : s->blk) {   // A^T = K~^T - E^T W_Z
+    for (const Blk& B : s->blk) {   // A^T = K~^T - E^T W_Z (A^T holds a copy of K~^T)
         const Op Ed{B.F + B.npad + rpad + TS, B.m, false}, WZ{B.F + B.npad, B.m, true};
-        gp(B.At, B.ppad, B.ppad, rpad, true, false, false, Op{B.KuP, rpad, true}, XCt, rpad, false, &Ed, &WZ, B.npad,
-           true, B.np, R, R, B.nst);
+        gp(B.At, B.ppad, B.ppad, rpad, false, false, false, Ed, WZ, B.npad, true, nullptr, nullptr, 0, false, B.np, R,
+           B.nst, 0);
     }
     end(s->tAt);
     balance_xcd(tasks, s->tAt.off, s->tAt.n);
@@ -813,6 +819,7 @@ int pitc_predict(PitcState* s, const PitcBorrow& b, double* mean, double* var, h
         return EP_ERR_STATE;
     }
     hipStream_t st = b.st;
+    PCHK(hipMemcpyAsync(s->ws + s->offAt, s->ws + s->offKt, sizeof(double) * s->nKt, hipMemcpyDeviceToDevice, st));
     gemm_range(s, st, s->tAt);
     gemm_range(s, st, s->tSAt);
     launch_pitc_predict(st, s->d_blk, s->d_predbase, s->K, s->npred_tasks, s->ws, s->d_ids, s->ws + s->offMu, s->m0,
