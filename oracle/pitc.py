@@ -176,3 +176,156 @@ class DensePITC:
             var[nodes] = (np.diag(self.K)[nodes] - np.einsum("ij,ij->j", kst, w)
                           + np.einsum("ij,ij->j", wu, V_u @ wu))
         return mean, var
+
+
+class DensePITCTheta(DensePITC):
+    """The same block EP with the mean parameters Theta in the sites: the
+    paper's q(u, Theta) (Sec. 4.1, App. B).  The prior mean of the field is
+    the disc + bump function of phi = ln theta, linearised at the hyperprior
+    mean phihat = mu0 (the sightlines are frozen there too, the gauss_linear
+    likelihood): f = mhat + J psi + delta, psi = phi - phihat ~ N(0, S0),
+    delta ~ N(0, K), so that
+        a~_k | u, phi:  mean mu_k(phi) = muhat_k + H_k psi (H_k = G_k J)
+        u | phi:        mean m(phi)    = mhat_u + J_u psi, covariance C.
+    The sites are Gaussians over z = (u, psi), kept in natural parameters.
+    Per block, after App. B (minus sign in C'_k, P1):
+        p(u | a~_k, phi) = N(m'_k(phi), C'_k),
+        m'_k(phi) = m(phi) + rho_k^T A_k^{-1} (a~_k - mu_k(phi)),
+        p(a~_k | phi)    = N(mu_k(phi), A_k),  A_k = Sigma_k + S_k;
+    the tilted distribution is the reduced cavity times p(phi) p(u | a~_k,
+    phi) p(a~_k | phi), and the new site is it divided by the full cavity
+    p(phi) p(u | phi) q'_{-k}."""
+
+    def __init__(self, cfg, xyz, a_obs, sigma, blocks, inducing, node_block=None, sightlines=None, K=None,
+                 prior=None):
+        from . import meanfn
+        sl = sightlines or epo.Sightlines(cfg, xyz)
+        self.cfg = dict(cfg)
+        pos = sl.grid.xyz()
+        self.mu0, self.s0sq = prior if prior is not None else meanfn.hyperprior(cfg)
+        self.mhat, self.J = meanfn.mean_and_jacobian(cfg, pos, self.mu0)
+        N = sl.grid.N
+        self.sl = sl
+        self.grid = sl.grid
+        self.m0 = None
+        self.K = node_cov(cfg) if K is None else K
+        gval, _, c = sl.linearise(self.mhat)
+        self.G = sl.G_dense(gval)
+        self.a_obs = np.asarray(a_obs, dtype=np.float64)
+        self.s2 = np.asarray(sigma, dtype=np.float64) ** 2
+        self.mu_a = c + self.G @ self.mhat               # muhat
+        self.H = self.G @ self.J
+        self.blocks = np.asarray(blocks)
+        self.nblk = int(self.blocks.max()) + 1 if self.blocks.size else 0
+        self.members = [np.nonzero(self.blocks == k)[0] for k in range(self.nblk)]
+        self.u = np.asarray(inducing, dtype=np.int64)
+        self.node_block = None if node_block is None else np.asarray(node_block)
+        R, M = len(self.u), len(self.mu0)
+        self.M = M
+        self.m_u = self.mhat[self.u]
+        self.Ju = self.J[self.u]
+        self.C = self.K[np.ix_(self.u, self.u)]
+        self.Cinv = np.linalg.inv(self.C)
+        self.Lam = np.zeros((self.nblk, R + M, R + M))
+        self.eta = np.zeros((self.nblk, R + M))
+
+    def _prior_z(self):
+        """Natural parameters of p(psi) p(u | phi) over z = (u, psi)."""
+        R, M = len(self.u), self.M
+        E = np.hstack([np.eye(R), -self.Ju])
+        P = E.T @ self.Cinv @ E
+        P[R:, R:] += np.diag(1.0 / self.s0sq)
+        return P, E.T @ self.Cinv @ self.m_u
+
+    def sweep(self, damping: float = 1.0):
+        R, M = len(self.u), self.M
+        Lam_tot, eta_tot = self.Lam.sum(axis=0), self.eta.sum(axis=0)
+        P0, e0 = self._prior_z()
+        new_L, new_e = np.zeros_like(self.Lam), np.zeros_like(self.eta)
+        for k in range(self.nblk):
+            idx = self.members[k]
+            mu, A, rho = self.block_joint(k)
+            Ainv = np.linalg.inv(A)
+            r = self.a_obs[idx] - mu
+            # p(u | a~_k, phi) = N(alpha + beta psi, C'_k)
+            alpha = self.m_u + rho.T @ Ainv @ r
+            beta = self.Ju - rho.T @ Ainv @ self.H[idx]
+            C1 = self.C - rho.T @ Ainv @ rho
+            C1inv = np.linalg.inv(0.5 * (C1 + C1.T))
+            E1 = np.hstack([np.eye(R), -beta])
+            P_cond, e_cond = E1.T @ C1inv @ E1, E1.T @ C1inv @ alpha
+            # p(a~_k | phi) = N(muhat_k + H_k psi, A_k)
+            Hk = self.H[idx]
+            P_marg = np.zeros((R + M, R + M))
+            P_marg[R:, R:] = Hk.T @ Ainv @ Hk
+            e_marg = np.concatenate([np.zeros(R), Hk.T @ Ainv @ r])
+            Lc, ec = Lam_tot - self.Lam[k], eta_tot - self.eta[k]            # reduced cavity
+            # tilted = q'_{-k} p(phi) p(u|a~_k,phi) p(a~_k|phi); cavity = p(phi) p(u|phi) q'_{-k}
+            Pphi = np.zeros((R + M, R + M))
+            Pphi[R:, R:] = np.diag(1.0 / self.s0sq)
+            L_til = Lc + Pphi + P_cond + P_marg
+            e_til = ec + e_cond + e_marg
+            new_L[k] = L_til - (P0 + Lc)
+            new_e[k] = e_til - (e0 + ec)
+        d = float(damping)
+        self.Lam = (1.0 - d) * self.Lam + d * new_L
+        self.eta = (1.0 - d) * self.eta + d * new_e
+
+    def posterior_z(self):
+        """(mean, cov) of q(u, psi)."""
+        P0, e0 = self._prior_z()
+        P = P0 + self.Lam.sum(axis=0)
+        V = np.linalg.inv(P)
+        V = 0.5 * (V + V.T)
+        return V @ (e0 + self.eta.sum(axis=0)), V
+
+    def posterior_u(self):
+        m, V = self.posterior_z()
+        R = len(self.u)
+        return m[:R], V[:R, :R]
+
+    def theta_posterior(self):
+        """Mean and covariance of phi = ln theta under q."""
+        m, V = self.posterior_z()
+        R = len(self.u)
+        return self.mu0 + m[R:], V[R:, R:]
+
+    def log_evidence(self) -> float:
+        """ln p(a~) with phi marginalised: a~ ~ N(muhat, Q + S + H S0 H^T)."""
+        S = len(self.a_obs)
+        rho = self.G @ self.K[:, self.u]
+        Q = rho @ self.Cinv @ rho.T
+        for k in range(self.nblk):
+            idx = self.members[k]
+            Q[np.ix_(idx, idx)] = self.G[idx] @ self.K @ self.G[idx].T
+        Q += np.diag(self.s2) + self.H @ np.diag(self.s0sq) @ self.H.T
+        r = self.a_obs - self.mu_a
+        _, logdet = np.linalg.slogdet(Q)
+        return float(-0.5 * (S * math.log(2 * math.pi) + logdet + r @ np.linalg.solve(Q, r)))
+
+    def predict(self):
+        """PIC predictive of f at every node: f_p = mhat_p + J_p psi + delta_p,
+        delta_p | a~_i, u, psi from the joint Gaussian of (delta_p, a~_i, u)
+        given psi, integrated over q(u, psi)."""
+        N = self.grid.N
+        mean, var = np.zeros(N), np.zeros(N)
+        mz, Vz = self.posterior_z()
+        R = len(self.u)
+        for i in range(self.nblk):
+            nodes = np.nonzero(self.node_block == i)[0]
+            if nodes.size == 0:
+                continue
+            idx = self.members[i]
+            mu, A, rho = self.block_joint(i)
+            J = np.block([[A, rho], [rho.T, self.C]])
+            kst = np.vstack([self.G[idx] @ self.K[:, nodes], self.K[np.ix_(self.u, nodes)]])
+            w = np.linalg.solve(J, kst)
+            wa, wu = w[: len(idx)], w[len(idx):]
+            # E[delta_p | a~_i, u, psi] = wa^T (a~_i - muhat_i - H_i psi) + wu^T (u - mhat_u - J_u psi)
+            # so f_p = const + b^T z with b = (wu, J_p - H_i^T wa - J_u^T wu)
+            b = np.vstack([wu, self.J[nodes].T - self.H[idx].T @ wa - self.Ju.T @ wu])
+            const = self.mhat[nodes] + wa.T @ (self.a_obs[idx] - mu) - wu.T @ self.m_u
+            mean[nodes] = const + b.T @ mz
+            var[nodes] = (np.diag(self.K)[nodes] - np.einsum("ij,ij->j", kst, w)
+                          + np.einsum("ij,ij->j", b, Vz @ b))
+        return mean, var

@@ -174,3 +174,128 @@ def test_paper_sign_of_the_conditional_covariance_fails():
     plus = o.C + rho.T @ np.linalg.solve(A, rho)
     _, C1 = o.u_given_block(0)
     assert np.trace(plus) > np.trace(o.C) > np.trace(C1)
+
+
+# --- the mean parameters in the sites (q(u, Theta)) --------------------------
+
+THETA_PRIOR = (1500.0, 150.0, 7.5e-4, 600.0, 0.1)
+THETA_TRUE = (1000.0, 200.0, 1.2e-3, 500.0, 0.2)
+
+
+def _case_theta(n=5, L=400.0, stars=50, n_lon=2, n_lat=2, R=10, seed=6):
+    from oracle import meanfn
+    w = Workload("pitct", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law="uniform", d_max_pc=L,
+                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood="gauss_linear", seed_id=seed)
+    cfg = w.ep_fields()
+    # Vecchia conditioning over the whole box: Q0 = K^{-1} exactly (the
+    # reference below uses the precision form)
+    cfg.update(sun_radius_pc=8000.0, bump_width_pc=200.0, theta_prior=THETA_PRIOR,
+               vecchia_radius_pc=2.0 * L)
+    raw = draw(w)
+    sl = epo.Sightlines(cfg, raw["xyz"])
+    vec = epo.Vecchia(cfg)
+    pos = vec.grid.xyz()
+    m_true, _ = meanfn.mean_and_jacobian(cfg, pos, np.log(THETA_TRUE))
+    f_true = m_true + vec.draw(0.0, raw["xi"])
+    mu0, _ = meanfn.hyperprior(cfg)
+    mhat, _ = meanfn.mean_and_jacobian(cfg, pos, mu0)
+    gval, _, c = sl.linearise(mhat)
+    a = c + sl.G_dense(gval) @ f_true + raw["sigma"] * raw["eps"]
+    blocks = sky_cells(w, raw["xyz"], n_lon, n_lat)
+    _, blocks = np.unique(blocks, return_inverse=True)
+    nb = np.minimum(sky_cells(w, node_positions(w), n_lon, n_lat), blocks.max())
+    rng = np.random.default_rng(seed)
+    u = np.sort(rng.choice(w.N, size=R, replace=False)) if R < w.N else np.arange(w.N)
+    return w, cfg, raw, a, sl, vec, blocks, nb, u
+
+
+def _exact_theta(cfg, raw, a, sl, vec):
+    """The exact joint posterior of (f, phi) (dense EP with the linear mean in
+    the Gaussian mode: one sweep is exact), as f's mean, covariance, phi's
+    moments, and the evidence by the information form."""
+    from oracle import meanfn
+    ep = meanfn.DenseEPTheta(cfg, raw["xyz"], a, raw["sigma"], sightlines=sl, vecchia=vec)
+    ep.sweep()
+    mu, Sig, Gx, cp = ep.posterior_x()
+    A, c0 = ep.f_operator()
+    return c0 + A @ mu, A @ Sig @ A.T, ep.theta_posterior()
+
+
+def test_theta_sites_every_node_inducing_is_exact():
+    w, cfg, raw, a, sl, vec, blocks, nb, u = _case_theta(R=125)
+    o = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    fm, fV, (pm_, pV_) = _exact_theta(cfg, raw, a, sl, vec)
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, fm) < 1e-8 and _rel(V_u, fV) < 1e-6
+    tm, tV = o.theta_posterior()
+    assert _rel(tm, pm_) < 1e-9 and _rel(tV, pV_) < 1e-7
+    pm, pv = o.predict()
+    assert _rel(pm, fm) < 1e-8 and _rel(pv, np.diag(fV)) < 1e-6
+
+
+def test_theta_sites_one_block_is_exact():
+    w, cfg, raw, a, sl, vec, blocks, nb, u = _case_theta(n_lon=1, n_lat=1, R=12)
+    assert blocks.max() == 0
+    o = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    fm, fV, (pm_, pV_) = _exact_theta(cfg, raw, a, sl, vec)
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, fm[u]) < 1e-9 and _rel(V_u, fV[np.ix_(u, u)]) < 1e-7
+    tm, tV = o.theta_posterior()
+    assert _rel(tm, pm_) < 1e-9 and _rel(tV, pV_) < 1e-7
+    pm, pv = o.predict()
+    assert _rel(pm, fm) < 1e-8 and _rel(pv, np.diag(fV)) < 1e-6
+    # evidence: a~ ~ N(muhat, G K G^T + S + H S0 H^T), by the determinant lemma
+    r = a - o.mu_a
+    # marginalise delta first: cov_1 = S + G K G^T, then phi: + H S0 H^T
+    C1 = np.diag(o.s2) + o.G @ o.K @ o.G.T
+    C1inv = np.linalg.inv(C1)
+    M = np.diag(1.0 / o.s0sq) + o.H.T @ C1inv @ o.H
+    ld = (np.linalg.slogdet(C1)[1] + np.linalg.slogdet(M)[1] + np.log(o.s0sq).sum())
+    t = o.H.T @ C1inv @ r
+    quad = r @ C1inv @ r - t @ np.linalg.solve(M, t)
+    ref = -0.5 * (len(r) * math.log(2 * math.pi) + ld + quad)
+    assert abs(o.log_evidence() - ref) < 1e-9 * abs(ref)
+
+
+def test_theta_sites_closed_form_with_blocks():
+    """Several blocks: q(u, psi) equals the information form of
+    p(a~ | u, psi) = N(muhat + Psi (u - mhat_u - J_u psi) + H psi, blockdiag B_k)
+    under the prior N(0, C) x N(0, S0) of (u - m(phi), psi)."""
+    w, cfg, raw, a, sl, vec, blocks, nb, u = _case_theta(stars=70, R=20, seed=7)
+    assert blocks.max() >= 2
+    o = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep()
+    S = len(a)
+    rho = o.G @ o.K[:, u]
+    Psi = rho @ o.Cinv
+    Lam = np.zeros((S, S))
+    for k in range(o.nblk):
+        idx = o.members[k]
+        Lam[np.ix_(idx, idx)] = (o.G[idx] @ o.K @ o.G[idx].T + np.diag(o.s2[idx]) - rho[idx] @ o.Cinv @ rho[idx].T)
+    Li = np.linalg.inv(Lam)
+    X = np.hstack([Psi, o.H])                                  # coordinates (du, psi)
+    R, M = len(u), o.M
+    P = np.zeros((R + M, R + M))
+    P[:R, :R] = o.Cinv
+    P[R:, R:] = np.diag(1.0 / o.s0sq)
+    P += X.T @ Li @ X
+    V = np.linalg.inv(P)
+    m = V @ (X.T @ Li @ (a - o.mu_a))                          # mean of (du, psi)
+    T = np.hstack([np.eye(R), o.Ju])                           # u = mhat_u + du + J_u psi
+    mu_ref, V_ref = o.m_u + T @ m, T @ V @ T.T
+    mu_u, V_u = o.posterior_u()
+    assert _rel(mu_u, mu_ref) < 1e-9 and _rel(V_u, V_ref) < 1e-8
+    tm, tV = o.theta_posterior()
+    assert _rel(tm, o.mu0 + m[R:]) < 1e-9 and _rel(tV, V[R:, R:]) < 1e-8
+
+
+def test_theta_sites_damping():
+    w, cfg, raw, a, sl, vec, blocks, nb, u = _case_theta(stars=50, R=10, seed=9)
+    full = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    full.sweep(1.0)
+    half = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl, K=full.K)
+    for t in range(1, 3):
+        half.sweep(0.5)
+        assert _rel(half.Lam, (1 - 0.5 ** t) * full.Lam) < 1e-10
