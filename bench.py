@@ -219,6 +219,27 @@ def main():
         g.sweep()
         gm, gv = g.posterior_mean(), g.marginal_var()
         g.close()
+        # the same with the disc + bump mean's parameters in the sites, q(u, Theta),
+        # on observations drawn around THETA_TRUE
+        ct = E.make_config(gl, leaf_size=args.leaf, device=0, mean_fn="disc_bump")
+        sim = E.make_config(gl, device=0, mean_fn="disc_bump", theta_prior=THETA_TRUE)
+        _, a_th = E.ep_simulate(sim, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+        gt = E.EP(ct, raw["xyz"], a_th, raw["sigma"])
+        gt.pitc_setup(blocks, u, nb)
+        for _ in range(args.warmup):
+            gt.pitc_sweep(1.0)
+        tt = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            gt.pitc_sweep(1.0)
+            tt.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        gt.pitc_predict()
+        tpt = time.perf_counter() - t0
+        pm_t, pc_t = gt.pitc_theta()
+        info_t = gt.pitc_info()
+        gt.close()
+        sd_t = np.sqrt(np.diag(pc_t))
         z_pic = (f_t - pm) / np.sqrt(pv)
         z_grid = (f_t - gm) / np.sqrt(gv)
         return {
@@ -234,6 +255,13 @@ def main():
                 "median_var_ratio_pic_over_grid": float(np.median(pv / gv)),
                 "rms_z_true_pic": float(np.sqrt(np.mean(z_pic ** 2))),
                 "rms_z_true_grid": float(np.sqrt(np.mean(z_grid ** 2)))},
+            "with_mean_parameters": {
+                "ms_sweep": float(np.mean(tt)) * 1e3, "ms_predict": tpt * 1e3,
+                "sweep_tflops": info_t["sweep_flops"] / (float(np.mean(tt))) / 1e12,
+                "theta_true": list(THETA_TRUE),
+                "theta_mean": [float(v) for v in np.exp(pm_t + 0.5 * sd_t ** 2)],
+                "log_theta_sd": [float(v) for v in sd_t],
+                "z_true": [float(v) for v in (pm_t - np.log(THETA_TRUE)) / sd_t]},
             "note": ("flops: algorithmic (unpadded) dense work of the pass; the grid path uses the Vecchia "
                      "precision, PITC the tapered covariance itself (the two priors agree where the Vecchia "
                      "conditioning radius covers the taper)"),

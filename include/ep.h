@@ -366,17 +366,20 @@ int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *o
 
 /* ---- The paper's sparse approximation: PITC sub-catalogue EP with a PIC
  * predictive (Sec. 4.1, App. A.1, App. B, App. C) ----
- * Needs a context with likelihood GAUSS_LINEAR and mean_fn CONSTANT: the
- * observed log-extinctions a~_n ~ N(a_n, sigma_n^2) with a_n = c_n + g_n . f
- * the sightline linearised at the prior mean (Sec. 4.1's Gaussian case),
- * f ~ N(m0 1, K), K the tapered covariance between nodes (not the Vecchia
+ * Needs a context with likelihood GAUSS_LINEAR: the observed
+ * log-extinctions a~_n ~ N(a_n, sigma_n^2) with a_n = c_n + g_n . f the
+ * sightline linearised at the prior mean (Sec. 4.1's Gaussian case),
+ * f ~ N(m, K), K the tapered covariance between nodes (not the Vecchia
  * precision: this path is the paper's alternative to it).  Stars are split
  * into sub-catalogues k; u = f at R inducing nodes.  Blocks are independent
- * given u (PITC); EP keeps one Gaussian site on u per sub-catalogue, the
- * site of p(u | a~_k) / p(u) (the conditional with the minus sign the
- * Gaussian conditional needs; App. B prints a plus).  The hyper-parameters
- * are fixed, so every block's tilted distribution is Gaussian and one
- * undamped sweep reaches the fixed point.
+ * given u (PITC); EP keeps one Gaussian site per sub-catalogue, the site of
+ * p(u | a~_k) / p(u) (the conditional with the minus sign the Gaussian
+ * conditional needs; App. B prints a plus).  With mean_fn CONSTANT, m = m0
+ * and the sites are on u; with mean_fn DISC_BUMP the prior mean is the
+ * disc + bump function linearised at the hyperprior mean, m = mhat + J psi,
+ * and the sites are on (u, psi) (the paper's q(u, Theta)), psi = ln theta -
+ * phihat with its log-normal hyperprior.  Every block's tilted distribution
+ * is Gaussian, so one undamped sweep reaches the fixed point.
  * Memory: per sub-catalogue O((N_k + R + P_k) N_k + V_k (V_k + R + P_k))
  * doubles, V_k the nodes its sightlines touch and P_k the nodes it predicts.
  *
@@ -385,7 +388,7 @@ int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *o
  * node_block (n^3 int32: the sub-catalogue whose stars each node's
  * prediction conditions on).  Plans and allocates; replaces an earlier set-up
  * and its sites.  Errors: INVALID_ARG (ranges, empty block, duplicate
- * inducing node, wrong likelihood or mean), OOM/DEVICE.
+ * inducing node, wrong likelihood), OOM/DEVICE.
  * ep_pitc_sweep: one parallel pass over the sub-catalogues from the same
  * q(u); sites damped by 'damping' in (0, 1] in natural parameters (the first
  * sweep starts from zero sites).  lnZ (may be NULL): the PITC log marginal
@@ -412,6 +415,10 @@ int ep_pitc_setup(ep_ctx *ctx, int32_t n_blocks, const int32_t *star_block, int6
 int ep_pitc_sweep(ep_ctx *ctx, double damping, double *lnZ);
 int ep_pitc_inducing(ep_ctx *ctx, double *mean, double *cov);
 int ep_pitc_predict(ep_ctx *ctx, double *mean, double *var);
+/* Mean (5) and covariance (5 x 5, row-major) of phi = ln theta under
+ * q(u, Theta) (mean_fn DISC_BUMP).  STATE before the first sweep or with a
+ * constant mean. */
+int ep_pitc_theta(ep_ctx *ctx, double *mean, double *cov);
 /* Sizes and algorithmic flop counts of the current set-up (STATE without one). */
 int ep_pitc_info(const ep_ctx *ctx, ep_pitc_stats *out);
 

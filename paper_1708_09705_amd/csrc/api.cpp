@@ -2082,6 +2082,14 @@ static PitcBorrow pitc_borrow(ep_ctx* ctx) {
     b.d_c = ctx->d_c;
     b.d_A = ctx->d_A;
     b.d_sigma = ctx->d_sigma;
+    b.M = ctx->M;
+    b.d_mhat = ctx->d_mhat;
+    b.d_J = ctx->d_J;
+    b.d_h = ctx->d_h;
+    for (int j = 0; j < ctx->M; j++) {
+        b.s0sq[j] = ctx->s0sq[j];
+        b.phihat[j] = ctx->phihat[j];
+    }
     // what hbm_cap_bytes leaves after the context's own allocations
     b.cap_bytes = ctx->cfg.hbm_cap_bytes > 0 ? std::max<int64_t>(ctx->cfg.hbm_cap_bytes - ctx->dev_bytes, 1) : 0;
     return b;
@@ -2101,8 +2109,8 @@ int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int6
         g_tls_err = "ep_pitc_setup: null context";
         return EP_ERR_INVALID_ARG;
     }
-    if (ctx->cfg.likelihood != EP_LIK_GAUSS_LINEAR || ctx->M) {
-        ctx->err = "ep_pitc_setup: needs likelihood GAUSS_LINEAR and mean_fn CONSTANT";
+    if (ctx->cfg.likelihood != EP_LIK_GAUSS_LINEAR) {
+        ctx->err = "ep_pitc_setup: needs likelihood GAUSS_LINEAR";
         return EP_ERR_INVALID_ARG;
     }
     if (n_blocks < 1 || n_inducing < 1 || !star_block || !inducing || !node_block) {
@@ -2116,7 +2124,7 @@ int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int6
     HIPCHK(host_view(dev, inducing, n_inducing, hu));
     HIPCHK(host_view(dev, node_block, ctx->g.N(), hn));
     HIPCHK(hipSetDevice(ctx->cfg.device));
-    enqueue_linearise(ctx);   // the frozen sightline weights at the prior mean
+    enqueue_linearise(ctx);   // the frozen sightline weights (and h_n) at the prior mean
     HIPCHK(hipStreamSynchronize(ctx->stream));
     pitc_free(ctx->pitc);
     ctx->pitc = nullptr;
@@ -2148,6 +2156,16 @@ int ep_pitc_inducing(ep_ctx* ctx, double* mean, double* cov) {
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     return pitc_status(ctx, pitc_inducing(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
+}
+
+int ep_pitc_theta(ep_ctx* ctx, double* mean, double* cov) {
+    if (!ctx || !ctx->pitc) {
+        if (ctx) ctx->err = "ep_pitc_theta: no ep_pitc_setup";
+        return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    std::string err;
+    return pitc_status(ctx, pitc_theta(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
 }
 
 int ep_pitc_predict(ep_ctx* ctx, double* mean, double* var) {

@@ -66,6 +66,13 @@ struct Blk {
 
 struct PitcState {
     int K = 0, R = 0, rpad = 0;
+    int M = 0, xdim = 0;   // mean parameters in the sites; posterior variables x = (v, psi), padded
+    int64_t u0 = 0;        // the inducing nodes in d_ids
+    PitcMeanDev mean{};
+    PitcPriorDev prior{};
+    Phi5 phihat{};
+    double ln_det_s0 = 0;
+    int64_t offT = 0;
     int64_t S = 0, N = 0;
     std::vector<Blk> blk;
     int64_t ws_n = 0, wx_n = 0;
@@ -83,7 +90,7 @@ struct PitcState {
     BatchEnt* d_be = nullptr;
     GemmTask* d_tasks = nullptr;
     double* d_table = nullptr;
-    double *d_mean = nullptr, *d_var = nullptr;
+    double *d_mean = nullptr, *d_var = nullptr, *d_theta = nullptr;
     int* d_err = nullptr;
     PitcCovDev cov{};
     FrontsDev F{};
@@ -366,7 +373,17 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     s->N = N;
     s->m0 = b.pp->mean;
     const int rpad = s->rpad;
-    const int64_t e1 = rpad + TS;
+    s->M = b.M;
+    const int hb = b.M > 0 ? TS : 0;   // the tile of the mean parameters' rows
+    s->xdim = rpad + hb;
+    const int xdim = s->xdim;
+    const int64_t e1 = xdim + TS;
+    s->prior.M = b.M;
+    for (int j = 0; j < b.M; j++) {
+        s->prior.s0inv[j] = 1.0 / b.s0sq[j];
+        s->ln_det_s0 += std::log(b.s0sq[j]);
+        s->phihat.v[j] = b.phihat[j];
+    }
 
     // stars by block (ascending ids), node sets, prediction nodes
     std::vector<int32_t> stars;
@@ -408,6 +425,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         B.ppad = (int)pad64(std::max(B.np, 1));
     }
     const int64_t u0 = (int64_t)ids.size();
+    s->u0 = u0;
     ids.insert(ids.end(), inducing, inducing + R);
     for (int k = 0; k < n_blocks; k++) {
         s->blk[k].p0 = (int64_t)ids.size();
@@ -416,7 +434,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
 
     // workspace layout (doubles, every offset a multiple of 64)
     int64_t w = 0;
-    int maxld = 2 * rpad + TS;
+    int maxld = 2 * xdim + TS;
     s->offG = w;
     for (auto& B : s->blk) {
         B.G = w;
@@ -424,7 +442,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     }
     s->nG = w - s->offG;
     for (auto& B : s->blk) {
-        B.m = B.npad + rpad + TS + B.ppad;
+        B.m = B.npad + rpad + hb + TS + B.ppad;
         maxld = std::max({maxld, B.m, B.vpad, B.npad, B.ppad});
         B.KV = w;
         w += (int64_t)B.vpad * (B.vpad + rpad + B.ppad);
@@ -442,33 +460,37 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         if (q == 1) s->offAt = w;
         for (auto& B : s->blk) {
             (q == 0 ? B.Kt : (q == 1 ? B.At : B.SAt)) = w;
-            w += (int64_t)B.ppad * rpad;
+            w += (int64_t)B.ppad * xdim;
         }
     }
     s->nKt = s->offAt - s->offKt;
     s->offLam = w;
     w += (int64_t)n_blocks * e1 * e1;
     s->mC = 2 * rpad;
-    s->mQ = 2 * rpad + TS;
-    s->mE = rpad + TS;
+    s->mQ = 2 * xdim + TS;
+    s->mE = xdim + TS;
     s->offC = w;
     w += (int64_t)s->mC * rpad;
     s->offQ = w;
-    w += (int64_t)s->mQ * rpad;
+    w += (int64_t)s->mQ * xdim;
     s->offE = w;
-    w += (int64_t)s->mE * rpad;
+    w += (int64_t)s->mE * xdim;
     for (int64_t* o : {&s->offSnew, &s->offSsites}) {
         *o = w;
         w += e1 * e1;
     }
-    for (int64_t* o : {&s->offSig, &s->offT1, &s->offSigU}) {
+    s->offSig = w;
+    w += (int64_t)xdim * xdim;
+    for (int64_t* o : {&s->offT, &s->offT1}) {
         *o = w;
-        w += (int64_t)rpad * rpad;
+        w += (int64_t)rpad * xdim;
     }
-    for (int64_t* o : {&s->offMu, &s->offMuU}) {
-        *o = w;
-        w += (int64_t)rpad * TS;
-    }
+    s->offSigU = w;
+    w += (int64_t)rpad * rpad;
+    s->offMu = w;
+    w += (int64_t)xdim * TS;
+    s->offMuU = w;
+    w += (int64_t)rpad * TS;
     s->offLnz = w;
     w += TS;
     // the product kernel stages whole 256 x 128 blocks: a pad of 256 leading
@@ -489,7 +511,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
             const int q = k - n_blocks;
             foff[k] = q == 0 ? s->offC : (q == 1 ? s->offQ : s->offE);
             fm[k] = q == 0 ? s->mC : (q == 1 ? s->mQ : s->mE);
-            fnv[k] = rpad;
+            fnv[k] = q == 0 ? rpad : xdim;
         }
         fxoff[k] = xo;
         xo += (int64_t)fnv[k] * fnv[k];
@@ -560,7 +582,6 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     Gemm gs{tasks, fs}, gp{tasks, fp};
     auto begin = [&](Range& r) { r.off = (int64_t)tasks.size(); };
     auto end = [&](Range& r) { r.n = (int64_t)tasks.size() - r.off; };
-    const Op LC{s->offC, s->mC, false}, LCt{s->offC, s->mC, true};          // L_C (lower), transposed
     const Op XCt{s->offC + rpad, s->mC, false}, XCtT{s->offC + rpad, s->mC, true};   // L_C^{-T}, its transpose
     {
         std::vector<int> one{n_blocks};
@@ -630,7 +651,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         std::copy(ids.begin() + B.p0, ids.begin() + B.p0 + B.np, col.begin());
         const std::vector<Win> w = windows(B, col);
         gs.win = &w;
-        gs(B.F + B.npad + rpad + TS, B.m, B.npad, B.ppad, true, false, true, Op{B.G, B.npad, false},
+        gs(B.F + B.npad + rpad + hb + TS, B.m, B.npad, B.ppad, true, false, true, Op{B.G, B.npad, false},
            Op{B.KV + (int64_t)B.vpad * (B.vpad + rpad), B.vpad, false}, B.vpad, false, &Zt, &KtT, rpad, true, B.nst,
            B.np, B.nv, R);
         gs.win = nullptr;
@@ -643,14 +664,14 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         double ff = 0;
         plan_factor(blks, foff, fm, fnv, tasks, flists, be, s->facB, ff);
         for (const Blk& B : s->blk)
-            fs += (double)B.nst * B.nst * B.nst / 3.0 + (double)B.nst * B.nst * (R + 1 + B.np);
+            fs += (double)B.nst * B.nst * B.nst / 3.0 + (double)B.nst * B.nst * (R + b.M + 1 + B.np);
     }
     begin(s->tLam);
     for (int k = 0; k < n_blocks; k++) {   // [W_Z | w_r]^T [W_Z | w_r]
         const Blk& B = s->blk[k];
         gs(s->offLam + (int64_t)k * e1 * e1, (int)e1, (int)e1, (int)e1, true, false, false,
-           Op{B.F + B.npad, B.m, false}, Op{B.F + B.npad, B.m, true}, B.npad, false, nullptr, nullptr, 0, false, R + 1,
-           R + 1, B.nst, 0);
+           Op{B.F + B.npad, B.m, false}, Op{B.F + B.npad, B.m, true}, B.npad, false, nullptr, nullptr, 0, false,
+           R + b.M + 1, R + b.M + 1, B.nst, 0);
     }
     end(s->tLam);
     balance_xcd(tasks, s->tLam.off, s->tLam.n);
@@ -658,42 +679,44 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         std::vector<int> qe{n_blocks + 1, n_blocks + 2};
         double ff = 0;
         plan_factor(qe, foff, fm, fnv, tasks, flists, be, s->facQE, ff);
-        fs += 2.0 * ((double)R * R * R / 3.0) + (double)R * R * (R + 2);
+        const double X = R + b.M;
+        fs += 2.0 * (X * X * X / 3.0) + X * X * (X + 2);
     }
     begin(s->tSig);   // Sigma~ = L_q^{-T} L_q^{-1}
-    gs(s->offSig, rpad, rpad, rpad, true, false, false, Op{s->offQ + rpad, s->mQ, false},
-       Op{s->offQ + rpad, s->mQ, true}, rpad, false, nullptr, nullptr, 0, false, R, R, R, 0);
+    gs(s->offSig, xdim, xdim, xdim, true, false, false, Op{s->offQ + xdim, s->mQ, false},
+       Op{s->offQ + xdim, s->mQ, true}, xdim, false, nullptr, nullptr, 0, false, R + b.M, R + b.M, R + b.M, 0);
     end(s->tSig);
     begin(s->tMu);    // mu~ = L_q^{-T} (L_q^{-1} h)
-    gs(s->offMu, rpad, rpad, TS, true, false, false, Op{s->offQ + rpad, s->mQ, false},
-       Op{s->offQ + 2 * rpad, s->mQ, true}, rpad, false, nullptr, nullptr, 0, false, R, 1, R, 0);
+    gs(s->offMu, xdim, xdim, TS, true, false, false, Op{s->offQ + xdim, s->mQ, false},
+       Op{s->offQ + 2 * xdim, s->mQ, true}, xdim, false, nullptr, nullptr, 0, false, R + b.M, 1, R + b.M, 0);
     end(s->tMu);
     double fi = 0;
     Gemm gi{tasks, fi};
     begin(s->tT1);
-    gi(s->offT1, rpad, rpad, rpad, true, false, false, LC, Op{s->offSig, rpad, false}, rpad, false, nullptr, nullptr,
-       0, false, R, R, R, 0);
+    const Op Tn{s->offT, rpad, false}, Tt{s->offT, rpad, true};   // T = [L_C | J_u], u = m(phihat) + T x
+    gi(s->offT1, rpad, rpad, xdim, true, false, false, Tn, Op{s->offSig, xdim, false}, xdim, false, nullptr, nullptr,
+       0, false, R, R + b.M, R + b.M, 0);
     end(s->tT1);
     begin(s->tSigU);
-    gi(s->offSigU, rpad, rpad, rpad, true, false, false, Op{s->offT1, rpad, false}, LCt, rpad, false, nullptr, nullptr,
-       0, false, R, R, R, 0);
+    gi(s->offSigU, rpad, rpad, rpad, true, false, false, Op{s->offT1, rpad, false}, Tt, xdim, false, nullptr, nullptr,
+       0, false, R, R, R + b.M, 0);
     end(s->tSigU);
     begin(s->tMuU);
-    gi(s->offMuU, rpad, rpad, TS, true, false, false, LC, Op{s->offMu, rpad, false}, rpad, false, nullptr, nullptr, 0,
+    gi(s->offMuU, rpad, rpad, TS, true, false, false, Tn, Op{s->offMu, xdim, false}, xdim, false, nullptr, nullptr, 0,
        false, R, 1, R, 0);
     end(s->tMuU);
     begin(s->tAt);
     for (const Blk& B : s->blk) {   // A^T = K~^T - E^T W_Z (A^T holds a copy of K~^T)
-        const Op Ed{B.F + B.npad + rpad + TS, B.m, false}, WZ{B.F + B.npad, B.m, true};
-        gp(B.At, B.ppad, B.ppad, rpad, false, false, false, Ed, WZ, B.npad, true, nullptr, nullptr, 0, false, B.np, R,
-           B.nst, 0);
+        const Op Ed{B.F + B.npad + rpad + hb + TS, B.m, false}, WZ{B.F + B.npad, B.m, true};
+        gp(B.At, B.ppad, B.ppad, xdim, false, false, false, Ed, WZ, B.npad, true, nullptr, nullptr, 0, false, B.np,
+           R + b.M, B.nst, 0);
     }
     end(s->tAt);
     balance_xcd(tasks, s->tAt.off, s->tAt.n);
     begin(s->tSAt);
     for (const Blk& B : s->blk)   // (Sigma~ A)^T = A^T Sigma~
-        gp(B.SAt, B.ppad, B.ppad, rpad, true, false, false, Op{B.At, B.ppad, false}, Op{s->offSig, rpad, false}, rpad,
-           false, nullptr, nullptr, 0, false, B.np, R, R, 0);
+        gp(B.SAt, B.ppad, B.ppad, xdim, true, false, false, Op{B.At, B.ppad, false}, Op{s->offSig, xdim, false}, xdim,
+           false, nullptr, nullptr, 0, false, B.np, R + b.M, R + b.M, 0);
     end(s->tSAt);
     balance_xcd(tasks, s->tSAt.off, s->tSAt.n);
     s->flops_sweep = fs;
@@ -713,6 +736,9 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         d.m = B.m;
         d.npad = B.npad;
         d.rpad = rpad;
+        d.xdim = xdim;
+        d.rrow = B.npad + rpad + hb;
+        d.drow = B.npad + rpad + hb + TS;
         d.ppad = B.ppad;
         d.nstars = B.nst;
         d.npred = B.np;
@@ -733,7 +759,8 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         (rc = dupload(s, &s->d_foff, foff, err)) || (rc = dupload(s, &s->d_fxoff, fxoff, err)) ||
         (rc = dupload(s, &s->d_fm, fm32, err)) || (rc = dupload(s, &s->d_fnvpad, fnv32, err)) ||
         (rc = dupload(s, &s->d_table, table, err)) || (rc = dalloc(s, &s->d_mean, N, err)) ||
-        (rc = dalloc(s, &s->d_var, N, err)) || (rc = dalloc(s, &s->d_err, 1, err)))
+        (rc = dalloc(s, &s->d_var, N, err)) || (rc = dalloc(s, &s->d_err, 1, err)) ||
+        (rc = dalloc(s, &s->d_theta, 8 + 64, err)))
         return fail(rc);
     // the whole workspace starts at zero (padding rows and columns are read
     // as operands)
@@ -742,6 +769,12 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         err = "pitc: memset failed";
         return fail(EP_ERR_DEVICE);
     }
+    s->mean.mhat = b.M > 0 ? b.d_mhat : nullptr;
+    s->mean.J = b.d_J;
+    s->mean.h = b.d_h;
+    s->mean.m0 = s->m0;
+    s->mean.N = N;
+    for (int j = 0; j < b.M; j++) s->mean.phihat[j] = b.phihat[j];
     s->cov.table = s->d_table;
     s->cov.n = b.g->n;
     s->cov.w = wmax;
@@ -767,19 +800,21 @@ int pitc_sweep(PitcState* s, const PitcBorrow& b, double damping, double* lnZ, s
     launch_pitc_kfill(st, s->d_jobs, s->d_jobbase, s->njobs, s->ntiles, s->cov, s->d_ids, s->ws);
     launch_pitc_cfront_prep(st, s->ws + s->offC, s->mC, s->R, rpad);
     enqueue_factor(s, st, s->facC);
-    for (const Range* r : {&s->tM1, &s->tZt, &s->tB, &s->tKt, &s->tD}) gemm_range(s, st, *r);
-    launch_pitc_block_prep(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, b.d_A, b.d_sigma, s->m0, s->ws);
+    for (const Range* r : {&s->tM1, &s->tZt, &s->tB, &s->tKt}) gemm_range(s, st, *r);
+    if (s->M) launch_pitc_kt_j(st, s->d_blk, s->d_predbase, s->K, s->npred_tasks, s->d_ids, s->mean, s->ws);
+    gemm_range(s, st, s->tD);
+    launch_pitc_block_prep(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, b.d_A, b.d_sigma, s->mean, s->ws);
     enqueue_factor(s, st, s->facB);
     gemm_range(s, st, s->tLam);
-    const int64_t e1 = rpad + TS;
+    const int64_t e1 = s->xdim + TS;
     launch_pitc_sum_blocks(st, s->ws + s->offLam, s->K, e1 * e1, s->ws + s->offSnew);
     launch_pitc_sites_fronts(st, s->ws + s->offSnew, s->ws + s->offSsites, damping, !s->swept, s->ws + s->offQ, s->mQ,
-                             s->ws + s->offE, s->mE, rpad);
+                             s->ws + s->offE, s->mE, rpad, s->xdim, s->prior);
     enqueue_factor(s, st, s->facQE);
     gemm_range(s, st, s->tSig);
     gemm_range(s, st, s->tMu);
-    launch_pitc_lnz(st, s->d_blk, s->K, s->ws, s->ws + s->offE, s->mE, rpad, s->ws + s->offSnew, s->S,
-                    s->ws + s->offLnz);
+    launch_pitc_lnz(st, s->d_blk, s->K, s->ws, s->ws + s->offE, s->mE, s->xdim, s->ws + s->offSnew, s->S,
+                    s->ln_det_s0, s->ws + s->offLnz);
     int bad = 0;
     double lz = 0;
     PCHK(hipMemcpyAsync(&bad, s->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -801,13 +836,33 @@ int pitc_inducing(PitcState* s, const PitcBorrow& b, double* mean, double* cov, 
         return EP_ERR_STATE;
     }
     hipStream_t st = b.st;
+    launch_pitc_build_t(st, s->ws + s->offC, s->mC, s->d_ids + s->u0, s->R, s->rpad, s->xdim, s->mean,
+                        s->ws + s->offT);
     for (const Range* r : {&s->tT1, &s->tSigU, &s->tMuU}) gemm_range(s, st, *r);
-    launch_pitc_add_const(st, s->ws + s->offMuU, s->R, s->m0);
+    launch_pitc_add_mean(st, s->ws + s->offMuU, s->d_ids + s->u0, s->R, s->mean);
     const size_t R = (size_t)s->R;
     if (mean) PCHK(hipMemcpyAsync(mean, s->ws + s->offMuU, sizeof(double) * R, kind, st));
     if (cov)
         PCHK(hipMemcpy2DAsync(cov, sizeof(double) * R, s->ws + s->offSigU, sizeof(double) * s->rpad,
                               sizeof(double) * R, R, kind, st));
+    PCHK(hipStreamSynchronize(st));
+    PCHK(hipGetLastError());
+    return EP_OK;
+}
+
+int pitc_theta(PitcState* s, const PitcBorrow& b, double* mean, double* cov, hipMemcpyKind kind, std::string& err) {
+    if (!s->swept) {
+        err = "pitc_theta: no sweep yet";
+        return EP_ERR_STATE;
+    }
+    if (!s->M) {
+        err = "pitc_theta: the context has no inferred mean parameters (mean_fn CONSTANT)";
+        return EP_ERR_STATE;
+    }
+    hipStream_t st = b.st;
+    launch_pitc_theta_out(st, s->ws + s->offMu, s->ws + s->offSig, s->xdim, s->rpad, s->M, s->phihat, s->d_theta);
+    if (mean) PCHK(hipMemcpyAsync(mean, s->d_theta, sizeof(double) * s->M, kind, st));
+    if (cov) PCHK(hipMemcpyAsync(cov, s->d_theta + s->M, sizeof(double) * s->M * s->M, kind, st));
     PCHK(hipStreamSynchronize(st));
     PCHK(hipGetLastError());
     return EP_OK;
@@ -822,8 +877,8 @@ int pitc_predict(PitcState* s, const PitcBorrow& b, double* mean, double* var, h
     PCHK(hipMemcpyAsync(s->ws + s->offAt, s->ws + s->offKt, sizeof(double) * s->nKt, hipMemcpyDeviceToDevice, st));
     gemm_range(s, st, s->tAt);
     gemm_range(s, st, s->tSAt);
-    launch_pitc_predict(st, s->d_blk, s->d_predbase, s->K, s->npred_tasks, s->ws, s->d_ids, s->ws + s->offMu, s->m0,
-                        s->k0, s->rpad, s->d_mean, s->d_var);
+    launch_pitc_predict(st, s->d_blk, s->d_predbase, s->K, s->npred_tasks, s->ws, s->d_ids, s->ws + s->offMu, s->mean,
+                        s->k0, s->d_mean, s->d_var);
     if (mean) PCHK(hipMemcpyAsync(mean, s->d_mean, sizeof(double) * s->N, kind, st));
     if (var) PCHK(hipMemcpyAsync(var, s->d_var, sizeof(double) * s->N, kind, st));
     PCHK(hipStreamSynchronize(st));

@@ -58,27 +58,40 @@ __global__ __launch_bounds__(256) void k_kfill(const PitcKJob* __restrict__ jobs
     }
 }
 
-// Per block: sigma^2 onto the diagonal of B, 1 on its padding diagonal, and
-// the residual tile (row 0: a~_n - c_n - m0 sum_i g_ni; rows 1..63: 0).
+// Per block: sigma^2 onto the diagonal of B, 1 on its padding diagonal;
+// with mean parameters the H tile (rows 0..4: h_n = J^T g_n); the residual
+// tile (row 0: a~_n minus its prior mean, c_n + m0 sum_i g_ni, or c'_n +
+// h_n . phihat with mean parameters; rows 1..63: 0).
 __global__ __launch_bounds__(256) void k_block_prep(const PitcBlockDev* __restrict__ blk, const int32_t* __restrict__ stars,
-                                                    const int64_t* __restrict__ sptr, const double* __restrict__ g,
-                                                    const double* __restrict__ c, const double* __restrict__ A,
-                                                    const double* __restrict__ sigma, double m0, double* __restrict__ ws) {
+                                                    const int64_t* __restrict__ sptr,
+                                                    const double* __restrict__ g, const double* __restrict__ c,
+                                                    const double* __restrict__ A, const double* __restrict__ sigma,
+                                                    PitcMeanDev mean, double* __restrict__ ws) {
     const PitcBlockDev B = blk[blockIdx.x];
     double* F = ws + B.front;
     const int64_t m = B.m;
-    double* rt = F + B.npad + B.rpad;   // residual tile, rows npad + rpad .. + 63
+    double* rt = F + B.rrow;                            // residual tile
+    double* ht = B.xdim > B.rpad ? F + B.npad + B.rpad : nullptr;   // H tile
     for (int n = threadIdx.x; n < B.npad; n += blockDim.x) {
         double* d = F + n + (int64_t)n * m;
         if (n < B.nstars) {
             const int32_t s = stars[B.star0 + n];
             double sg = 0.0;
-            for (int64_t q = sptr[s]; q < sptr[s + 1]; q++) sg += g[q];
+            if (mean.mhat) {
+                for (int j = 0; j < NTHETA; j++) sg += mean.h[(int64_t)NTHETA * s + j] * mean.phihat[j];
+            } else {
+                for (int64_t q = sptr[s]; q < sptr[s + 1]; q++) sg += g[q];
+                sg *= mean.m0;
+            }
             *d += sigma[s] * sigma[s];
-            rt[(int64_t)n * m] = A[s] - c[s] - m0 * sg;
+            rt[(int64_t)n * m] = A[s] - c[s] - sg;
+            if (ht)
+                for (int r = 0; r < TS; r++) ht[r + (int64_t)n * m] = r < NTHETA ? mean.h[(int64_t)NTHETA * s + r] : 0.0;
         } else {
             *d = 1.0;
             rt[(int64_t)n * m] = 0.0;
+            if (ht)
+                for (int r = 0; r < TS; r++) ht[r + (int64_t)n * m] = 0.0;
         }
         for (int r = 1; r < TS; r++) rt[r + (int64_t)n * m] = 0.0;
     }
@@ -104,33 +117,38 @@ __global__ void k_sum_blocks(const double* __restrict__ lam, int nblk, int64_t E
     }
 }
 
-// Sites (damped) and the two R x R fronts: Fq = [I + S_sites; I; h_sites^T],
-// Fe = [I + S_new; h_new^T] (lower triangles; upper tiles zero).
+// Sites (damped) and the two fronts over x (xdim): Fq = [P0 + S_sites; I;
+// h_sites^T], Fe = [P0 + S_new; h_new^T] (lower triangles; upper tiles
+// zero), P0 the prior precision of x.  S_* are E1 x E1 with E1 = xdim + 64:
+// the x block, then the residual row xdim.
 __global__ void k_sites_fronts(const double* __restrict__ Snew, double* __restrict__ Ssites, double damp, int first,
-                               double* __restrict__ Fq, int64_t mq, double* __restrict__ Fe, int64_t me, int rpad) {
-    const int64_t e1 = rpad + TS;
+                               double* __restrict__ Fq, int64_t mq, double* __restrict__ Fe, int64_t me, int rpad,
+                               int xdim, PitcPriorDev prior) {
+    const int64_t e1 = xdim + TS;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1 * e1; e += (int64_t)gridDim.x * blockDim.x) {
         const double s = first ? damp * Snew[e] : (1.0 - damp) * Ssites[e] + damp * Snew[e];
         Ssites[e] = s;
         const int i = (int)(e % e1), j = (int)(e / e1);
-        if (j >= rpad) continue;
-        if (i < rpad) {
-            const double d = (i == j) ? 1.0 : 0.0;
+        if (j >= xdim) continue;
+        if (i < xdim) {
+            double d = 0.0;
+            if (i == j) d = (i >= rpad && i < rpad + prior.M) ? prior.s0inv[i - rpad] : 1.0;
             Fq[i + (int64_t)j * mq] = i >= j ? d + s : 0.0;
             Fe[i + (int64_t)j * me] = i >= j ? d + Snew[e] : 0.0;
-            Fq[rpad + i + (int64_t)j * mq] = d;
+            Fq[xdim + i + (int64_t)j * mq] = (i == j) ? 1.0 : 0.0;
         } else {
-            Fq[2 * rpad + (i - rpad) + (int64_t)j * mq] = (i == rpad) ? s : 0.0;
-            Fe[rpad + (i - rpad) + (int64_t)j * me] = (i == rpad) ? Snew[e] : 0.0;
+            Fq[2 * xdim + (i - xdim) + (int64_t)j * mq] = (i == xdim) ? s : 0.0;
+            Fe[xdim + (i - xdim) + (int64_t)j * me] = (i == xdim) ? Snew[e] : 0.0;
         }
     }
 }
 
 // ln p(a~) = -1/2 [S ln 2 pi + sum_k ln|B_k| + sum_k r_k^T B_k^{-1} r_k
-//            + ln|I + S_new| - |L_e^{-1} h_new|^2]; one block of 256
+//            + ln|S0| + ln|P0 + S_new| - |L_e^{-1} h_new|^2]; one block of 256
 __global__ __launch_bounds__(256) void k_lnz(const PitcBlockDev* __restrict__ blk, int nblk, const double* __restrict__ ws,
-                                             const double* __restrict__ Fe, int64_t me, int rpad,
-                                             const double* __restrict__ Snew, int64_t S, double* __restrict__ out) {
+                                             const double* __restrict__ Fe, int64_t me, int xdim,
+                                             const double* __restrict__ Snew, int64_t S, double ln_det_s0,
+                                             double* __restrict__ out) {
     __shared__ double part[256];
     double s = 0.0;
     for (int k = 0; k < nblk; k++) {
@@ -138,9 +156,9 @@ __global__ __launch_bounds__(256) void k_lnz(const PitcBlockDev* __restrict__ bl
         const double* F = ws + B.front;
         for (int n = threadIdx.x; n < B.nstars; n += blockDim.x) s += 2.0 * log(F[n + (int64_t)n * B.m]);
     }
-    for (int i = threadIdx.x; i < rpad; i += blockDim.x) {
+    for (int i = threadIdx.x; i < xdim; i += blockDim.x) {
         s += 2.0 * log(Fe[i + (int64_t)i * me]);
-        const double v = Fe[rpad + (int64_t)i * me];
+        const double v = Fe[xdim + (int64_t)i * me];
         s -= v * v;
     }
     part[threadIdx.x] = s;
@@ -150,22 +168,24 @@ __global__ __launch_bounds__(256) void k_lnz(const PitcBlockDev* __restrict__ bl
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int64_t e1 = rpad + TS;
-        const double rr = Snew[rpad + (int64_t)rpad * e1];
-        out[0] = -0.5 * ((double)S * 1.8378770664093453 + part[0] + rr);
+        const int64_t e1 = xdim + TS;
+        const double rr = Snew[xdim + (int64_t)xdim * e1];
+        out[0] = -0.5 * ((double)S * 1.8378770664093453 + part[0] + rr + ln_det_s0);
     }
 }
 
 // PIC predictive at the nodes of each block, one thread per node:
-//   mean = m0 + a^T mu~ + e^T w_r
+//   mean = m(x_p) + a^T mu~ + e^T w_r
 //   var  = k0 - |k~|^2 - |e|^2 + a^T Sigma~ a
-// with k~ = X_C K_u* (row of Kt), e = L_B^{-1} d (row of the front's D part),
-// a = k~ - W_Z^T e (row of At), Sigma~ a (row of SAt).
+// with k~ = L_C^{-1} K(u, p) (the first rpad entries of Kt's row; with mean
+// parameters its next entries are J_p), e = L_B^{-1} d (row of the front's
+// D part), a = Kt row - W_x^T e (row of At), Sigma~ a (row of SAt); x-space
+// vectors have xdim entries.
 __global__ __launch_bounds__(256) void k_predict(const PitcBlockDev* __restrict__ blk, const int64_t* __restrict__ base,
                                                  int nblk, int64_t ntasks, const double* __restrict__ ws,
                                                  const int32_t* __restrict__ pnodes, const double* __restrict__ mu_t,
-                                                 double m0, double k0, int rpad, double* __restrict__ mean,
-                                                 double* __restrict__ var) {
+                                                 PitcMeanDev mean, double k0, double* __restrict__ out_mean,
+                                                 double* __restrict__ out_var) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntasks) return;
     const int k = (int)find_job(base, nblk, t);
@@ -173,31 +193,71 @@ __global__ __launch_bounds__(256) void k_predict(const PitcBlockDev* __restrict_
     const int p = (int)(t - base[k]);
     if (p >= B.npred) return;
     const double* F = ws + B.front;
-    const double* Erow = F + B.npad + B.rpad + TS + p;   // e_n at Erow[n m]
-    const double* wr = F + B.npad + B.rpad;             // w_r,n at wr[n m]
+    const double* Erow = F + B.drow + p;   // e_n at Erow[n m]
+    const double* wr = F + B.rrow;         // w_r,n at wr[n m]
     const int64_t ldp = B.ppad;
     const double* kt = ws + B.kt + p;
     const double* at = ws + B.at + p;
     const double* sat = ws + B.sat + p;
-    double mn = m0, v = k0;
+    const int32_t node = pnodes[B.pred0 + p];
+    double mn = mean.mhat ? mean.mhat[node] : mean.m0, v = k0;
     for (int n = 0; n < B.nstars; n++) {
         const double e = Erow[(int64_t)n * B.m];
         mn += e * wr[(int64_t)n * B.m];
         v -= e * e;
     }
-    for (int r = 0; r < rpad; r++) {
-        const double a = at[r * ldp], kk = kt[r * ldp];
+    for (int r = 0; r < B.xdim; r++) {
+        const double a = at[r * ldp];
         mn += a * mu_t[r];
-        v += a * sat[r * ldp] - kk * kk;
+        v += a * sat[r * ldp];
+        if (r < B.rpad) {
+            const double kk = kt[r * ldp];
+            v -= kk * kk;
+        }
     }
-    const int32_t node = pnodes[B.pred0 + p];
-    mean[node] = mn;
-    var[node] = v;
+    out_mean[node] = mn;
+    out_var[node] = v;
 }
 
-__global__ void k_add_const(double* p, int64_t n, double c) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] += c;
+// Kt columns rpad .. rpad + 4: J at the block's prediction nodes
+__global__ void k_kt_j(const PitcBlockDev* __restrict__ blk, const int64_t* __restrict__ base, int nblk, int64_t ntasks,
+                       const int32_t* __restrict__ pnodes, PitcMeanDev mean, double* __restrict__ ws) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntasks) return;
+    const int k = (int)find_job(base, nblk, t);
+    const PitcBlockDev B = blk[k];
+    const int p = (int)(t - base[k]);
+    if (p >= B.npred) return;
+    const int32_t node = pnodes[B.pred0 + p];
+    double* kt = ws + B.kt + p;
+    for (int j = 0; j < NTHETA; j++) kt[(int64_t)(B.rpad + j) * B.ppad] = mean.J[node + (int64_t)j * mean.N];
+}
+
+// T = [L_C | J_u] (rpad x xdim, ld rpad): the C front's lower triangle (its
+// strictly upper tiles are zero and its diagonal tiles zero above the
+// diagonal), then J at the inducing nodes
+__global__ void k_build_t(const double* __restrict__ Cf, int64_t mC, const int32_t* __restrict__ unodes, int R, int rpad,
+                          int xdim, PitcMeanDev mean, double* __restrict__ T) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)rpad * xdim;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % rpad), j = (int)(e / rpad);
+        double v = 0.0;
+        if (j < rpad) v = Cf[i + (int64_t)j * mC];
+        else if (j - rpad < NTHETA && i < R) v = mean.J[unodes[i] + (int64_t)(j - rpad) * mean.N];
+        T[e] = v;
+    }
+}
+
+__global__ void k_add_mean(double* out, const int32_t* __restrict__ unodes, int R, PitcMeanDev mean) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x)
+        out[r] += mean.mhat ? mean.mhat[unodes[r]] : mean.m0;
+}
+
+__global__ void k_theta_out(const double* __restrict__ mu_t, const double* __restrict__ sig_t, int xdim, int rpad, int M,
+                            Phi5 phihat, double* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t < M) out[t] = phihat.v[t] + mu_t[rpad + t];
+    if (t < M * M) out[M + t] = sig_t[(rpad + t / M) + (int64_t)(rpad + t % M) * xdim];
 }
 
 unsigned grid_for(int64_t n) {
@@ -214,10 +274,10 @@ void launch_pitc_kfill(hipStream_t st, const PitcKJob* jobs, const int64_t* base
     if (ntiles > 0) hipLaunchKernelGGL(k_kfill, dim3((unsigned)ntiles), dim3(256), 0, st, jobs, base, njobs, ntiles, cov, ids, ws);
 }
 void launch_pitc_block_prep(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const int64_t* sptr,
-                            const double* g, const double* c, const double* A, const double* sigma, double m0,
+                            const double* g, const double* c, const double* A, const double* sigma, PitcMeanDev mean,
                             double* ws) {
     if (nblk > 0)
-        hipLaunchKernelGGL(k_block_prep, dim3(nblk), dim3(256), 0, st, blk, stars, sptr, g, c, A, sigma, m0, ws);
+        hipLaunchKernelGGL(k_block_prep, dim3(nblk), dim3(256), 0, st, blk, stars, sptr, g, c, A, sigma, mean, ws);
 }
 void launch_pitc_cfront_prep(hipStream_t st, double* F, int64_t m, int R, int rpad) {
     hipLaunchKernelGGL(k_cfront_prep, dim3(grid_for((int64_t)rpad * rpad)), dim3(256), 0, st, F, m, R, rpad);
@@ -226,24 +286,39 @@ void launch_pitc_sum_blocks(hipStream_t st, const double* lam, int nblk, int64_t
     hipLaunchKernelGGL(k_sum_blocks, dim3(grid_for(E)), dim3(256), 0, st, lam, nblk, E, out);
 }
 void launch_pitc_sites_fronts(hipStream_t st, const double* Snew, double* Ssites, double damp, bool first, double* Fq,
-                              int64_t mq, double* Fe, int64_t me, int rpad) {
-    const int64_t e1 = rpad + TS;
+                              int64_t mq, double* Fe, int64_t me, int rpad, int xdim, PitcPriorDev prior) {
+    const int64_t e1 = xdim + TS;
     hipLaunchKernelGGL(k_sites_fronts, dim3(grid_for(e1 * e1)), dim3(256), 0, st, Snew, Ssites, damp, first ? 1 : 0, Fq,
-                       mq, Fe, me, rpad);
+                       mq, Fe, me, rpad, xdim, prior);
 }
 void launch_pitc_lnz(hipStream_t st, const PitcBlockDev* blk, int nblk, const double* ws, const double* Fe, int64_t me,
-                     int rpad, const double* Snew, int64_t S, double* out) {
-    hipLaunchKernelGGL(k_lnz, dim3(1), dim3(256), 0, st, blk, nblk, ws, Fe, me, rpad, Snew, S, out);
+                     int xdim, const double* Snew, int64_t S, double ln_det_s0, double* out) {
+    hipLaunchKernelGGL(k_lnz, dim3(1), dim3(256), 0, st, blk, nblk, ws, Fe, me, xdim, Snew, S, ln_det_s0, out);
 }
 void launch_pitc_predict(hipStream_t st, const PitcBlockDev* blk, const int64_t* base, int nblk, int64_t ntasks,
-                         const double* ws, const int32_t* pnodes, const double* mu_t, double m0, double k0, int rpad,
-                         double* mean, double* var) {
+                         const double* ws, const int32_t* pnodes, const double* mu_t, PitcMeanDev mean, double k0,
+                         double* out_mean, double* out_var) {
     if (ntasks > 0)
         hipLaunchKernelGGL(k_predict, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0, st, blk, base, nblk, ntasks,
-                           ws, pnodes, mu_t, m0, k0, rpad, mean, var);
+                           ws, pnodes, mu_t, mean, k0, out_mean, out_var);
 }
-void launch_pitc_add_const(hipStream_t st, double* p, int64_t n, double c) {
-    if (n > 0) hipLaunchKernelGGL(k_add_const, dim3(grid_for(n)), dim3(256), 0, st, p, n, c);
+void launch_pitc_kt_j(hipStream_t st, const PitcBlockDev* blk, const int64_t* base, int nblk, int64_t ntasks,
+                      const int32_t* pnodes, PitcMeanDev mean, double* ws) {
+    if (ntasks > 0)
+        hipLaunchKernelGGL(k_kt_j, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0, st, blk, base, nblk, ntasks,
+                           pnodes, mean, ws);
+}
+void launch_pitc_build_t(hipStream_t st, const double* Cf, int64_t mC, const int32_t* unodes, int R, int rpad, int xdim,
+                         PitcMeanDev mean, double* T) {
+    hipLaunchKernelGGL(k_build_t, dim3(grid_for((int64_t)rpad * xdim)), dim3(256), 0, st, Cf, mC, unodes, R, rpad, xdim,
+                       mean, T);
+}
+void launch_pitc_theta_out(hipStream_t st, const double* mu_t, const double* sig_t, int xdim, int rpad, int M,
+                           Phi5 phihat, double* out) {
+    hipLaunchKernelGGL(k_theta_out, dim3(1), dim3(64), 0, st, mu_t, sig_t, xdim, rpad, M, phihat, out);
+}
+void launch_pitc_add_mean(hipStream_t st, double* out, const int32_t* unodes, int R, PitcMeanDev mean) {
+    if (R > 0) hipLaunchKernelGGL(k_add_mean, dim3(grid_for(R)), dim3(256), 0, st, out, unodes, R, mean);
 }
 
 }  // namespace ep

@@ -94,7 +94,7 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
            "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info")
+           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta")
 MLP_NPARAM = 34065
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
@@ -125,6 +125,13 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
+    # torch ships its own HIP runtime; it must be loaded and initialised
+    # before this library's, or torch later finds no GPU in the process
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     L = ctypes.CDLL(p)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     cfgp = ctypes.POINTER(ep_config)
@@ -161,12 +168,13 @@ def load(path: str | None = None):
     L.ep_pitc_inducing.argtypes = [vp, vp, vp]
     L.ep_pitc_predict.argtypes = [vp, vp, vp]
     L.ep_pitc_info.argtypes = [vp, ctypes.POINTER(ep_pitc_stats)]
+    L.ep_pitc_theta.argtypes = [vp, vp, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
                  "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info"):
+                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -450,6 +458,12 @@ class EP:
         """Mean (R) and covariance (R x R) of q(u)."""
         (m, pm), (c, pc) = self._out(self.n_inducing), self._out((self.n_inducing, self.n_inducing))
         _check(self.L, self.L.ep_pitc_inducing(self.ctx, pm, pc), self.ctx)
+        return m, c
+
+    def pitc_theta(self):
+        """Mean (5) and covariance (5 x 5) of phi = ln theta under q(u, Theta)."""
+        (m, pm), (c, pc) = self._out(N_THETA), self._out((N_THETA, N_THETA))
+        _check(self.L, self.L.ep_pitc_theta(self.ctx, pm, pc), self.ctx)
         return m, c
 
     def pitc_info(self) -> dict:

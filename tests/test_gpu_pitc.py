@@ -191,3 +191,82 @@ def test_pitc_full_size_properties():
     print(f"lnZ {lz1:.3f}; predictive var in [{pv.min():.3e}, {pv.max():.3e}]", flush=True)
     assert np.all(np.isfinite(pm)) and np.all(pv > 0) and np.all(pv <= k0 * (1 + 1e-9))
     g.close()
+
+
+# --- the mean parameters in the sites: q(u, Theta) ---------------------------
+
+THETA_PRIOR = (1500.0, 150.0, 7.5e-4, 600.0, 0.1)
+THETA_TRUE = (1000.0, 200.0, 1.2e-3, 500.0, 0.2)
+
+
+def _case_theta(n, L, stars, n_lon, n_lat, R, seed):
+    from oracle import epo, meanfn
+    w = Workload("pitct", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law="uniform", d_max_pc=L,
+                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood="gauss_linear", seed_id=seed)
+    cfg = w.ep_fields()
+    cfg.update(sun_radius_pc=8000.0, bump_width_pc=200.0, theta_prior=THETA_PRIOR)
+    raw = draw(w)
+    sl = epo.Sightlines(cfg, raw["xyz"])
+    vec = epo.Vecchia(cfg)
+    pos = vec.grid.xyz()
+    m_true, _ = meanfn.mean_and_jacobian(cfg, pos, np.log(THETA_TRUE))
+    f_true = m_true + vec.draw(0.0, raw["xi"])
+    mu0, _ = meanfn.hyperprior(cfg)
+    mhat, _ = meanfn.mean_and_jacobian(cfg, pos, mu0)
+    gval, _, c = sl.linearise(mhat)
+    a = c + sl.G_dense(gval) @ f_true + raw["sigma"] * raw["eps"]
+    blocks = sky_cells(w, raw["xyz"], n_lon, n_lat)
+    used, blocks = np.unique(blocks, return_inverse=True)
+    lut = np.array([int(np.argmin(np.abs(used - cc))) for cc in range(n_lon * n_lat)])
+    nb = lut[sky_cells(w, node_positions(w), n_lon, n_lat)].astype(np.int32)
+    u = np.sort(np.random.default_rng(seed).choice(w.N, size=R, replace=False)).astype(np.int32)
+    return w, cfg, raw, a, sl, blocks.astype(np.int32), u, nb
+
+
+@pytest.mark.parametrize("kw", [dict(n=8, L=1000.0, stars=150, n_lon=3, n_lat=2, R=40, seed=51),
+                                dict(n=9, L=1200.0, stars=400, n_lon=3, n_lat=1, R=100, seed=53)],
+                         ids=["n8-6blk", "n9-3blk-3tiles"])
+@pytest.mark.parametrize("damping", [(1.0,), (0.5, 0.8)], ids=["undamped", "damped"])
+def test_pitc_theta_matches_oracle(kw, damping):
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, a, sl, blocks, u, nb = _case_theta(**kw)
+    print(f"case n={kw['n']} stars={kw['stars']} blocks={blocks.max() + 1} R={len(u)} damping={damping}", flush=True)
+    ora = pitc.DensePITCTheta(cfg, raw["xyz"], a, raw["sigma"], blocks, u, nb, sightlines=sl)
+    g = E.EP(dict(cfg, leaf_size=48, mean_fn="disc_bump"), raw["xyz"], a, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    for d in damping:
+        ora.sweep(d)
+        lz = g.pitc_sweep(d)
+    om, oV = ora.posterior_u()
+    gm, gV = g.pitc_inducing()
+    tm, tV = ora.theta_posterior()
+    gtm, gtV = g.pitc_theta()
+    olz = ora.log_evidence()
+    print(f"q(u): mean {relerr(gm, om):.2e} cov {_rel(gV, oV):.2e}; phi: mean {relerr(gtm, tm):.2e} "
+          f"cov {_rel(gtV, tV):.2e}; lnZ {lz:.6f} vs {olz:.6f}", flush=True)
+    assert relerr(gm, om) < 1e-8 and _rel(gV, oV) < 1e-8
+    assert relerr(gtm, tm) < 1e-8 and _rel(gtV, tV) < 1e-8
+    assert abs(lz - olz) < 1e-8 * abs(olz)
+    pm, pv = g.pitc_predict()
+    qm, qv = ora.predict()
+    print(f"predictive: mean {relerr(pm, qm):.2e} var {relerr(pv, qv):.2e}", flush=True)
+    assert relerr(pm, qm) < 1e-8 and relerr(pv, qv) < 1e-8
+    g.close()
+
+
+def test_pitc_theta_state_errors():
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, a, sl, blocks, u, nb = _case_theta(n=8, L=1000.0, stars=100, n_lon=2, n_lat=1, R=20, seed=55)
+    g = E.EP(dict(cfg, leaf_size=48, mean_fn="disc_bump"), raw["xyz"], a, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_theta()                                  # before a sweep
+    assert ei.value.code == -5
+    g.close()
+    g = E.EP(dict(cfg, leaf_size=48), raw["xyz"], a, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    g.pitc_sweep(1.0)
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_theta()                                  # constant mean
+    assert ei.value.code == -5
+    g.close()
