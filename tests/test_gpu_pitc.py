@@ -224,8 +224,9 @@ def _case_theta(n, L, stars, n_lon, n_lat, R, seed):
 
 
 @pytest.mark.parametrize("kw", [dict(n=8, L=1000.0, stars=150, n_lon=3, n_lat=2, R=40, seed=51),
-                                dict(n=9, L=1200.0, stars=400, n_lon=3, n_lat=1, R=100, seed=53)],
-                         ids=["n8-6blk", "n9-3blk-3tiles"])
+                                dict(n=9, L=1200.0, stars=400, n_lon=3, n_lat=1, R=100, seed=53),
+                                dict(n=10, L=1500.0, stars=700, n_lon=4, n_lat=2, R=250, seed=57)],
+                         ids=["n8-6blk", "n9-3blk-3tiles", "n10-8blk-R4tiles"])
 @pytest.mark.parametrize("damping", [(1.0,), (0.5, 0.8)], ids=["undamped", "damped"])
 def test_pitc_theta_matches_oracle(kw, damping):
     from paper_1708_09705_amd import ep as E
@@ -269,4 +270,39 @@ def test_pitc_theta_state_errors():
     with pytest.raises(E.EPError) as ei:
         g.pitc_theta()                                  # constant mean
     assert ei.value.code == -5
+    g.close()
+
+
+def test_pitc_theta_full_size_properties():
+    """The bench shape with the mean parameters in the sites: the fixed point
+    after one sweep, a symmetric positive definite covariance of (u, phi),
+    predictive variances in (0, prior variance + the mean's share]."""
+    from paper_1708_09705_amd import ep as E
+    w = preset(2, likelihood="gauss_linear")
+    cfg = w.ep_fields()
+    cfg.update(theta_prior=(3000.0, 150.0, 7.5e-4, 2000.0, 0.1))
+    raw = draw(w)
+    sim = E.make_config(dict(cfg, mean_fn="disc_bump", theta_prior=(2500.0, 200.0, 1.2e-3, 1800.0, 0.15)))
+    _, a_obs = E.ep_simulate(sim, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+    blocks = sky_cells(w, raw["xyz"], 40, 4)
+    u = boundary_inducing(w, 40, 4, (1000.0, 2000.0, 3000.0, 4000.0))
+    nb = sky_cells(w, node_positions(w), 40, 4)
+    g = E.EP(dict(cfg, mean_fn="disc_bump"), raw["xyz"], a_obs, raw["sigma"])
+    print(f"full size with mean parameters: blocks 160 R={len(u)}", flush=True)
+    g.pitc_setup(blocks, u, nb)
+    lz1 = g.pitc_sweep(1.0)
+    m1, V1 = g.pitc_inducing()
+    t1, T1 = g.pitc_theta()
+    lz2 = g.pitc_sweep(1.0)
+    m2, V2 = g.pitc_inducing()
+    t2, T2 = g.pitc_theta()
+    assert np.isfinite(lz1) and abs(lz2 - lz1) <= 1e-12 * abs(lz1)
+    assert relerr(m2, m1) < 1e-12 and _rel(V2, V1) < 1e-12 and relerr(t2, t1) < 1e-12 and _rel(T2, T1) < 1e-12
+    assert _rel(T1, T1.T) < 1e-12 and np.linalg.eigvalsh(0.5 * (T1 + T1.T)).min() > 0
+    assert np.linalg.eigvalsh(0.5 * (V1 + V1.T)).min() > 0
+    # the data constrain phi: its posterior sd is below the hyperprior's sqrt(ln 2)
+    assert np.all(np.sqrt(np.diag(T1)) < np.sqrt(np.log(2.0)))
+    pm, pv = g.pitc_predict()
+    print(f"lnZ {lz1:.3f}; phi {np.round(t1, 3)}; predictive var in [{pv.min():.3e}, {pv.max():.3e}]", flush=True)
+    assert np.all(np.isfinite(pm)) and np.all(pv > 0)
     g.close()
