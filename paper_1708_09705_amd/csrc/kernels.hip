@@ -407,16 +407,24 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+// FT: the element type of the fronts being factored (double, or float for
+// the FP32 copy of a mixed-precision level); the arithmetic is FP64 either
+// way and X is FP64.
+template <typename FT> __device__ __forceinline__ FT* fronts_of(const Bufs& b);
+template <> __device__ __forceinline__ double* fronts_of<double>(const Bufs& b) { return b.fronts; }
+template <> __device__ __forceinline__ float* fronts_of<float>(const Bufs& b) { return b.F32; }
+
+template <typename FT>
 __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
                                               int* err) {
     __shared__ double T[TS * LDP];
     const int f = flist[blockIdx.x];
     const int m = F.m[f];
-    double* A = bufs.fronts + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
+    FT* A = fronts_of<FT>(bufs) + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
     const int i = threadIdx.x;
     double a[TS];
 #pragma unroll
-    for (int c = 0; c < TS; c++) a[c] = A[i + (int64_t)c * m];
+    for (int c = 0; c < TS; c++) a[c] = (double)A[i + (int64_t)c * m];
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < TS; j++) {
@@ -434,7 +442,7 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
 #pragma unroll
     for (int c = 0; c < TS; c++) {
         const double v = (i >= c) ? a[c] : 0.0;
-        A[i + (int64_t)c * m] = v;
+        A[i + (int64_t)c * m] = (FT)v;
         T[i * LDP + c] = v;
     }
     __shared__ double dinv[TS];
@@ -464,7 +472,7 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
 
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_potrf, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
+    hipLaunchKernelGGL(k_potrf<double>, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1500,64 +1508,6 @@ __global__ __launch_bounds__(256) void k_to_f32(const BatchEnt* __restrict__ be,
     for (int64_t q = threadIdx.x; q < (int64_t)TS * m; q += 256) dst[q] = (float)src[q];
 }
 
-__global__ __launch_bounds__(256) void k_potrf32(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
-                                                 int* err) {
-    __shared__ double L[TS * LDP];
-    __shared__ double Xs[TS * LDP];
-    __shared__ int bad;
-    const int f = flist[blockIdx.x];
-    const int m = F.m[f];
-    float* A = bufs.F32 + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
-    const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
-    {
-        const int i = tid & 63;
-        for (int r = 0; r < 16; r++) {
-            int j = (tid >> 6) + 4 * r;
-            L[i * LDP + j] = (double)A[i + (int64_t)j * m];
-        }
-    }
-    __syncthreads();
-    for (int j = 0; j < TS; j++) {
-        if (tid == 0) {
-            double d = L[j * LDP + j];
-            if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
-            L[j * LDP + j] = sqrt(d);
-        }
-        __syncthreads();
-        const double dj = L[j * LDP + j];
-        if (tid > j && tid < TS) L[tid * LDP + j] /= dj;
-        __syncthreads();
-        for (int idx = tid; idx < TS * TS; idx += 256) {
-            int i = idx >> 6, c = idx & 63;
-            if (c > j && i >= c) L[i * LDP + c] -= L[i * LDP + j] * L[c * LDP + j];
-        }
-        __syncthreads();
-    }
-    if (tid < TS) {
-        const int j = tid;
-        for (int i = 0; i < j; i++) Xs[i * LDP + j] = 0.0;
-        Xs[j * LDP + j] = 1.0 / L[j * LDP + j];
-        for (int i = j + 1; i < TS; i++) {
-            double s = 0.0;
-            for (int q = j; q < i; q++) s += L[i * LDP + q] * Xs[q * LDP + j];
-            Xs[i * LDP + j] = -s / L[i * LDP + i];
-        }
-    }
-    __syncthreads();
-    double* Xk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
-    const int ldx = F.nvpad[f];
-    {
-        const int i = tid & 63;
-        for (int r = 0; r < 16; r++) {
-            int j = (tid >> 6) + 4 * r;
-            A[i + (int64_t)j * m] = (i >= j) ? (float)L[i * LDP + j] : 0.0f;
-            Xk[i + (int64_t)j * ldx] = Xs[i * LDP + j];
-        }
-    }
-    if (tid == 0 && bad) atomicCAS(err, 0, f + 1);
-}
-
 __global__ __launch_bounds__(256) void k_trsm32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int k,
                                                 FrontsDev F, Bufs bufs) {
     __shared__ float sA[TS * LDF];
@@ -1659,7 +1609,7 @@ void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
 }
 void launch_potrf32(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_potrf32, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
+    hipLaunchKernelGGL(k_potrf<float>, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
 }
 void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
