@@ -49,8 +49,9 @@ struct TaskRange {
 };
 struct LevelPlan {
     std::vector<FList> potrf;   // per pivot step
-    std::vector<Launch> trsm, inner, trail;   // trail[k]: panels ending at step k (FP32 levels)
-    // FP64 levels, left-looking by panel, as 128 x 128 GEMM tasks:
+    std::vector<Launch> trsm, inner;
+    std::vector<TaskRange> trail32;   // FP32 levels: after a panel ending at step k, its trailing update (FP32 tasks)
+    // FP64 levels, left-looking by panel, as 256 x 128 GEMM tasks:
     // panelT[k]: before step k (a panel start), the panel's columns take the
     //            updates of every earlier panel;
     // finalT[k]: after step k (a front's last pivot step), the update block
@@ -275,7 +276,7 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         for (int k = 0; k < Pmax; k++) {
             FList fl;
             fl.off = (int64_t)flists.size();
-            std::vector<std::pair<int, int64_t>> tr, in, tl;
+            std::vector<std::pair<int, int64_t>> tr, in;
             const int g = k / PW;
             for (int f : lv[l]) {
                 const int Pf = P_of(f), M = M_of(f);
@@ -286,16 +287,12 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                 int64_t cnt = 0;
                 for (int j = k + 1; j < gend; j++) cnt += M - j;
                 in.emplace_back(f, cnt);
-                if (gend - 1 == k) {
-                    int64_t T = M - gend;
-                    tl.emplace_back(f, T * (T + 1) / 2);
-                }
             }
             fl.n = (int)((int64_t)flists.size() - fl.off);
             P.potrf.push_back(fl);
             P.trsm.push_back(mk_launch(tr));
             P.inner.push_back(mk_launch(in));
-            P.trail.push_back(mk_launch(tl));
+
             // left-looking updates as 256 x 128 block tasks (four row tiles x
             // two column tiles), C(i, j) -= sum over K of L(i, kk) L(j, kk)^T
             // for j <= i < M; blocks straddling the diagonal store only their
@@ -310,7 +307,7 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                     for (int j = j0; j < j1 && j <= i + 3; j += 2) c++;
                 return c;
             };
-            auto lower_tasks = [&](int f, int j0, int j1, int kk0, int kk1, int split) {
+            auto lower_tasks = [&](int f, int j0, int j1, int kk0, int kk1, int split, int buf = BUF_FRONTS) {
                 const Front& Fr = sym.fronts[f];
                 const int M = M_of(f);
                 const int64_t m = Fr.m;
@@ -324,10 +321,10 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                             GemmTask t{};
                             t.c = Fr.off + TS * i + TS * j * m;
                             t.ldc = (int32_t)m;
-                            t.flags = (split > 1 ? 2 : 0) | (1 << 4) | (BUF_FRONTS << 8) |
+                            t.flags = (split > 1 ? 2 : 0) | (1 << 4) | (buf << 8) |
                                       gt_shape(std::min(4, M - i), j + 1 < j1, true, i - j, false);
-                            t.s[0] = mkseg(BUF_FRONTS, Fr.off + TS * i + TS * a0 * m, TS * m, (int)m, false, true,
-                                           BUF_FRONTS, Fr.off + TS * j + TS * a0 * m, TS * m, (int)m, true, a1 - a0);
+                            t.s[0] = mkseg(buf, Fr.off + TS * i + TS * a0 * m, TS * m, (int)m, false, true, buf,
+                                           Fr.off + TS * j + TS * a0 * m, TS * m, (int)m, true, a1 - a0);
                             tasks.push_back(t);
                         }
             };
@@ -377,6 +374,20 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             ft.n = (int64_t)tasks.size() - ft.off;
             balance_range(tasks, ft);
             P.finalT.push_back(ft);
+            // FP32 levels, right-looking by panel: after the panel ending at
+            // step k, its trailing update as FP32 MFMA block tasks
+            TaskRange t32;
+            t32.off = (int64_t)tasks.size();
+            if (is_f32_level(ctx, l))
+                for (int f : lv[l]) {
+                    const int Pf = P_of(f), M = M_of(f);
+                    if (Pf <= k) continue;
+                    const int gend = std::min(PW * (k / PW + 1), Pf);
+                    if (gend - 1 == k && M > gend) lower_tasks(f, gend, M, PW * (k / PW), gend, 1, BUF_F32);
+                }
+            t32.n = (int64_t)tasks.size() - t32.off;
+            balance_range(tasks, t32);
+            P.trail32.push_back(t32);
         }
         std::vector<std::pair<int, int64_t>> ea, fx, fr;
         for (int f : lv[l]) {
@@ -994,10 +1005,10 @@ static void enqueue_factor(ep_ctx* ctx) {
                 kt_begin(ctx, s.ntasks);
                 launch_syrk_inner32(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
                 kt_end(ctx, s.ntasks, EP_KK_INNER);
-                const Launch& r = P.trail[k];
-                kt_begin(ctx, r.ntasks);
-                launch_syrk_trail32(st, ctx->d_batches + r.be_off, r.nbe, r.ntasks, (int)k / PW, ctx->F, b);
-                kt_end(ctx, r.ntasks, EP_KK_TRAIL);
+                const TaskRange& r = P.trail32[k];
+                kt_begin(ctx, r.n);
+                launch_gemm_tasks_f32(st, ctx->d_tasks + r.off, r.n, ctx->d_f32);
+                kt_end(ctx, r.n, EP_KK_TRAIL);
             }
             const Launch& e = P.extend;
             launch_extend_add32(st, ctx->d_batches + e.be_off, e.nbe, e.ntasks, ctx->F, b);

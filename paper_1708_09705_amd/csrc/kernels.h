@@ -84,6 +84,8 @@ void launch_scatter_set(hipStream_t st, double* base, const int64_t* dest, const
 void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int64_t n, double v);
 
 void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, bool a32);
+// the same layout in FP32 on the FP32 copy of the fronts (every offset into F32)
+void launch_gemm_tasks_f32(hipStream_t st, const GemmTask* t, int64_t n, float* F32);
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
@@ -206,7 +208,6 @@ void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
 void launch_potrf32(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 void launch_syrk_inner32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
-void launch_syrk_trail32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b);
 void launch_extend_add32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 // r = b - Q x in FP64 (Q = Vecchia prior precision + star sites), for refinement
 void launch_residual(hipStream_t st, int64_t N, const int64_t* rp, const int32_t* col, const double* val,

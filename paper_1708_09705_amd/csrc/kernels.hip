@@ -1547,29 +1547,6 @@ __global__ __launch_bounds__(256) void k_syrk_inner32(const BatchEnt* __restrict
     tile_store32(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
 }
 
-__global__ __launch_bounds__(256) void k_syrk_trail32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int g,
-                                                      FrontsDev F, Bufs bufs) {
-    __shared__ float sA[TS * LDF];
-    __shared__ float sB[TS * LDF];
-    const int64_t t = xcd_task(ntasks);
-    if (t >= ntasks) return;
-    const int e = (int)batch_find(be, nbe, t);
-    const int f = be[e].front;
-    const int m = F.m[f];
-    const int P = F.nvpad[f] / TS;
-    const int k0 = PW * g;
-    const int gend = min(k0 + PW, P);
-    int ii, jj;
-    tri_decode(t - be[e].base, ii, jj);
-    const int i = gend + ii, j = gend + jj;
-    float* base = bufs.F32 + F.off[f];
-    f4 acc[2][2];
-    acc32_zero(acc);
-    seg_run32(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0f,
-              base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, gend - k0);
-    tile_store32(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
-}
-
 // update block of the FP32 front added into the FP64 parent
 __global__ __launch_bounds__(256) void k_extend_add32(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
                                                       FrontsDev F, Bufs bufs) {
@@ -1618,10 +1595,6 @@ void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
 void launch_syrk_inner32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_syrk_inner32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b);
-}
-void launch_syrk_trail32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int g, FrontsDev F, Bufs b) {
-    if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_syrk_trail32, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, g, F, b);
 }
 void launch_extend_add32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
