@@ -269,10 +269,11 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
         LevelPlan& P = ctx->levels[l];
         int Pmax = 0;
         for (int f : lv[l]) Pmax = std::max(Pmax, P_of(f));
-        // Blocked right-looking partial Cholesky, panels of PW tiles:
-        //   step k: diagonal tile, column below it, update of the rest of
-        //   k's panel (K = 1); after a panel's last step, the trailing
-        //   update of every later column with K = panel width.
+        // Blocked partial Cholesky, panels of PW tiles:
+        //   step k: diagonal tile, column below it, then column k + 1 of the
+        //   panel takes the updates of the panel's pivots up to k (K = k + 1
+        //   - panel start); the columns of later panels take their updates
+        //   in GEMM tasks.
         for (int k = 0; k < Pmax; k++) {
             FList fl;
             fl.off = (int64_t)flists.size();
@@ -284,9 +285,7 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                 flists.push_back(f);
                 tr.emplace_back(f, (int64_t)(M - k - 1));
                 const int gend = std::min(PW * (g + 1), Pf);
-                int64_t cnt = 0;
-                for (int j = k + 1; j < gend; j++) cnt += M - j;
-                in.emplace_back(f, cnt);
+                in.emplace_back(f, k + 1 < gend ? (int64_t)(M - k - 1) : 0);
             }
             fl.n = (int)((int64_t)flists.size() - fl.off);
             P.potrf.push_back(fl);

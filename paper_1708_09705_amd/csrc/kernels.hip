@@ -498,7 +498,9 @@ __global__ __launch_bounds__(256) void k_trsm_step(const BatchEnt* __restrict__ 
     tile_store(acc, sA, Aik, m, 1);
 }
 
-// inner update at pivot step kk: columns j in (kk, end of kk's panel), rows i >= j
+// In-panel update at pivot step kk (left-looking): column j = kk + 1 of the
+// panel, rows i >= j, takes the updates of the panel's pivot columns
+// k0 .. kk (K = kk - k0 + 1 tiles), once, after the column solve of kk.
 __global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int kk,
                                                     FrontsDev F, Bufs bufs) {
     __shared__ double sA[TS * LDP];
@@ -507,16 +509,14 @@ __global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__
     if (t >= ntasks) return;
     const int e = (int)batch_find(be, nbe, t);
     const int f = be[e].front;
-    const int m = F.m[f], M = m / TS;
-    int j = kk + 1;
-    int64_t r = t - be[e].base;
-    while (r >= M - j) { r -= M - j; j++; }
-    const int i = j + (int)r;
+    const int m = F.m[f];
+    const int j = kk + 1, i = j + (int)(t - be[e].base);
+    const int k0 = PW * (kk / PW);
     double* base = bufs.fronts + F.off[f];
     d4 acc[2][2];
     acc_zero(acc);
-    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * kk * m, 0, m, false, -1.0,
-            base + (int64_t)TS * j + (int64_t)TS * kk * m, 0, m, true, 1);
+    seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0,
+            base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, kk - k0 + 1);
     tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
 }
 
@@ -1534,16 +1534,14 @@ __global__ __launch_bounds__(256) void k_syrk_inner32(const BatchEnt* __restrict
     if (t >= ntasks) return;
     const int e = (int)batch_find(be, nbe, t);
     const int f = be[e].front;
-    const int m = F.m[f], M = m / TS;
-    int j = kk + 1;
-    int64_t r = t - be[e].base;
-    while (r >= M - j) { r -= M - j; j++; }
-    const int i = j + (int)r;
+    const int m = F.m[f];
+    const int j = kk + 1, i = j + (int)(t - be[e].base);
+    const int k0 = PW * (kk / PW);
     float* base = bufs.F32 + F.off[f];
     f4 acc[2][2];
     acc32_zero(acc);
-    seg_run32(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * kk * m, 0, m, false, -1.0f,
-              base + (int64_t)TS * j + (int64_t)TS * kk * m, 0, m, true, 1);
+    seg_run32(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0f,
+              base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, kk - k0 + 1);
     tile_store32(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
 }
 
