@@ -371,7 +371,11 @@ def main():
             "surrogate_fallbacks": int(stats32[-1]["surrogate_fallbacks"]),
             "rel_err_vs_fp64": {
                 "posterior_mean": float(np.max(np.abs(mean32 - mean64) / np.abs(mean64))),
-                "marginal_var": float(np.max(np.abs(var32 - var64) / np.abs(var64)))},
+                "marginal_var": float(np.max(np.abs(var32 - var64) / np.abs(var64))),
+                "kind": "max over nodes of |x - x_fp64| / |x_fp64|"},
+            "rms_rel_err_vs_fp64": {
+                "posterior_mean": float(np.sqrt(np.mean(((mean32 - mean64) / mean64) ** 2))),
+                "marginal_var": float(np.sqrt(np.mean(((var32 - var64) / var64) ** 2)))},
             "note": "same warm-up and step count as the FP64 run; errors after the same sweeps",
         }
 
