@@ -192,3 +192,123 @@ def test_multi_star_iterates_match_reduced_ep():
     # the stars interact: the reduced prior is far from diagonal
     off = S - np.diag(np.diag(S))
     assert np.max(np.abs(off)) > 0.05 * np.max(np.diag(S))
+
+
+def _lnA_plain(cfg, xyz, f):
+    """ln A_n and its gradient by a plain numpy forward model written here:
+    T = max(1, ceil(d / step)) equal steps from the observer, trapezoid
+    weights, trilinear interpolation with cell clamp(floor(s / h), 0, n - 2)."""
+    n, L = int(cfg["n"]), float(cfg["box_pc"])
+    h = L / (n - 1)
+    o = np.asarray(cfg["observer_pc"], dtype=np.float64)
+    lnA = np.zeros(len(xyz))
+    grad = np.zeros((len(xyz), n ** 3))
+    for s, x in enumerate(xyz):
+        d = float(np.linalg.norm(x - o))
+        T = max(1, math.ceil(d / cfg["los_step_pc"]))
+        t = np.arange(T + 1)
+        w = np.full(T + 1, d / T)
+        w[0] *= 0.5
+        w[-1] *= 0.5
+        pts = o[None, :] + (t[:, None] / T) * (x - o)[None, :]
+        u = pts / h
+        cell = np.clip(np.floor(u), 0, n - 2).astype(int)
+        fr = u - cell
+        F = np.zeros(T + 1)
+        corners = []
+        for di in (0, 1):
+            for dj in (0, 1):
+                for dk in (0, 1):
+                    wt = ((fr[:, 0] if di else 1 - fr[:, 0]) * (fr[:, 1] if dj else 1 - fr[:, 1])
+                          * (fr[:, 2] if dk else 1 - fr[:, 2]))
+                    node = (cell[:, 0] + di) + n * ((cell[:, 1] + dj) + n * (cell[:, 2] + dk))
+                    F += wt * f[node]
+                    corners.append((node, wt))
+        e = w * np.exp(F)
+        A = e.sum()
+        lnA[s] = math.log(A)
+        for node, wt in corners:
+            np.add.at(grad[s], node, e * wt / A)
+    return lnA, grad
+
+
+def test_relinearised_fixed_point():
+    """With the sightlines re-linearised at the posterior mean every sweep
+    (the linearisation of the log-extinction likelihood in a_n about the
+    current field), iterate damped EP to its fixed point and check what the
+    fixed point must satisfy:
+      * the linearisation point equals the posterior mean it produces;
+      * posterior() linearises at the current point: Q and b rebuilt from a
+        plain numpy forward model and its gradient at fhat give the same mean
+        and covariance;
+      * the moment-matching invariant (App. A.2) holds at that point;
+      * the fixed point is not the frozen-projection one (so a stale
+        linearisation would fail the checks above)."""
+    w, cfg = _small(n=7, L=420.0, stars=30, relinearize=True, damping=0.5)
+    raw = draw(w)
+    f_true, A_obs, sl = epo.simulate(cfg, raw)
+    sig = raw["sigma"]
+    ep = epo.DenseEP(cfg, raw["xyz"], A_obs, sig, sightlines=sl)
+    assert ep.relin
+    m0b = ep.Q0 @ np.full(sl.grid.N, cfg["prior_mean"])
+    # the iterates: each sweep moves the point to the mean of the posterior
+    # built, with the sites it started from, at the point it started from
+    for _ in range(3):
+        lnA, Gp = _lnA_plain(cfg, raw["xyz"], ep.fhat)
+        Q = ep.Q0 + Gp.T @ (ep.tau[:, None] * Gp)
+        mu_next = np.linalg.solve(Q, m0b + Gp.T @ (ep.nu - ep.tau * (lnA - Gp @ ep.fhat)))
+        ep.sweep()
+        assert np.allclose(ep.fhat, mu_next, rtol=1e-11, atol=1e-11)
+    for it in range(400):
+        st = ep.sweep()
+        if st["max_dtau"] < 1e-10 and st["max_dmu"] < 1e-10:
+            break
+    assert st["max_dtau"] < 1e-10 and st["max_dmu"] < 1e-10, (it, st["max_dtau"], st["max_dmu"])
+    mu, Sig, G, c = ep.posterior()
+    # (1) fhat = mu
+    assert np.max(np.abs(mu - ep.fhat)) < 1e-10
+    # (2) brute-force re-linearisation at the current fhat
+    lnA, Gp = _lnA_plain(cfg, raw["xyz"], ep.fhat)
+    cp = lnA - Gp @ ep.fhat
+    assert np.allclose(G, Gp, rtol=0, atol=1e-12)
+    Q = ep.Q0 + Gp.T @ (ep.tau[:, None] * Gp)
+    b = ep.Q0 @ np.full(sl.grid.N, cfg["prior_mean"]) + Gp.T @ (ep.nu - ep.tau * cp)
+    Sig_p = np.linalg.inv(Q)
+    assert np.allclose(mu, np.linalg.solve(Q, b), rtol=1e-11, atol=1e-11)
+    assert np.allclose(Sig, Sig_p, rtol=1e-10, atol=1e-13)
+    # (3) moment matching at the fixed point
+    qm = cp + Gp @ mu
+    qv = np.einsum("ij,jk,ik->i", Gp, Sig_p, Gp)
+    tau_c = 1 / qv - ep.tau
+    nu_c = qm / qv - ep.nu
+    assert np.all(tau_c > 0)
+    _, mh, vh = epo.tilted(0, nu_c / tau_c, 1 / tau_c, A_obs, sig)
+    assert np.allclose(qm, mh, rtol=1e-8, atol=1e-8)
+    assert np.allclose(qv, vh, rtol=1e-8)
+    # (4) the frozen projection converges elsewhere
+    fz = epo.DenseEP(dict(cfg, relinearize=False), raw["xyz"], A_obs, sig, sightlines=sl)
+    for _ in range(200):
+        if fz.sweep()["max_dtau"] < 1e-10:
+            break
+    assert np.max(np.abs(fz.posterior_mean() - mu)) > 1e-3
+
+
+def test_posterior_uses_current_linearisation_point():
+    """posterior() after a manual move of the linearisation point: its mean
+    and covariance are those of Q and b rebuilt at the new point from the
+    plain forward model (so no stale linearisation can be cached)."""
+    w, cfg = _small(n=6, L=400.0, stars=15, relinearize=True)
+    raw = draw(w)
+    f_true, A_obs, sl = epo.simulate(cfg, raw)
+    ep = epo.DenseEP(cfg, raw["xyz"], A_obs, raw["sigma"], sightlines=sl)
+    ep.sweep()
+    ep.sweep()
+    rng = np.random.default_rng(3)
+    ep.fhat = ep.fhat + 0.3 * rng.standard_normal(sl.grid.N)
+    mu, Sig, G, c = ep.posterior()
+    lnA, Gp = _lnA_plain(cfg, raw["xyz"], ep.fhat)
+    cp = lnA - Gp @ ep.fhat
+    Q = ep.Q0 + Gp.T @ (ep.tau[:, None] * Gp)
+    b = ep.Q0 @ np.full(sl.grid.N, cfg["prior_mean"]) + Gp.T @ (ep.nu - ep.tau * cp)
+    assert np.allclose(mu, np.linalg.solve(Q, b), rtol=1e-11, atol=1e-11)
+    assert np.allclose(Sig, np.linalg.inv(Q), rtol=1e-10, atol=1e-13)
