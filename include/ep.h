@@ -316,6 +316,28 @@ int ep_mlp_predict(const float *weights, int64_t n, const double *inputs, double
 int ep_mlp_loss_grad(const float *weights, int64_t n, const float *xstd, const float *ystd, double *loss,
                      float *grad, int32_t device);
 
+/* ---- For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) ----
+ * ep_mlp_predict_noalloc: ep_mlp_predict on device memory with no device
+ * allocation.  weights (EP_MLP_NPARAM floats, or NULL for the gate centred at
+ * the analytic baseline), inputs (n x 4), out3 (n x 3), errest (n) and
+ * accepted (n) are device buffers on `device`, owned by the caller; errest
+ * and accepted may be NULL.  stream: the hipStream_t to run on (NULL = the
+ * device's null stream); the call returns after completion.  Same results as
+ * ep_mlp_predict on the same data.  The BF16 copy of the hidden layers, the
+ * inputs split per field, the zero site arrays and an error counter live in
+ * one static device array of about 40 MB that every GPU the library runs on
+ * holds until the process ends; it is looked up on the first call on each
+ * device.  Calls on one GPU share that array: calls that overlap on one GPU
+ * (other host threads, other streams) race and must be serialised by the
+ * caller.  Errors: INVALID_ARG (n < 0 or n > EP_NOALLOC_MAX_TUPLES, NULL
+ * buffers, tol <= 0, device out of range, or a tuple with a non-finite mean or
+ * observation or v_c <= 0 or sigma <= 0, checked on the device before the
+ * network runs; outputs are then untouched), DEVICE. */
+#define EP_NOALLOC_MAX_TUPLES 1048576
+int ep_mlp_predict_noalloc(const float *weights, int64_t n, const double *inputs, double tol, double *out3,
+                           double *errest, int32_t *accepted, int32_t device, void *stream);
+
 /* Give a context the network used when cfg.moments = EP_MOM_SURROGATE. */
 int ep_mlp_load(ep_ctx *ctx, const float *weights);
 

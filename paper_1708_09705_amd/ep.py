@@ -94,8 +94,9 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
            "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta")
+           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc")
 MLP_NPARAM = 34065
+EP_NOALLOC_MAX_TUPLES = 1 << 20   # ep.h
 KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
 
 
@@ -169,12 +170,13 @@ def load(path: str | None = None):
     L.ep_pitc_predict.argtypes = [vp, vp, vp]
     L.ep_pitc_info.argtypes = [vp, ctypes.POINTER(ep_pitc_stats)]
     L.ep_pitc_theta.argtypes = [vp, vp, vp]
+    L.ep_mlp_predict_noalloc.argtypes = [vp, i64, vp, ctypes.c_double, vp, vp, vp, i32, vp]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
                  "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta"):
+                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -341,6 +343,35 @@ def ep_mlp_train(inputs, targets, epochs=20, batch=4096, lr=1e-3, seed=1, device
     hp = ep_mlp_hyper(epochs, batch, lr, seed)
     _check(L, L.ep_mlp_train(ctypes.byref(hp), X.shape[0], _ptr(X), _ptr(Y), _ptr(w), _ptr(loss), device))
     return w, loss
+
+
+def ep_mlp_predict_noalloc(weights, inputs, out3, errest=None, accepted=None, tol=1e-4, device=0, stream=None,
+                           lib=None):
+    """The allocation-free form of ep_mlp_predict: every array is a
+    contiguous tensor already on cuda:device (weights float32 or None, inputs
+    (n, 4) and out3 (n, 3) float64, errest float64, accepted int32; either of
+    the last two may be None); stream is a torch stream or None.  Nothing is
+    allocated: the outputs are written in place."""
+    L = lib or load()
+
+    def ptr(t, dtype, what):
+        if t is None:
+            return None
+        if str(t.dtype) != "torch." + dtype or not t.is_contiguous() or t.device.type != "cuda" \
+                or t.device.index != device:
+            raise ValueError(f"{what}: expected a contiguous {dtype} tensor on cuda:{device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    n = inputs.shape[0] if inputs.dim() == 2 else inputs.numel() // 4
+    if inputs.numel() != 4 * n or out3.numel() != 3 * n:
+        raise ValueError("inputs must hold n x 4 and out3 n x 3 values")
+    for t, k in ((errest, 1), (accepted, 1)):
+        if t is not None and t.numel() != k * n:
+            raise ValueError("errest and accepted must hold n values")
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(L, L.ep_mlp_predict_noalloc(ptr(weights, "float32", "weights"), n, ptr(inputs, "float64", "inputs"), tol,
+                                       ptr(out3, "float64", "out3"), ptr(errest, "float64", "errest"),
+                                       ptr(accepted, "int32", "accepted"), device, st))
 
 
 def ep_mlp_predict(weights, inputs, tol=1e-4, device=0, lib=None):

@@ -63,3 +63,14 @@ def test_invalid_inputs_rejected_before_device_work():
         E.ep_tilted_moments(0, [0.0], [-1.0], [0.3], [0.05])
     assert ei.value.code == -1
     assert b"no error" != L.ep_last_error(None)
+
+
+def test_noalloc_size_limit_rejected_before_device_work():
+    E, L = _lib()
+    assert E.EP_NOALLOC_MAX_TUPLES == 1 << 20
+    rc = L.ep_mlp_predict_noalloc(None, E.EP_NOALLOC_MAX_TUPLES + 1, None, 1e-4, None, None, None, 0, None)
+    assert rc == -1
+    assert b"exceeds the maximum" in L.ep_last_error(None)
+    rc = L.ep_mlp_predict_noalloc(None, 10, None, 1e-4, None, None, None, 0, None)
+    assert rc == -1
+    assert L.ep_mlp_predict_noalloc(None, 0, None, 1e-4, None, None, None, 0, None) == 0
