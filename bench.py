@@ -396,7 +396,8 @@ def main():
             "updated_last_sweep": int(stats_m[-1]["updated"]),
             "skipped_negative_site_last_sweep": int(stats_m[-1]["skipped_negsite"]),
             "note": "per-star two-component (ln s, log-extinction) mixtures; distance marginalised in the tilted "
-                    "distribution (closed-form Gaussian mixture in a_n)",
+                    "distribution by a 256-node rule in ln s per component along each sightline extended to the "
+                    "cube's face (extinction at each distance from the forward model at the linearisation point)",
         }
     if args.theta:
         # Data drawn around a disc + bump mean at THETA_TRUE; EP infers the

@@ -228,18 +228,24 @@ int ep_get_sites(ep_ctx *ctx, double *tau, double *nu);
 int ep_set_sites(ep_ctx *ctx, const double *tau, const double *nu);
 
 /* Unknown distances (Sec. 4.2 general case; likelihood GMM): per-star
- * Gaussian mixtures over (l, b) = (ln distance / pc, log-extinction implied at
- * that distance), K (1..8) components per star, comps n_stars x K x 6 rows
+ * Gaussian mixtures over (l, b) = (ln distance / pc, log-extinction to that
+ * distance), K (1..8) components per star, comps n_stars x K x 6 rows
  * (w, m_l, m_b, C_ll, C_lb, C_bb): weights >= 0 with a positive sum, C_bb > 0,
  * C positive definite (or C_ll = C_lb = 0: the distance is known).  The
- * distance is marginalised in the tilted distribution with the
- * log-extinction linearised in ln s about the catalogue distance s~
- * (beta_n = d ln A / d ln s = s~ e^{F(x_n)} / A_n at the current field);
- * each component then gives a Gaussian likelihood in a_n with mean
- * m_b - beta (m_l - ln s~) and variance C_bb - 2 beta C_lb + beta^2 C_ll, and
- * the tilted moments are those of a Gaussian mixture.  May be called again
- * (e.g. with another K).  Errors: INVALID_ARG, STATE (likelihood not GMM),
- * OOM, DEVICE. */
+ * tilted distribution sums over the components and integrates over the
+ * distance s.  The site stays on a_n = ln A to the catalogue position
+ * (distance s~); the log-extinction at distance s is
+ * a_n + ln A(s; fhat) - ln A(s~; fhat), from the sightline forward model at
+ * the linearisation point extended past the star (the star's own steps to s~,
+ * then steps of los_step_pc to the cube's face; the trapezoid sum to the last
+ * sample below s plus the partial trapezoid to s); distances past the cube's
+ * face carry no likelihood.  Per component the integral over a_n is closed
+ * form and the one over l = ln s a composite 16-panel, 16-node
+ * Gauss-Legendre rule over m_l +- 8 sd(l).  A star whose every component lies
+ * outside the cube gets lnZ = -inf and keeps its site.  May be called again
+ * (e.g. with another K).  Errors: INVALID_ARG (also when the extended
+ * sightlines and K need more than the kernel's 64 KB of LDS), STATE
+ * (likelihood not GMM), OOM, DEVICE. */
 int ep_set_gmm(ep_ctx *ctx, int32_t K, const double *comps);
 
 /* Linearisation point: fhat (n^3 doubles), followed with mean_fn DISC_BUMP

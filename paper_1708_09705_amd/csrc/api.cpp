@@ -130,9 +130,11 @@ struct ep_ctx {
     double phihat[NTHETA] = {};                   // mean linearisation point
     BorderDev border{};                           // mu_phi, phihat, Sigma_phiphi of the last border solve
     double *d_mhat = nullptr, *d_J = nullptr, *d_h = nullptr, *d_R = nullptr, *d_Wb = nullptr, *d_part = nullptr;
-    // unknown distances (likelihood GMM): per-star mixtures (ep_set_gmm), beta_n, ln of the catalogue distance
+    // unknown distances (likelihood GMM): per-star mixtures (ep_set_gmm) and the
+    // largest sample count of the sightlines extended to the cube's face
     int gmm_K = 0;
-    double *d_gmm = nullptr, *d_beta = nullptr, *d_lref = nullptr;
+    double* d_gmm = nullptr;
+    int64_t gmm_kcap = 0;
     // multi-vector solves (border columns, batches of posterior draws): MR_MAX x N each, at first use
     double *d_ymr = nullptr, *d_tmr = nullptr, *d_xmr = nullptr, *d_omr = nullptr;
     // PITC sub-catalogue pass (ep_pitc_setup)
@@ -850,14 +852,9 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
         std::copy(A, A + S, vA.begin());
         std::copy(sig, sig + S, vs.begin());
     } else {
-        std::vector<double> lref((size_t)S);
-        for (int64_t s = 0; s < S; s++) {
-            double d2 = 0;
-            for (int a = 0; a < 3; a++) d2 += (xyz[3 * s + a] - g.obs[a]) * (xyz[3 * s + a] - g.obs[a]);
-            lref[s] = 0.5 * std::log(d2);
-        }
-        TRY(upload(ctx, &ctx->d_lref, lref));
-        TRY(dev_alloc(ctx, &ctx->d_beta, S));
+        for (int64_t s = 0; s < S; s++)
+            ctx->gmm_kcap = std::max(ctx->gmm_kcap, gmm_ray_samples(xyz + 3 * s, g.obs, ctx->sup.nsamp[s], c.box_pc,
+                                                                    c.los_step_pc) + 1);
     }
     TRY(upload(ctx, &ctx->d_xyz, vx));
     TRY(upload(ctx, &ctx->d_A, vA));
@@ -949,7 +946,6 @@ static void enqueue_linearise(ep_ctx* ctx) {
         }
     }
     launch_los(ctx->stream, ctx->GD, ctx->SD, field, ctx->max_support);
-    if (ctx->cfg.likelihood == EP_LIK_GMM) launch_beta(ctx->stream, ctx->GD, ctx->SD, field, ctx->d_beta);
     if (ctx->M) launch_star_border(ctx->stream, ctx->SD, ctx->d_mhat, ctx->d_J, phi5(ctx->phihat), ctx->d_h, ctx->g.N());
     ctx->linearised = true;
 }
@@ -1330,8 +1326,16 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
     EpParams p{ctx->cfg.likelihood == EP_LIK_GAUSS_LINEAR ? 1 : 0, ctx->cfg.damping, ctx->cfg.cavity_var_floor};
     ctx->fallbacks = 0;
     if (ctx->cfg.likelihood == EP_LIK_GMM) {
+        // the extinction curves at the point the sightlines were linearised
+        // about: fhat, or the constant prior mean when frozen
         p.mode = 2;
-        launch_gmm_update(st, ctx->SD, p, ctx->d_gmm, ctx->gmm_K, ctx->d_beta, ctx->d_lref);
+        const double* field = ctx->d_fhat;
+        if (frozen(ctx) && !ctx->M) {
+            launch_fill(st, ctx->d_t, N, ctx->pp.mean);
+            field = ctx->d_t;
+        }
+        launch_gmm_ray(st, ctx->GD, ctx->SD, p, field, ctx->d_gmm, ctx->gmm_K, ctx->cfg.box_pc, ctx->cfg.los_step_pc,
+                       (int)ctx->gmm_kcap);
     } else if (ctx->cfg.moments == EP_MOM_SURROGATE && p.mode == 0) {
         // gated surrogate for every star, quadrature for the rejected ones
         HIPCHK(hipMemsetAsync(ctx->d_fb_count, 0, sizeof(int32_t), st));
@@ -1831,6 +1835,11 @@ int ep_set_gmm(ep_ctx* ctx, int32_t K, const double* comps) {
             wsum += c[0];
         }
         if (!(wsum > 0)) { ctx->err = "ep_set_gmm: star " + std::to_string(s) + " has no positive weight"; return EP_ERR_INVALID_ARG; }
+    }
+    if (gmm_lds_doubles(ctx->gmm_kcap, K) * (int64_t)sizeof(double) > 65536) {
+        ctx->err = "ep_set_gmm: the sightlines extended to the cube's face have " + std::to_string(ctx->gmm_kcap) +
+                   " samples; with " + std::to_string(K) + " components they exceed the 64 KB the kernel keeps in LDS";
+        return EP_ERR_INVALID_ARG;
     }
     if (ctx->gmm_K != K) {
         if (ctx->d_gmm) {   // resize: the old buffer stays in the context's list until ep_free

@@ -192,16 +192,20 @@ struct EpParams {
     double damping;
     double vfloor;
 };
-// unknown distances (gmm.hip): beta_n = d ln A / d ln s at the field f, and
-// the mixture tilted moments with the site update
-void launch_beta(hipStream_t st, GridDev g, StarsDev s, const double* f, double* beta);
-void launch_gmm_update(hipStream_t st, StarsDev s, EpParams p, const double* comps, int K, const double* beta,
-                       const double* lref);
+// unknown distances (gmm.hip): the tilted moments with the distance
+// marginalised along each sightline extended to the cube's face, and the site
+// update.  gmm_ray_samples: samples of one star's extended sightline (host);
+// gmm_lds_doubles: the kernel's LDS per star, kcap >= every star's samples.
+int64_t gmm_ray_samples(const double* xyz, const double* obs, int32_t T, double box, double step);
+int64_t gmm_lds_doubles(int64_t kcap, int K);
+void launch_gmm_ray(hipStream_t st, GridDev g, StarsDev s, EpParams p, const double* f, const double* comps, int K,
+                    double box, double step, int kcap);
 // list: optional subset of stars (nlist entries)
 void launch_tilted_update(hipStream_t st, StarsDev s, EpParams p, const int32_t* list = nullptr, int64_t nlist = 0);
 void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, const double* v, const double* A,
                          const double* sig, double* lnZ, double* mean, double* var);
 hipError_t set_gauss_legendre(hipStream_t st);
+void gauss_legendre16(double* x, double* w);   // nodes and weights on [-1, 1]
 
 // mixed precision factor (FP32 storage and MFMA, FP64 diagonal pivots)
 void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);

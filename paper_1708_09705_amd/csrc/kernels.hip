@@ -1350,9 +1350,8 @@ void launch_tilted_batch(hipStream_t st, int mode, int64_t n, const double* mu, 
 // cos(pi (i + 3/4) / (n + 1/2)) (the standard construction, e.g. Press et
 // al., Numerical Recipes, Sec. 4.5); computed on the host, copied to
 // constant memory.
-hipError_t set_gauss_legendre(hipStream_t st) {
+void gauss_legendre16(double* x, double* wgt) {
     const int n = 16;
-    double x[16], wgt[16];
     for (int i = 0; i < n; i++) {
         double z = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
         double dp = 1.0;
@@ -1380,6 +1379,11 @@ hipError_t set_gauss_legendre(hipStream_t st) {
         x[i] = z;
         wgt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
+}
+
+hipError_t set_gauss_legendre(hipStream_t st) {
+    double x[16], wgt[16];
+    gauss_legendre16(x, wgt);
     hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), wgt, sizeof(wgt), 0, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
