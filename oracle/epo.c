@@ -22,6 +22,7 @@
  * Build: gcc -O2 -fPIC -shared -fopenmp (no -ffast-math).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -666,5 +667,36 @@ void epo_prior_quadform_batch(int64_t N, const int64_t *rowptr, const int32_t *c
             out[s] = epo_prior_quadform(N, rowptr, col, val, d, (int)(ptr[s + 1] - ptr[s]),
                                         nodes + ptr[s], gval + ptr[s], work);
         free(work);
+    }
+}
+
+/* X <- Q0^{-1} X for k right-hand sides (X is N x k, row-major), with
+ * Q0^{-1} = (I-B)^{-1} D (I-B)^{-T}: a column-oriented backward substitution
+ * with (I-B)^T, the scaling by D, a forward substitution with (I-B).  The
+ * right-hand sides are split over the threads. */
+void epo_q0_solve_multi(int64_t N, const int64_t *rowptr, const int32_t *col, const double *val,
+                        const double *d, int64_t k, double *X) {
+#pragma omp parallel
+    {
+        int nt = omp_get_num_threads(), t = omp_get_thread_num();
+        int64_t c0 = k * t / nt, c1 = k * (t + 1) / nt;
+        if (c1 > c0) {
+            for (int64_t p = N - 1; p >= 0; p--) {
+                double *xp = X + p * k;
+                for (int64_t e = rowptr[p]; e < rowptr[p + 1]; e++) {
+                    double *xc = X + (int64_t)col[e] * k;
+                    for (int64_t j = c0; j < c1; j++) xc[j] += val[e] * xp[j];
+                }
+            }
+            for (int64_t p = 0; p < N; p++)
+                for (int64_t j = c0; j < c1; j++) X[p * k + j] *= d[p];
+            for (int64_t p = 0; p < N; p++) {
+                double *xp = X + p * k;
+                for (int64_t e = rowptr[p]; e < rowptr[p + 1]; e++) {
+                    const double *xc = X + (int64_t)col[e] * k;
+                    for (int64_t j = c0; j < c1; j++) xp[j] += val[e] * xc[j];
+                }
+            }
+        }
     }
 }

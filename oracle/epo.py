@@ -69,6 +69,7 @@ def lib():
         L.epo_vecchia.argtypes = [i32, d, d, d, d, d, p, p, p, p]
         L.epo_prior_draw.argtypes = [i64, p, p, p, p, d, p, p]
         L.epo_prior_quadform_batch.argtypes = [i64, p, p, p, p, i64, p, p, p, p]
+        L.epo_q0_solve_multi.argtypes = [i64, p, p, p, p, i64, p]
         L.epo_los_counts.argtypes = [i32, d, p, d, i64, p, p]
         L.epo_los_fill.argtypes = [i32, d, p, d, i64, p, p, p]
         L.epo_los_linearise.argtypes = [i32, d, p, d, i64, p, p, p, p, p, p, p]
@@ -181,6 +182,13 @@ class Vecchia:
         lib().epo_prior_draw(self.grid.N, _p(self.rowptr), _p(self.col), _p(self.val), _p(self.d),
                              m0, _p(xi), _p(f))
         return f
+
+    def q0_solve(self, X: np.ndarray) -> np.ndarray:
+        """Q0^{-1} X for X of shape (N,) or (N, k)."""
+        Y = np.array(X, dtype=np.float64, order="C", copy=True)
+        k = 1 if Y.ndim == 1 else Y.shape[1]
+        lib().epo_q0_solve_multi(self.grid.N, _p(self.rowptr), _p(self.col), _p(self.val), _p(self.d), k, _p(Y))
+        return Y
 
     def prior_quadform(self, ptr, nodes, gval) -> np.ndarray:
         """g_n^T Q0^{-1} g_n for every star (CSR rows)."""
