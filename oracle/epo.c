@@ -700,3 +700,56 @@ void epo_q0_solve_multi(int64_t N, const int64_t *rowptr, const int32_t *col, co
         }
     }
 }
+
+/* Y = Q X for k vectors (X, Y: N x k, row-major) with the posterior
+ * precision Q = (I-B)^T D^{-1} (I-B) + G^T diag(tau) G, G the star rows
+ * (CSR gptr, gnode, gval), never formed.  work: N x k doubles.  The vectors
+ * are split over the threads. */
+void epo_q_mul_multi(int64_t N, const int64_t *rowptr, const int32_t *col, const double *val,
+                     const double *d, int64_t S, const int64_t *gptr, const int32_t *gnode,
+                     const double *gval, const double *tau, int64_t k, const double *X, double *Y,
+                     double *work) {
+#pragma omp parallel
+    {
+        int nt = omp_get_num_threads(), t = omp_get_thread_num();
+        int64_t c0 = k * t / nt, c1 = k * (t + 1) / nt;
+        if (c1 > c0) {
+            /* work = D^{-1} (I-B) X */
+            for (int64_t p = 0; p < N; p++) {
+                double *wp = work + p * k;
+                const double *xp = X + p * k;
+                for (int64_t j = c0; j < c1; j++) wp[j] = xp[j];
+                for (int64_t e = rowptr[p]; e < rowptr[p + 1]; e++) {
+                    const double *xc = X + (int64_t)col[e] * k;
+                    for (int64_t j = c0; j < c1; j++) wp[j] -= val[e] * xc[j];
+                }
+                for (int64_t j = c0; j < c1; j++) wp[j] /= d[p];
+            }
+            /* Y = (I-B)^T work */
+            for (int64_t p = 0; p < N; p++)
+                for (int64_t j = c0; j < c1; j++) Y[p * k + j] = work[p * k + j];
+            for (int64_t p = 0; p < N; p++) {
+                const double *wp = work + p * k;
+                for (int64_t e = rowptr[p]; e < rowptr[p + 1]; e++) {
+                    double *yc = Y + (int64_t)col[e] * k;
+                    for (int64_t j = c0; j < c1; j++) yc[j] -= val[e] * wp[j];
+                }
+            }
+            /* Y += G^T (tau * (G X)), one star at a time */
+            double *a = (double *)malloc(sizeof(double) * (size_t)(c1 - c0));
+            for (int64_t s = 0; s < S; s++) {
+                for (int64_t j = c0; j < c1; j++) a[j - c0] = 0.0;
+                for (int64_t e = gptr[s]; e < gptr[s + 1]; e++) {
+                    const double *xq = X + (int64_t)gnode[e] * k;
+                    for (int64_t j = c0; j < c1; j++) a[j - c0] += gval[e] * xq[j];
+                }
+                for (int64_t j = c0; j < c1; j++) a[j - c0] *= tau[s];
+                for (int64_t e = gptr[s]; e < gptr[s + 1]; e++) {
+                    double *yq = Y + (int64_t)gnode[e] * k;
+                    for (int64_t j = c0; j < c1; j++) yq[j] += gval[e] * a[j - c0];
+                }
+            }
+            free(a);
+        }
+    }
+}

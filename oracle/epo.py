@@ -70,6 +70,7 @@ def lib():
         L.epo_prior_draw.argtypes = [i64, p, p, p, p, d, p, p]
         L.epo_prior_quadform_batch.argtypes = [i64, p, p, p, p, i64, p, p, p, p]
         L.epo_q0_solve_multi.argtypes = [i64, p, p, p, p, i64, p]
+        L.epo_q_mul_multi.argtypes = [i64, p, p, p, p, i64, p, p, p, p, i64, p, p, p]
         L.epo_los_counts.argtypes = [i32, d, p, d, i64, p, p]
         L.epo_los_fill.argtypes = [i32, d, p, d, i64, p, p, p]
         L.epo_los_linearise.argtypes = [i32, d, p, d, i64, p, p, p, p, p, p, p]

@@ -20,34 +20,39 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .epo import Sightlines, Vecchia
+from .epo import Sightlines, Vecchia, _p, lib
 
 
 class PosteriorOps:
     """Products with Q and solves with Q0 for one set of sites."""
 
     def __init__(self, vec: Vecchia, sl: Sightlines, gval: np.ndarray, tau: np.ndarray):
+        self.vec, self.sl = vec, sl
+        self.gval = np.ascontiguousarray(gval, dtype=np.float64)
+        self.tau = np.ascontiguousarray(tau, dtype=np.float64)
         N, S = vec.grid.N, sl.n_stars
-        rows = np.repeat(np.arange(N), np.diff(vec.rowptr))
-        IB = sp.identity(N, format="csr") - sp.csr_matrix(
-            (vec.val[: vec.nnz], (rows, vec.col[: vec.nnz])), shape=(N, N))
-        self.IB, self.IBt = IB.tocsr(), IB.T.tocsr()
-        self.dinv = 1.0 / vec.d
-        G = sp.csr_matrix((gval, sl.nodes, sl.ptr), shape=(S, N))
-        self.G, self.Gt = G, G.T.tocsr()
-        self.tau = np.asarray(tau, dtype=np.float64)
-        self.vec = vec
+        self.G = sp.csr_matrix((self.gval, sl.nodes, sl.ptr), shape=(S, N))
+        self.Gt = self.G.T.tocsr()
 
     def Q(self, X: np.ndarray) -> np.ndarray:
-        X2 = X if X.ndim == 2 else X[:, None]
-        Y = self.IBt @ (self.dinv[:, None] * (self.IB @ X2)) + self.Gt @ (self.tau[:, None] * (self.G @ X2))
+        X2 = np.ascontiguousarray(X if X.ndim == 2 else X[:, None], dtype=np.float64)
+        N, k = X2.shape
+        Y = np.empty_like(X2)
+        work = np.empty_like(X2)
+        v, sl = self.vec, self.sl
+        lib().epo_q_mul_multi(N, _p(v.rowptr), _p(v.col), _p(v.val), _p(v.d), sl.n_stars, _p(sl.ptr),
+                              _p(sl.nodes), _p(self.gval), _p(self.tau), k, _p(X2), _p(Y), _p(work))
         return Y if X.ndim == 2 else Y[:, 0]
+
+    def Q0(self, x: np.ndarray) -> np.ndarray:
+        """Q0 x (no site term)."""
+        return PosteriorOps(self.vec, self.sl, self.gval, np.zeros_like(self.tau)).Q(x)
 
     def M(self, R: np.ndarray) -> np.ndarray:
         return self.vec.q0_solve(R)
 
 
-def pcg(ops: PosteriorOps, R: np.ndarray, rtol: float = 1e-15, maxit: int = 5000, log=None):
+def pcg(ops: PosteriorOps, R: np.ndarray, rtol: float = 1e-15, maxit: int = 5000, log=None, stall: int = 40):
     """Q^{-1} R, one preconditioned CG recurrence per column, each run until
     its residual falls below rtol times its right-hand side or stops falling
     (no halving in 40 iterations: rounding has been reached).
@@ -76,7 +81,7 @@ def pcg(ops: PosteriorOps, R: np.ndarray, rtol: float = 1e-15, maxit: int = 5000
         gain = res < 0.5 * best
         best = np.where(gain, res, best)
         since = np.where(gain, 0, since + 1)
-        active = active & (res > rtol) & (since < 40)
+        active = active & (res > rtol) & (since < stall)
         if log and (it % 50 == 0 or not active.any()):
             log(f"pcg iteration {it}: max relative residual {res.max():.3e}, {int(active.sum())} columns active")
         if not active.any():
