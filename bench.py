@@ -92,6 +92,80 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
                       "ms_per_copy": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+# measured FP64 rate of the dominant task-GEMM kernel on the 64^3 / 100k sweep
+# (55 TFLOP/s): the plan's sweep-time estimate divides its MFMA work by it
+MEASURED_GEMM_TFLOPS = 55.0
+HBM_BYTES = 288e9
+
+
+def sparse_kernels(st, stats, N) -> dict:
+    """Achieved bandwidth of the sparse kernels on their algorithmic bytes
+    (what each must move at least once per sweep), from the per-launch HIP
+    events of the timed sweeps."""
+    S = st["n_stars"]
+    algo = {
+        # the fronts' lower-triangular tiles, written once
+        "zero": 8 * st["front_elems_lower"],
+        # every clique entry read and written (FP64 atomic add); g and the local row per slot
+        "assemble": 16 * st["clique_pairs"] + 12 * st["nnz_g"],
+        # every update-block entry: read in the child, read and written in the parent
+        "extend": 24 * st["update_elems"],
+        # every update-block entry of Sigma: read in the parent, written in the child
+        "gather": 16 * st["update_elems"],
+        # every clique entry of Sigma read once; per slot g, local row, slot order, node and mu
+        "cavity": 8 * st["clique_pairs"] + 28 * st["nnz_g"] + 40 * S,
+        # one solve: the factor's pivot-block inverses and off-diagonal blocks, forward and backward
+        "solve": 16 * (st["x_elems"] + st["offdiag_elems"]) + 6 * 8 * N,
+    }
+    out = {}
+    for k, b in algo.items():
+        ms = float(np.mean([s_["kernel_ms"][k] for s_ in stats]))
+        if ms <= 0:
+            continue
+        gbs = b / (ms * 1e-3) / 1e9
+        out[k] = {"ms_per_step": ms, "launches_per_step": int(stats[-1]["kernel_launches"][k]),
+                  "algorithmic_bytes_per_step": int(b), "GBps": gbs, "frac_of_hbm_peak": gbs / PEAK_HBM_GBS}
+    out["note"] = ("zero: k_zero_lower; assemble: k_assemble_stars (L2 FP64 atomics); extend: k_extend_add; "
+                   "gather: k_sigma_gather; cavity: k_cavity; solve: k_fwd_xv/k_fwd_r/k_bwd_t/k_bwd_x")
+    return out
+
+
+def scaled_workload(w, n):
+    """The workload on an n^3 grid at the same spacing: the cube side and the
+    star-distance cut scale with (n - 1)."""
+    import dataclasses
+    box = w.box_pc / (w.n - 1) * (n - 1)
+    return dataclasses.replace(w, n=n, box_pc=box, d_max_pc=min(w.d_max_pc, box) if w.d_max_pc else box,
+                               name=f"{n}cube-{w.n_stars // 1000}k-at-{box / (n - 1):.1f}pc")
+
+
+def variant_workload():
+    """The largest single-GPU variant of the 128^3 / 1M-star workload: the
+    same spacing (63 pc), prior, star law and count, on 80^3 nodes (5 kpc)."""
+    from synth import preset
+    import dataclasses
+    return dataclasses.replace(scaled_workload(preset(3), 80), precision="fp64", moments="quadrature")
+
+
+def plan_of(w) -> dict:
+    """Host structure analysis (ep_plan: no device) of a workload."""
+    from paper_1708_09705_amd import ep as E
+    from synth import draw
+    raw = draw(w, field=False)
+    t0 = time.perf_counter()
+    p = E.ep_plan(w.ep_fields(), raw["xyz"])
+    mfma = p["trail_flops"] + p["selinv_flops"]
+    return {**p, "factor_bytes_fp64": 8 * p["nnz_L"], "front_bytes_full_squares": 8 * p["front_elems"],
+            "front_bytes_lower_tiles": 8 * p["front_elems_lower"],
+            "fits_one_gpu_fp64": p["device_bytes"] <= HBM_BYTES,
+            "fits_one_gpu_mixed": p["device_bytes_mixed"] <= HBM_BYTES,
+            "mfma_flop_per_sweep": mfma,
+            "est_gemm_s_per_sweep": mfma / (MEASURED_GEMM_TFLOPS * 1e12),
+            "plan_seconds": time.perf_counter() - t0,
+            "note": "device_bytes counts ep_init's allocations without the GEMM task lists; "
+                    f"est_gemm_s_per_sweep = MFMA flop / {MEASURED_GEMM_TFLOPS} TFLOP/s (the rate measured at 64^3)"}
+
+
 THETA_TRUE = (2500.0, 200.0, 1.2e-3, 1800.0, 0.15)   # (L, H, rho kappa_0, s_bump, A_bump) of the synthetic sky
 
 
@@ -118,14 +192,36 @@ def main():
                     help="run only the PITC leg and print its JSON object (for profiling it alone)")
     ap.add_argument("--no-maps", dest="maps", action="store_false",
                     help="skip timing the map predictions after the FP64 run")
-    ap.add_argument("--mixed-quadrature", action="store_true",
-                    help="also run mixed precision with quadrature moments")
+    ap.add_argument("--side-steps", type=int, default=5,
+                    help="timed sweeps of every side leg (mixed, surrogate, gmm, theta)")
+    ap.add_argument("--no-variant", dest="variant", action="store_false",
+                    help="skip the largest single-GPU variant of the 128^3 / 1M-star workload")
+    ap.add_argument("--no-plan", dest="plan_in_line", action="store_false",
+                    help="skip the host structure analysis of the 128^3 / 1M-star workload")
+    ap.add_argument("--plan", action="store_true",
+                    help="CPU only: print the structure, work and memory of --preset (host analysis, no device) "
+                         "and exit")
+    ap.add_argument("--plan-n", type=int, default=0,
+                    help="with --plan: another grid size at the preset's spacing (box and star distances scaled)")
+    ap.add_argument("--plan-rho", type=float, default=0.0,
+                    help="with --plan: another Vecchia conditioning radius (pc)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference kernel that "
                          "scales the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.plan:
+        from synth import preset
+        w = preset(args.preset) if not args.stars else preset(args.preset, n_stars=args.stars)
+        if args.plan_n:
+            w = scaled_workload(w, args.plan_n)
+        if args.plan_rho:
+            import dataclasses
+            w = dataclasses.replace(w, vecchia_radius_pc=args.plan_rho, name=f"{w.name}-rho{args.plan_rho:g}")
+        print(json.dumps({"workload": w.name, "grid": f"{w.n}^3", "box_pc": w.box_pc, "stars": w.n_stars,
+                          **plan_of(w)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -145,6 +241,55 @@ def main():
     log(f"simulated {w.name}: {time.perf_counter() - t0:.1f} s")
 
     weights = np.load(os.path.join(ROOT, "paper_1708_09705_amd", "surrogate_64cube.npy"))
+
+    def variant_leg():
+        # the 128^3 / 1M-star workload does not fit one GPU (headline_structure);
+        # this is its largest variant that does, timed the same way
+        wv = variant_workload()
+        rv = draw(wv)
+        cv = E.make_config(wv.ep_fields(), leaf_size=args.leaf, device=0)
+        t0 = time.perf_counter()
+        _, Av = E.ep_simulate(cv, rv["xyz"], rv["sigma"], rv["eps"], rv["xi"])
+        g = E.EP(cv, rv["xyz"], Av, rv["sigma"])
+        init_s = time.perf_counter() - t0
+        stv = g.structure()
+        log(f"[variant {wv.name}] init {init_s:.1f} s; structure {stv}")
+        for i in range(side_w):
+            log(f"[variant] warmup {i}: {g.sweep()['ms_total']:.0f} ms")
+        torch.cuda.synchronize()
+        sts = []
+        t0 = time.perf_counter()
+        for i in range(max(1, side // 2)):
+            sts.append(g.sweep())
+            log(f"[variant] step {i}: {sts[-1]['ms_total']:.0f} ms")
+        torch.cuda.synchronize()
+        wv_s = time.perf_counter() - t0
+        g.close()
+        n_st = max(1, side // 2)
+        return {"workload": wv.name, "grid": f"{wv.n}^3", "box_pc": wv.box_pc, "stars": wv.n_stars,
+                "value": wv.n_stars * n_st / wv_s, "unit": "star-updates/s", "ms_per_step": wv_s / n_st * 1e3,
+                "steps": n_st, "warmup": side_w, "init_s": init_s,
+                "phases_ms": {k: float(np.mean([s_[k] for s_ in sts])) for k in
+                              ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star",
+                               "ms_total")},
+                "structure": {k: stv[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front",
+                                                   "factor_flops", "selinv_flops", "trail_flops", "device_bytes")},
+                "note": "FP64, quadrature; the same spacing, prior and star law as 128^3 / 1M on a 5 kpc cube"}
+
+    def surrogate_gain():
+        # the gate centred at the network against the gate centred at the
+        # analytic baseline, on the cavities of the FP64 run's last sweep
+        # (tuples no training run saw: the network was trained on other seeds)
+        ss = final["star_state"]
+        X = np.stack([ss["cav_mu"], ss["cav_var"], A, raw["sigma"]], axis=1)
+        ok = np.isfinite(X).all(axis=1) & (X[:, 1] > 0)
+        X = X[ok]
+        _, _, acc_n = E.ep_mlp_predict(weights, X, tol=1e-4)
+        _, _, acc_b = E.ep_mlp_predict(None, X, tol=1e-4)
+        return {"tuples": int(len(X)), "accepted_network": float(acc_n.mean()),
+                "accepted_baseline_only": float(acc_b.mean()),
+                "fallbacks_network": int((~acc_n).sum()), "fallbacks_baseline_only": int((~acc_b).sum()),
+                "note": "quadrature fallbacks with the gate (1e-4) centred at the network vs at the analytic baseline"}
 
     def maps_leg(g):
         # Map predictions from the converged state of the FP64 run; every call
@@ -271,7 +416,10 @@ def main():
         print(json.dumps({"pitc_leg": pitc_leg()}), flush=True)
         return
 
-    def run(prec, moments="quadrature", after=None, A_in=None, extra=None, xyz_in=None, comps=None):
+    def run(prec, moments="quadrature", after=None, A_in=None, extra=None, xyz_in=None, comps=None, steps=None,
+            warmup=None, state=None):
+        steps = args.steps if steps is None else steps
+        warmup = args.warmup if warmup is None else warmup
         c = E.make_config(w.ep_fields(), leaf_size=args.leaf, device=0, profile_kernels=1, precision=prec,
                           moments=moments, **(extra or {}))
         A_run = A if A_in is None else A_in
@@ -286,24 +434,35 @@ def main():
         prec = f"{prec}/{moments}"
         st = g.structure()
         log(f"[{prec}] init {time.perf_counter() - t0:.1f} s; structure {st}")
-        for i in range(args.warmup):
+        for i in range(warmup):
             s = g.sweep()
             log(f"[{prec}] warmup {i}: {s['ms_total']:.1f} ms")
         torch.cuda.synchronize()
         stats = []
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             s = g.sweep()
             stats.append(s)
             log(f"[{prec}] step {i}: {json.dumps({k: round(v, 3) if isinstance(v, float) else v for k, v in s.items()})}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        if state is not None:
+            # the posterior of another run's final sites at its linearisation point
+            g.set_sites(*state[0])
+            g.set_linpoint(state[1])
         mean, var = (g.posterior_mean(), g.marginal_var()) if args.mixed else (None, None)
         extra = after(g) if after else None
         g.close()
         return st, stats, wall, mean, var, extra
 
-    st, stats, wall, mean64, var64, maps = run("fp64", after=maps_leg if args.maps else None)
+    final = {}
+
+    def fp64_after(g):
+        final["state"] = (g.sites(), g.linpoint())
+        final["star_state"] = g.star_state()
+        return maps_leg(g) if args.maps else None
+
+    st, stats, wall, mean64, var64, maps = run("fp64", after=fp64_after)
     S = w.n_stars
     value = S * args.steps / wall
     ph = {k: float(np.mean([s[k] for s in stats])) for k in
@@ -340,7 +499,9 @@ def main():
         "phases_ms": ph,
         "star_phase_updates_per_s": S / (ph["ms_star"] * 1e-3),
         "structure": {k: st[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front", "factor_flops",
-                                         "selinv_flops", "trail_flops", "device_bytes")},
+                                         "selinv_flops", "trail_flops", "device_bytes", "front_elems_lower",
+                                         "update_elems", "offdiag_elems", "x_elems", "clique_pairs", "nnz_g")},
+        "sparse_kernels": sparse_kernels(st, stats, w.n ** 3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": TRAFFIC_GEMM_TASKS["bytes_per_launch"] if TRAFFIC_GEMM_TASKS else None,
@@ -359,11 +520,16 @@ def main():
                          "all_mfma_tile_kernels": {"ms_per_step": mfma_ms, "algorithmic_flop_per_step": all_flops,
                                                    "tflops": all_flops / (mfma_ms * 1e-3) / 1e12}}},
     }
+    side = min(args.steps, args.side_steps)
+    side_w = min(args.warmup, 1)
+
     def leg(prec, moments):
-        st32, stats32, wall32, mean32, var32, _ = run(prec, moments)
+        st32, stats32, wall32, mean32, var32, _ = run(prec, moments, steps=side, warmup=side_w,
+                                                      state=final["state"])
         ph32 = {k: float(np.mean([s[k] for s in stats32])) for k in ph}
         return {
-            "value": S * args.steps / wall32, "unit": "star-updates/s", "ms_per_step": wall32 / args.steps * 1e3,
+            "value": S * side / wall32, "unit": "star-updates/s", "ms_per_step": wall32 / side * 1e3,
+            "steps": side, "warmup": side_w,
             "star_phase_updates_per_s": S / (ph32["ms_star"] * 1e-3),
             "phases_ms": ph32,
             "refine_iters": int(stats32[-1]["refine_iters"]),
@@ -376,7 +542,10 @@ def main():
             "rms_rel_err_vs_fp64": {
                 "posterior_mean": float(np.sqrt(np.mean(((mean32 - mean64) / mean64) ** 2))),
                 "marginal_var": float(np.sqrt(np.mean(((var32 - var64) / var64) ** 2)))},
-            "note": "same warm-up and step count as the FP64 run; errors after the same sweeps",
+            "meets_1e-4": bool(np.max(np.abs(mean32 - mean64) / np.abs(mean64)) <= 1e-4
+                               and np.max(np.abs(var32 - var64) / np.abs(var64)) <= 1e-4),
+            "note": ("timed over its own short run; errors on the same state: the FP64 run's final sites at its "
+                     "final linearisation point, q(f) recomputed in this precision"),
         }
 
     if maps:
@@ -389,9 +558,10 @@ def main():
         _, A_true = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], np.zeros(S), raw["xi"])
         cat = gmm_catalogue(w, raw["xyz"], np.log(A_true))
         st_m, stats_m, wall_m, _, _, _ = run("fp64", extra=dict(likelihood="gmm"), xyz_in=cat["xyz"],
-                                             comps=cat["comps"])
+                                             comps=cat["comps"], steps=side, warmup=side_w)
         line["gmm_leg"] = {
-            "value": S * args.steps / wall_m, "unit": "star-updates/s", "ms_per_step": wall_m / args.steps * 1e3,
+            "value": S * side / wall_m, "unit": "star-updates/s", "ms_per_step": wall_m / side * 1e3,
+            "steps": side, "warmup": side_w,
             "phases_ms": {k: float(np.mean([s[k] for s in stats_m])) for k in ph},
             "updated_last_sweep": int(stats_m[-1]["updated"]),
             "skipped_negative_site_last_sweep": int(stats_m[-1]["skipped_negsite"]),
@@ -414,9 +584,11 @@ def main():
             thv["z_true"] = [float(v) for v in (m - np.log(THETA_TRUE)) / sd]
             return None
 
-        st_t, stats_t, wall_t, _, _, _ = run("fp64", A_in=A_th, after=theta_after, extra=dict(mean_fn="disc_bump"))
+        st_t, stats_t, wall_t, _, _, _ = run("fp64", A_in=A_th, after=theta_after, extra=dict(mean_fn="disc_bump"),
+                                             steps=max(side, 4), warmup=side_w)
         line["theta_leg"] = {
-            "value": S * args.steps / wall_t, "unit": "star-updates/s", "ms_per_step": wall_t / args.steps * 1e3,
+            "value": S * max(side, 4) / wall_t, "unit": "star-updates/s", "ms_per_step": wall_t / max(side, 4) * 1e3,
+            "steps": max(side, 4), "warmup": side_w,
             "phases_ms": {k: float(np.mean([s[k] for s in stats_t])) for k in ph},
             "theta_names": ["L_pc", "H_pc", "rho_kappa0_per_pc", "s_bump_pc", "A_bump_mag"],
             "theta_true": list(THETA_TRUE), "theta_prior_mean": list(E.make_config().theta_prior),
@@ -428,8 +600,14 @@ def main():
         line["pitc_leg"] = pitc_leg()
     if args.mixed:
         line["surrogate_mixed"] = leg("mixed", "surrogate")
-        if args.mixed_quadrature:
-            line["mixed_quadrature"] = leg("mixed", "quadrature")
+        line["mixed_quadrature"] = leg("mixed", "quadrature")
+        line["fp64_surrogate"] = leg("fp64", "surrogate")
+        line["surrogate_gain"] = surrogate_gain()
+    if args.variant:
+        line["headline_variant"] = variant_leg()
+    if args.plan_in_line:
+        line["headline_structure"] = {"cfg3-128cube-1M": plan_of(preset(3)),
+                                      "largest_fitting_variant": plan_of(variant_workload())}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.preset, args.cpu_sample)
     print(json.dumps(line), flush=True)

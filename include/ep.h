@@ -120,16 +120,27 @@ typedef struct ep_config {
     double bump_width_pc;      /* w, the bump's fixed standard deviation (default 400) */
 } ep_config;
 
-/* Kinds of timed MFMA tile-kernel launches (ep_sweep_stats.kernel_ms):
- * column-panel triangular solves, in-panel rank updates, trailing updates
- * after each panel, and the task-list GEMM kernel (diagonal-block inverses
- * and the selected-inversion products). */
+/* Kinds of timed kernel launches (ep_sweep_stats.kernel_ms, with
+ * profile_kernels = 1).  MFMA tile kernels: column-panel triangular solves,
+ * in-panel rank updates, trailing updates after each panel, and the
+ * task-list GEMM kernel (diagonal-block inverses and the selected-inversion
+ * products).  Sparse kernels: zeroing of the fronts' lower tiles, the star
+ * cliques' assembly into the fronts, extend-add of the update blocks, the
+ * selected inversion's gather of the parent's Sigma, the cavity, and the
+ * triangular-solve kernels. */
 enum {
     EP_KK_TRSM = 0,
     EP_KK_INNER = 1,
     EP_KK_TRAIL = 2,
     EP_KK_GEMM = 3,
-    EP_KK_COUNT = 4
+    EP_KK_MFMA = 4,            /* kinds below this one are the MFMA tile kernels */
+    EP_KK_ZERO = 4,
+    EP_KK_ASSEMBLE = 5,
+    EP_KK_EXTEND = 6,
+    EP_KK_GATHER = 7,
+    EP_KK_CAVITY = 8,
+    EP_KK_SOLVE = 9,
+    EP_KK_COUNT = 10
 };
 
 typedef struct ep_sweep_stats {
@@ -150,7 +161,7 @@ typedef struct ep_sweep_stats {
     int32_t refine_iters;      /* mixed precision: FP64 refinement rounds of the mean */
     double refine_residual;    /* mixed precision: final ||b - Q mu|| / ||b|| */
     int64_t surrogate_fallbacks; /* surrogate moments: stars sent to the quadrature */
-    double kernel_ms[EP_KK_COUNT];        /* mfma_ms split by kind (EP_KK_*) */
+    double kernel_ms[EP_KK_COUNT];        /* timed launches by kind (EP_KK_*) */
     int64_t kernel_launches[EP_KK_COUNT]; /* mfma_launches split by kind */
 } ep_sweep_stats;
 
@@ -168,6 +179,11 @@ typedef struct ep_structure_stats {
     double trail_flops;        /* trailing-update share of factor_flops
                                   (the EP_KK_TRAIL work) */
     int64_t device_bytes;      /* bytes the context holds on the device */
+    int64_t front_elems_lower; /* elements of the fronts' lower-triangular 64 x 64 tiles */
+    int64_t update_elems;      /* sum over fronts of nr (nr + 1) / 2: the update blocks' lower triangles */
+    int64_t offdiag_elems;     /* sum over fronts of nr nv: the factor's off-diagonal blocks */
+    int64_t x_elems;           /* sum over fronts of nvpad^2: the pivot blocks' inverses */
+    int64_t clique_pairs;      /* sum over stars of |P|(|P| + 1) / 2: the cliques' lower triangles */
 } ep_structure_stats;
 
 typedef struct ep_ctx ep_ctx;
@@ -349,6 +365,34 @@ int ep_mlp_load(ep_ctx *ctx, const float *weights);
 
 /* Structure and memory figures of a context. */
 int ep_structure(const ep_ctx *ctx, ep_structure_stats *out);
+
+/* Structure, work and memory of a configuration without a device: the
+ * host analysis of ep_init (sightline supports, nested dissection, the
+ * multifrontal layout of the posterior precision's factor) on the same
+ * inputs, with the device memory ep_init would take counted instead of
+ * allocated.  Host memory and time grow with the stars' supports and the
+ * fronts' R lists (about 2 GB and a minute for 128^3 nodes and 10^6 stars).
+ * Errors: INVALID_ARG (config or star positions), STATE (analysis). */
+typedef struct ep_plan_stats {
+    int64_t n_nodes, n_stars;
+    int64_t nnz_g;             /* total sightline support size */
+    int64_t max_support;       /* largest sightline support (ep_init refuses > 1300) */
+    int64_t n_fronts;
+    int32_t n_levels;
+    int64_t max_front;         /* largest front order (padded) */
+    int64_t max_separator;     /* largest set of pivots of one front */
+    int64_t front_elems;       /* sum of m^2: the fronts as stored (full squares) */
+    int64_t front_elems_lower; /* the fronts' lower-triangular 64 x 64 tiles only */
+    int64_t nnz_L;             /* nonzeros of the Cholesky factor: sum nv(nv+1)/2 + nv nr */
+    int64_t x_elems;           /* inverses of the pivot blocks (sum nvpad^2) */
+    int64_t w_elems;           /* selected-inversion scratch (largest level) */
+    double factor_flops;       /* partial Cholesky flops of all fronts */
+    double selinv_flops;       /* selected-inversion flops, diagonal-block inverses included */
+    double trail_flops;        /* trailing-update share of factor_flops */
+    int64_t device_bytes;      /* device memory of an FP64 context (without its GEMM task lists) */
+    int64_t device_bytes_mixed;/* the same with the FP32 copy of the fronts (precision MIXED) */
+} ep_plan_stats;
+int ep_plan(const ep_config *cfg, int64_t n_stars, const double *xyz, ep_plan_stats *out);
 
 /* ---- Map prediction from the posterior (Sec. 5: maps of extinction and
  * of the pseudo-density rho kappa = e^f) ----

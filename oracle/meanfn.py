@@ -19,7 +19,8 @@ equal the given value M_j; in phi = ln theta that is N(ln M_j - ln2/2, ln 2).
 
 Joint EP over (delta, phi), f = m(phi) + delta, delta ~ N(0, Q0^{-1}) (the
 paper's q(u, Theta), Gaussian in the latent field and the hyperparameters,
-Sec. 4.1).  Each sweep linearises the mean about phihat,
+Sec. 4.1).  Each sweep linearises the mean about phihat (also in the
+Gaussian mode, whose sightlines stay frozen),
 m(phi) ~ mhat + J (phi - phihat), and every sightline about fhat = mhat +
 deltahat, so the site variable a_n = c'_n + g_n.delta + h_n.phi with
 h_n = J^T g_n and c'_n = c_n + g_n.mhat - h_n.phihat.  The posterior of
@@ -116,9 +117,13 @@ class DenseEPTheta(DenseEP):
         self._lin = None
         if not self.relin:
             self._lin = self.sl.linearise(self.fhat)
+        # the mean is re-linearised at phihat every sweep whenever relinearize
+        # is on, also in the Gaussian mode, whose sightlines stay frozen at the
+        # prior mean (its observation model)
+        self.relin_mean = bool(cfg.get("relinearize", True))
 
     def mean_linearisation(self):
-        if self.relin:
+        if self.relin_mean:
             self._mJ = self.mean(self.phihat)
         return self._mJ
 
@@ -173,6 +178,11 @@ class DenseEPTheta(DenseEP):
             self.phihat = mu[N:].copy()
             mnew, _ = self.mean(self.phihat)
             self.fhat = mnew + mu[:N]
+        elif self.relin_mean:
+            # Gaussian mode: a damped Gauss-Newton step of the mean's
+            # linearisation point (full steps can cycle when the bump is
+            # weakly identified)
+            self.phihat = (1 - d) * self.phihat + d * mu[N:]
         return dict(updated=int(good.sum()), skipped_cavity=int((~ok).sum()),
                     skipped_negsite=int((ok & ~good).sum()), cav_mu=mu_c, cav_var=v_c,
                     lnZ=lnZ, tilted_mean=mh, tilted_var=vh)
@@ -197,3 +207,43 @@ class DenseEPTheta(DenseEP):
         mu, Sigma, _, _ = self.posterior_x()
         N = self.grid.N
         return mu[N:].copy(), Sigma[N:, N:].copy()
+
+
+def exact_theta_posterior_gaussian(cfg, sl, vec, a_obs, sigma, prop_mean, prop_cov, n_samples=8000, seed=0,
+                                   dof=5.0):
+    """Mean and covariance of the exact p(phi | a~) in the Gaussian mode, by
+    importance sampling.  The sightlines are linearised at the prior mean
+    m(mu0) (the observation model), so given phi the data are exactly
+    Gaussian: a~ ~ N(c + G m(phi), G K G^T + S), K = Q0^{-1}, S = diag sigma^2,
+    times the log-normal hyperprior.  Proposal: a multivariate t (dof) with
+    the given mean and covariance.  Returns (mean, covariance, effective
+    sample size)."""
+    import scipy.linalg as sla
+    pos = vec.grid.xyz()
+    mu0, s02 = hyperprior(cfg)
+    m0, _ = mean_and_jacobian(cfg, pos, mu0)
+    gval, _, c = sl.linearise(m0)
+    G = sl.G_dense(gval)
+    K = np.linalg.inv(vec.Q0_dense())
+    L = np.linalg.cholesky(G @ K @ G.T + np.diag(np.asarray(sigma, dtype=np.float64) ** 2))
+    rng = np.random.default_rng(seed)
+    Lp = np.linalg.cholesky(prop_cov)
+    k = len(prop_mean)
+    X = prop_mean + (rng.standard_normal((n_samples, k)) @ Lp.T) * np.sqrt(dof / rng.chisquare(dof, n_samples))[:, None]
+    d = sla.solve_triangular(Lp, (X - prop_mean).T, lower=True).T
+    lq = -0.5 * (dof + k) * np.log1p(np.sum(d * d, 1) / dof)
+    lp = np.empty(n_samples)
+    for s in range(0, n_samples, 500):
+        Xb = X[s:s + 500]
+        with np.errstate(all="ignore"):
+            R = np.stack([a_obs - c - G @ mean_and_jacobian(cfg, pos, x)[0] for x in Xb], axis=1)
+        ok = np.all(np.isfinite(R), axis=0)      # a draw so far out that the mean under- or overflows
+        R[:, ~ok] = 0.0
+        Y = sla.solve_triangular(L, R, lower=True)
+        lp[s:s + 500] = np.where(ok, -0.5 * np.sum(Y * Y, 0) - 0.5 * np.sum((Xb - mu0) ** 2 / s02, 1), -np.inf)
+    lw = lp - lq
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    mean = w @ X
+    cov = (X - mean).T @ ((X - mean) * w[:, None])
+    return mean, cov, 1.0 / float(np.sum(w * w))

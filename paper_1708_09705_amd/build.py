@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libep.so")
 SOURCES = ["api.cpp", "symbolic.cpp", "prior.cpp", "surrogate_api.cpp", "kernels.hip", "surrogate.hip", "maps.hip", "theta.hip",
-           "gmm.hip", "solve_mr.hip", "pitc.cpp", "pitc.hip", "gemm32.hip", "noalloc.hip"]
+           "gmm.hip", "solve_mr.hip", "pitc.cpp", "pitc.hip", "gemm32.hip", "noalloc.hip", "plan.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     "-munsafe-fp-atomics",

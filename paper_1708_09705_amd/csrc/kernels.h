@@ -147,6 +147,11 @@ struct StarsDev {
     double* tvar;
     int32_t* status;         // per star: 0 updated, 1 cavity skip, 2 negative site
     double* dtau;            // per star |delta tau|
+    // processing order of the clique kernels (assembly, cavity): slot i of a
+    // launch (block i / 4, wave i % 4) takes star order[i] (-1: none); NULL
+    // takes star i
+    const int32_t* order;
+    int64_t norder;
 };
 struct GridDev {
     int n;

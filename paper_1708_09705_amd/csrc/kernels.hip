@@ -28,6 +28,15 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// star of launch slot i (block i / 4, wave i % 4), -1 if none
+__device__ __forceinline__ int64_t star_of_slot(const StarsDev& s, int64_t i) {
+    if (s.order) return i < s.norder ? (int64_t)s.order[i] : -1;
+    return i < s.n ? i : -1;
+}
+static unsigned star_blocks(const StarsDev& s) {
+    return (unsigned)(((s.order ? s.norder : s.n) + 3) / 4);
+}
+
 __device__ __forceinline__ int64_t batch_find(const BatchEnt* be, int nbe, int64_t t) {
     int lo = 0, hi = nbe - 1;
     while (lo < hi) {
@@ -1012,8 +1021,8 @@ __global__ __launch_bounds__(256) void k_assemble_stars(StarsDev s, FrontsDev F,
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* sl = (int32_t*)smem + w * cap;
     double* sg = (double*)(smem + ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16) + w * cap;
-    const int64_t star = (int64_t)blockIdx.x * 4 + w;
-    if (star >= s.n) return;
+    const int64_t star = star_of_slot(s, (int64_t)blockIdx.x * 4 + w);
+    if (star < 0) return;
     const double tau = s.tau[star];
     if (tau == 0.0) return;
     const int64_t p0 = s.ptr[star];
@@ -1037,8 +1046,8 @@ __global__ __launch_bounds__(256) void k_assemble_stars(StarsDev s, FrontsDev F,
 
 __global__ void k_assemble_b(StarsDev s, double* b) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t star = (int64_t)blockIdx.x * 4 + w;
-    if (star >= s.n) return;
+    const int64_t star = star_of_slot(s, (int64_t)blockIdx.x * 4 + w);
+    if (star < 0) return;
     const double coef = s.nu[star] - s.tau[star] * s.c[star];
     if (coef == 0.0) return;
     const int64_t p0 = s.ptr[star];
@@ -1049,11 +1058,11 @@ __global__ void k_assemble_b(StarsDev s, double* b) {
 void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int cap) {
     if (s.n <= 0) return;
     size_t sh = ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16 + (size_t)4 * cap * sizeof(double);
-    hipLaunchKernelGGL(k_assemble_stars, dim3((unsigned)((s.n + 3) / 4)), dim3(256), sh, st, s, F, fronts, cap);
+    hipLaunchKernelGGL(k_assemble_stars, dim3(star_blocks(s)), dim3(256), sh, st, s, F, fronts, cap);
 }
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b) {
     if (s.n <= 0) return;
-    hipLaunchKernelGGL(k_assemble_b, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s, b);
+    hipLaunchKernelGGL(k_assemble_b, dim3(star_blocks(s)), dim3(256), 0, st, s, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,8 +1075,8 @@ __global__ __launch_bounds__(256) void k_cavity(StarsDev s, FrontsDev F, const d
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* sl = (int32_t*)smem + w * cap;
     double* sg = (double*)(smem + (size_t)4 * cap * sizeof(int32_t)) + w * cap;
-    const int64_t star = (int64_t)blockIdx.x * 4 + w;
-    const bool active = star < s.n;
+    const int64_t star = star_of_slot(s, (int64_t)blockIdx.x * 4 + w);
+    const bool active = star >= 0;
     int64_t p0 = 0;
     int cnt = 0;
     double mean = 0.0;
@@ -1105,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_cavity(StarsDev s, FrontsDev F, const d
 void launch_cavity(hipStream_t st, StarsDev s, FrontsDev F, const double* fronts, const double* mu, int cap) {
     if (s.n <= 0) return;
     size_t sh = (size_t)4 * cap * (sizeof(int32_t) + sizeof(double));
-    hipLaunchKernelGGL(k_cavity, dim3((unsigned)((s.n + 3) / 4)), dim3(256), sh, st, s, F, fronts, mu, cap);
+    hipLaunchKernelGGL(k_cavity, dim3(star_blocks(s)), dim3(256), sh, st, s, F, fronts, mu, cap);
 }
 
 // ---------------------------------------------------------------------------

@@ -72,7 +72,7 @@ class ep_sweep_stats(ctypes.Structure):
                [(k, ctypes.c_double) for k in ("max_dtau", "max_dmu", "mfma_ms")] + \
                [("mfma_launches", ctypes.c_int64), ("refine_iters", ctypes.c_int32),
                 ("refine_residual", ctypes.c_double), ("surrogate_fallbacks", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4)]
+                ("kernel_ms", ctypes.c_double * 10), ("kernel_launches", ctypes.c_int64 * 10)]
 
 
 class ep_structure_stats(ctypes.Structure):
@@ -80,7 +80,19 @@ class ep_structure_stats(ctypes.Structure):
                 ("n_fronts", ctypes.c_int64), ("n_levels", ctypes.c_int32), ("front_elems", ctypes.c_int64),
                 ("max_front", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("selinv_flops", ctypes.c_double), ("trail_flops", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("front_elems_lower", ctypes.c_int64),
+                ("update_elems", ctypes.c_int64), ("offdiag_elems", ctypes.c_int64), ("x_elems", ctypes.c_int64),
+                ("clique_pairs", ctypes.c_int64)]
+
+
+class ep_plan_stats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_stars", ctypes.c_int64), ("nnz_g", ctypes.c_int64),
+                ("max_support", ctypes.c_int64), ("n_fronts", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("max_front", ctypes.c_int64), ("max_separator", ctypes.c_int64), ("front_elems", ctypes.c_int64),
+                ("front_elems_lower", ctypes.c_int64), ("nnz_L", ctypes.c_int64), ("x_elems", ctypes.c_int64),
+                ("w_elems", ctypes.c_int64), ("factor_flops", ctypes.c_double), ("selinv_flops", ctypes.c_double),
+                ("trail_flops", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("device_bytes_mixed", ctypes.c_int64)]
 
 
 class ep_pitc_stats(ctypes.Structure):
@@ -94,10 +106,11 @@ EXPORTS = ("ep_config_default", "ep_init", "ep_sweep", "ep_posterior_mean", "ep_
            "ep_star_state", "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train",
            "ep_mlp_predict", "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments",
            "ep_extinction_map", "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc")
+           "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc", "ep_plan")
 MLP_NPARAM = 34065
 EP_NOALLOC_MAX_TUPLES = 1 << 20   # ep.h
-KERNEL_KINDS = ("trsm", "inner", "trail", "gemm")   # EP_KK_* order
+KERNEL_KINDS = ("trsm", "inner", "trail", "gemm", "zero", "assemble", "extend", "gather", "cavity",
+                "solve")   # EP_KK_* order
 
 
 class ep_mlp_hyper(ctypes.Structure):
@@ -171,12 +184,13 @@ def load(path: str | None = None):
     L.ep_pitc_info.argtypes = [vp, ctypes.POINTER(ep_pitc_stats)]
     L.ep_pitc_theta.argtypes = [vp, vp, vp]
     L.ep_mlp_predict_noalloc.argtypes = [vp, i64, vp, ctypes.c_double, vp, vp, vp, i32, vp]
+    L.ep_plan.argtypes = [cfgp, i64, vp, ctypes.POINTER(ep_plan_stats)]
     for name in ("ep_init", "ep_sweep", "ep_posterior_mean", "ep_marginal_var", "ep_get_sites",
                  "ep_set_sites", "ep_get_linpoint", "ep_set_linpoint", "ep_star_state",
                  "ep_tilted_moments", "ep_simulate", "ep_structure", "ep_mlp_train", "ep_mlp_predict",
                  "ep_mlp_loss_grad", "ep_mlp_load", "ep_ordering", "ep_density_moments", "ep_extinction_map",
                  "ep_point_predict", "ep_theta", "ep_set_gmm", "ep_pitc_setup", "ep_pitc_sweep",
-                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc"):
+                 "ep_pitc_inducing", "ep_pitc_predict", "ep_pitc_info", "ep_pitc_theta", "ep_mlp_predict_noalloc", "ep_plan"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -372,6 +386,17 @@ def ep_mlp_predict_noalloc(weights, inputs, out3, errest=None, accepted=None, to
     _check(L, L.ep_mlp_predict_noalloc(ptr(weights, "float32", "weights"), n, ptr(inputs, "float64", "inputs"), tol,
                                        ptr(out3, "float64", "out3"), ptr(errest, "float64", "errest"),
                                        ptr(accepted, "int32", "accepted"), device, st))
+
+
+def ep_plan(cfg, xyz, lib=None) -> dict:
+    """Structure, work and memory of a configuration from the host analysis
+    alone (no device)."""
+    L = lib or load()
+    c = cfg if isinstance(cfg, ep_config) else make_config(cfg, lib=L)
+    x = _arr(xyz).reshape(-1, 3)
+    out = ep_plan_stats()
+    _check(L, L.ep_plan(ctypes.byref(c), x.shape[0], _ptr(x), ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in ep_plan_stats._fields_}
 
 
 def ep_mlp_predict(weights, inputs, tol=1e-4, device=0, lib=None):

@@ -87,6 +87,15 @@ PRESETS = {
     3: Workload("cfg3-128cube-1M", n=128, box_pc=8000.0, n_stars=1_000_000, sweeps=20,
                 star_law="disc", d_max_pc=8000.0, noise_law="linear",
                 noise_a=0.02, noise_b=0.03, precision="mixed", seed_id=3),
+    4: Workload("cfg4-128cube-1M-surrogate", n=128, box_pc=8000.0, n_stars=1_000_000, sweeps=20,
+                star_law="disc", d_max_pc=8000.0, noise_law="linear",
+                noise_a=0.02, noise_b=0.03, precision="mixed", moments="surrogate", seed_id=4),
+    # positions from the disc law; the G < 17 magnitude cut needs the
+    # extinction along each sightline and is applied when observations are
+    # simulated, not here
+    5: Workload("cfg5-256cube-10M", n=256, box_pc=8000.0, n_stars=10_000_000, sweeps=10,
+                star_law="disc", d_max_pc=8000.0, noise_law="uniform", noise_a=0.03, noise_b=0.3,
+                support_pc=120.0, precision="mixed", moments="surrogate", seed_id=5),
 }
 
 

@@ -41,34 +41,39 @@ def test_mixed_against_oracle(n, L, stars, leaf):
 
 
 def test_mixed_config2_against_fp64_gpu():
+    """64^3 / 100k: the FP64 run's state after two sweeps (sites and
+    linearisation point) loaded into a mixed-precision context, so the
+    comparison is of the same q(f) computed in the two precisions."""
     E = _E()
     w = preset(2)
     raw = draw(w)
     cfg = E.make_config(w.ep_fields(), leaf_size=512)
     f, A = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
-    out = {}
-    for prec in ("fp64", "mixed"):
-        g = E.EP(E.make_config(w.ep_fields(), leaf_size=512, precision=prec), raw["xyz"], A, raw["sigma"])
-        for _ in range(2):
-            st = g.sweep()
-        out[prec] = (g.posterior_mean(), g.marginal_var(), g.sites()[0], st)
-        g.close()
-    em = relerr(out["mixed"][0], out["fp64"][0])
-    ev = relerr(out["mixed"][1], out["fp64"][1])
-    et = relerr(out["mixed"][2], out["fp64"][2])
-    print(f"config 2 mixed vs fp64: sites {et:.2e} mean {em:.2e} var {ev:.2e} "
-          f"refine {out['mixed'][3]['refine_iters']} rounds to {out['mixed'][3]['refine_residual']:.1e}", flush=True)
-    # The refined mean meets the 1e-4 bound.  The marginal variances do not
-    # at this size: the FP32 factor's rounding, amplified by the conditioning
-    # of the large separator fronts, leaves ~1e-3 (measured 1.3e-3; keeping
-    # the top five levels in FP64 still leaves 3e-4).  Pinned here so a
-    # regression shows, and reported as a shortfall.
-    assert out["mixed"][3]["refine_residual"] <= 1e-12
+    g = E.EP(E.make_config(w.ep_fields(), leaf_size=512), raw["xyz"], A, raw["sigma"])
+    for _ in range(2):
+        g.sweep()
+    sites, lin = g.sites(), g.linpoint()
+    m64, v64 = g.posterior_mean(), g.marginal_var()
+    g.close()
+    g = E.EP(E.make_config(w.ep_fields(), leaf_size=512, precision="mixed"), raw["xyz"], A, raw["sigma"])
+    g.set_sites(*sites)
+    g.set_linpoint(lin)
+    m32, v32 = g.posterior_mean(), g.marginal_var()
+    st = g.sweep()
+    g.close()
+    em, ev = relerr(m32, m64), relerr(v32, v64)
+    rms_v = float(np.sqrt(np.mean(((v32 - v64) / v64) ** 2)))
+    rms_m = float(np.sqrt(np.mean(((m32 - m64) / m64) ** 2)))
+    print(f"config 2 mixed vs fp64 on the same state: mean {em:.2e} var {ev:.2e} (rms {rms_m:.1e}, {rms_v:.1e}); "
+          f"refine {st['refine_iters']} rounds to {st['refine_residual']:.1e}", flush=True)
+    # The refined mean meets the 1e-4 bound.  The marginal variances do not,
+    # and no split of the dissection levels between FP64 and FP32 makes them:
+    # measured on a 12-sweep state of this workload, every level split leaves 3.0e-4 to 7.1e-4 at
+    # the worst node (the selected inversion carries the factor's FP32
+    # rounding down the tree, and an FP32 leaf alone leaves 3.0e-4), so the
+    # mixed form is not a 1e-4 result.  The bound asserted is the measured
+    # level, so that a regression shows.
+    assert st["refine_residual"] <= 1e-12
     assert em < 1e-4
-    assert ev < 1e-2
-    # Root-mean-square over the nodes the relative errors are far smaller
-    # (measured: mean ~2e-8, variance ~6e-6): the worst nodes are few.
-    rms_v = float(np.sqrt(np.mean(((out["mixed"][1] - out["fp64"][1]) / out["fp64"][1]) ** 2)))
-    rms_m = float(np.sqrt(np.mean(((out["mixed"][0] - out["fp64"][0]) / out["fp64"][0]) ** 2)))
-    print(f"rms relative: mean {rms_m:.2e} var {rms_v:.2e}", flush=True)
+    assert ev < 1.5e-3
     assert rms_m < 1e-6 and rms_v < 1e-4

@@ -74,8 +74,42 @@ def test_gate_accepts_only_moments_within_tolerance(trained):
     assert np.max(np.abs(a[:, 0] - y[:, 0])) < 1e-4
     assert np.max(np.abs(a[:, 1] - y[:, 1]) / scale) < 1e-4
     assert np.max(np.abs(a[:, 2] / y[:, 2] - 1)) < 1e-4
-    # the baseline-centred gate is just as exact where it accepts
+    # the baseline-centred gate is just as exact where it accepts, and the
+    # network sends fewer tuples to the quadrature
     assert acc0.mean() > 0.5
+    assert acc.mean() > acc0.mean()
+
+
+def test_network_gains_on_held_out_config2_tuples():
+    """What the trained network (the shipped weights, trained on config-2
+    EP runs of other seeds) gains over the same gate centred at the analytic
+    baseline: first-sweep cavities of the 64^3 / 100k workload drawn with a
+    seed no training run used, observations from the oracle's forward model."""
+    import os
+    E = _E()
+    from synth import draw, preset
+    w = preset(2, seed_id=22, n_stars=20000)
+    cfg = w.ep_fields()
+    raw = draw(w)
+    vec = epo.Vecchia(cfg)
+    f_true = vec.draw(cfg["prior_mean"], raw["xi"])
+    sl = epo.Sightlines(cfg, raw["xyz"])
+    _, lnA_true, _ = sl.linearise(f_true)
+    A = np.exp(lnA_true) + raw["sigma"] * raw["eps"]
+    gval, lnA, c = sl.linearise(np.full(sl.grid.N, cfg["prior_mean"]))
+    v = vec.prior_quadform(sl.ptr, sl.nodes, gval)
+    X = np.stack([lnA, v, A, raw["sigma"]], axis=1)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    wts = np.load(os.path.join(root, "paper_1708_09705_amd", "surrogate_64cube.npy"))
+    out, err, acc = E.ep_mlp_predict(wts, X, tol=1e-4)
+    _, _, acc0 = E.ep_mlp_predict(None, X, tol=1e-4)
+    print(f"held-out config-2 tuples: fallbacks {int((~acc).sum())} with the network, "
+          f"{int((~acc0).sum())} centred at the baseline, of {len(X)}", flush=True)
+    assert (~acc).sum() < (~acc0).sum()
+    # accepted moments agree with the oracle's adaptive quadrature
+    lz, m, vq = epo.tilted(0, lnA[acc], v[acc], A[acc], raw["sigma"][acc])
+    scale = np.maximum(np.abs(m), np.sqrt(vq))
+    assert np.max(np.abs(out[acc, 1] - m) / scale) < 1e-4 and np.max(np.abs(out[acc, 2] / vq - 1)) < 1e-4
 
 
 
@@ -93,7 +127,10 @@ def test_ep_with_surrogate_moments_tracks_quadrature(trained):
     em = relerr(s.posterior_mean(), q.posterior_mean())
     ev = relerr(s.marginal_var(), q.marginal_var())
     print(f"surrogate vs quadrature EP: mean {em:.2e} var {ev:.2e}", flush=True)
-    assert em < 1e-3 and ev < 1e-2
+    # measured: ~2e-9 (mean), ~3e-8 (variance): the gate's 1e-4 acceptance
+    # tolerance bounds each accepted star's moments, and the sites it moves
+    # shift q far less
+    assert em < 1e-7 and ev < 1e-6
 
 
 def test_surrogate_mode_without_weights_is_a_state_error():
