@@ -74,3 +74,29 @@ def test_noalloc_size_limit_rejected_before_device_work():
     rc = L.ep_mlp_predict_noalloc(None, 10, None, 1e-4, None, None, None, 0, None)
     assert rc == -1
     assert L.ep_mlp_predict_noalloc(None, 0, None, 1e-4, None, None, None, 0, None) == 0
+
+
+def test_plan_without_a_device():
+    """ep_plan runs the host analysis alone: its sightline supports are the
+    oracle's (integer results, compared exactly), its layout figures are
+    consistent, and bad inputs are refused."""
+    E, L = _lib()
+    from oracle import epo
+    from synth import draw, preset
+    w = preset(1)
+    cfg = w.ep_fields()
+    raw = draw(w, field=False)
+    p = E.ep_plan(cfg, raw["xyz"])
+    sl = epo.Sightlines(cfg, raw["xyz"])
+    assert p["n_nodes"] == w.n ** 3 and p["n_stars"] == w.n_stars
+    assert p["nnz_g"] == len(sl.nodes) and p["max_support"] == int(np.max(np.diff(sl.ptr)))
+    assert 0 < p["nnz_L"] <= p["front_elems_lower"] <= p["front_elems"]
+    assert p["max_separator"] <= p["max_front"] and p["n_levels"] >= 1
+    assert 0 < p["trail_flops"] <= p["factor_flops"] < p["selinv_flops"]
+    assert p["device_bytes"] > 8 * p["front_elems"] and p["device_bytes_mixed"] > p["device_bytes"]
+    # the dense limit: one star-free 4^3 grid has one front holding every node
+    q = E.ep_plan(dict(cfg, n=4, box_pc=200.0, observer_pc=(100.0, 0.0, 100.0)), np.zeros((0, 3)))
+    assert q["n_fronts"] == 1 and q["nnz_L"] == 64 * 65 // 2
+    with pytest.raises(E.EPError) as ei:
+        E.ep_plan(cfg, np.array([[10.0, 20.0, 5000.0]]))
+    assert ei.value.code == -1
