@@ -21,7 +21,7 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *srcs, "-lpthread"]
+    cmd = ["hipcc", *FLAGS, "-o", tmp, *srcs, "-lpthread", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -16,6 +16,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/ep.h"
 #include "kernels.h"
 #include "pitc.h"
@@ -25,6 +27,16 @@
 #include "symbolic.h"
 
 using namespace ep;
+
+namespace {
+// roctx range over a host-side scope (visible with rocprofv3 --marker-trace)
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 static thread_local std::string g_tls_err = "no error";
 namespace ep {
@@ -1346,11 +1358,20 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         ~EvGuard() { for (int i = 0; i < 8; i++) (void)hipEventDestroy(e[i]); }
     } guard{ev};
     ctx->kt_used = 0;
-    TRY(run_factor(ctx, ev));
-    TRY(run_solve(ctx));
-    if (ctx->M) TRY(border_solve(ctx));
+    {
+        Range r("ep: linearise, assemble, factor");
+        TRY(run_factor(ctx, ev));
+    }
+    {
+        Range r("ep: solve");
+        TRY(run_solve(ctx));
+        if (ctx->M) TRY(border_solve(ctx));
+    }
     HIPCHK(hipEventRecord(ev[4], st));
-    enqueue_selinv(ctx);
+    {
+        Range r("ep: selected inversion");
+        enqueue_selinv(ctx);
+    }
     HIPCHK(hipEventRecord(ev[5], st));
     // non-finite posterior mean -> NUMERIC, nothing changed (with an
     // inferred mean: the mean of f = mhat + J (mu_phi - phihat) + mu_delta)
@@ -1368,6 +1389,7 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
         dmu = std::max(dmu, std::fabs(mu[i] - fh[i]));
     }
     // per-star phase: cavity -> tilted -> site update
+    Range star_range("ep: cavity, tilted moments, site update");
     HIPCHK(hipMemcpyAsync(ctx->d_tau_bak, ctx->d_tau, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(ctx->d_nu_bak, ctx->d_nu, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(ev[6], st));
@@ -1641,6 +1663,7 @@ int ep_init(const ep_config* cfg, int64_t n_stars, const double* xyz, const doub
 int ep_sweep(ep_ctx* ctx, ep_sweep_stats* stats) {
     if (!ctx) { g_tls_err = "ctx is NULL"; return EP_ERR_INVALID_ARG; }
     HIPCHK(hipSetDevice(ctx->cfg.device));
+    Range r("ep_sweep");
     return sweep_impl(ctx, stats);
 }
 
