@@ -461,6 +461,10 @@ int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *o
  * prediction conditions on).  Plans and allocates; replaces an earlier set-up
  * and its sites.  Errors: INVALID_ARG (ranges, empty block, duplicate
  * inducing node, wrong likelihood), OOM/DEVICE.
+ * With the mean parameters the pass takes the context's mean linearised at
+ * the hyperprior mean; once grid sweeps (ep_sweep) have moved that
+ * linearisation (the Gaussian mode re-linearises the mean unless relinearize
+ * = 0), ep_pitc_setup and the calls below return STATE.
  * ep_pitc_sweep: one parallel pass over the sub-catalogues from the same
  * q(u); sites damped by 'damping' in (0, 1] in natural parameters (the first
  * sweep starts from zero sites).  lnZ (may be NULL): the PITC log marginal

@@ -2226,6 +2226,21 @@ static int pitc_status(ep_ctx* ctx, int rc, const std::string& err) {
     return rc;
 }
 
+// The PITC pass with the mean parameters reads the context's mean and border
+// rows linearised at the hyperprior mean (its oracle's reading).  Grid sweeps
+// in the Gaussian mode move that linearisation; then the pass refuses.
+static int pitc_mean_at_prior(ep_ctx* ctx, const char* who) {
+    for (int j = 0; j < ctx->M; j++)
+        if (ctx->phihat[j] != ctx->mu0[j]) {
+            ctx->err = std::string(who) +
+                       ": the mean parameters' linearisation has moved from the hyperprior mean (grid sweeps "
+                       "re-linearise it); the PITC pass linearises at the hyperprior mean: use a fresh context or "
+                       "relinearize = 0";
+            return EP_ERR_STATE;
+        }
+    return EP_OK;
+}
+
 int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int64_t n_inducing,
                   const int32_t* inducing, const int32_t* node_block) {
     if (!ctx) {
@@ -2240,6 +2255,7 @@ int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int6
         ctx->err = "ep_pitc_setup: bad arguments";
         return EP_ERR_INVALID_ARG;
     }
+    TRY(pitc_mean_at_prior(ctx, "ep_pitc_setup"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::vector<int32_t> hb, hu, hn;
     const bool dev = ctx->cfg.pointers_on_device != 0;
@@ -2263,6 +2279,7 @@ int ep_pitc_sweep(ep_ctx* ctx, double damping, double* lnZ) {
         if (ctx) ctx->err = "ep_pitc_sweep: no ep_pitc_setup";
         return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
     }
+    TRY(pitc_mean_at_prior(ctx, "ep_pitc_sweep"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     double lz = 0;
@@ -2276,6 +2293,7 @@ int ep_pitc_inducing(ep_ctx* ctx, double* mean, double* cov) {
         if (ctx) ctx->err = "ep_pitc_inducing: no ep_pitc_setup";
         return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
     }
+    TRY(pitc_mean_at_prior(ctx, "ep_pitc_inducing"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     return pitc_status(ctx, pitc_inducing(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
@@ -2286,6 +2304,7 @@ int ep_pitc_theta(ep_ctx* ctx, double* mean, double* cov) {
         if (ctx) ctx->err = "ep_pitc_theta: no ep_pitc_setup";
         return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
     }
+    TRY(pitc_mean_at_prior(ctx, "ep_pitc_theta"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     return pitc_status(ctx, pitc_theta(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
@@ -2296,6 +2315,7 @@ int ep_pitc_predict(ep_ctx* ctx, double* mean, double* var) {
         if (ctx) ctx->err = "ep_pitc_predict: no ep_pitc_setup";
         return ctx ? EP_ERR_STATE : EP_ERR_INVALID_ARG;
     }
+    TRY(pitc_mean_at_prior(ctx, "ep_pitc_predict"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     return pitc_status(ctx, pitc_predict(ctx->pitc, pitc_borrow(ctx), mean, var, kind_out(ctx), err), err);

@@ -271,6 +271,21 @@ def test_pitc_theta_state_errors():
         g.pitc_theta()                                  # constant mean
     assert ei.value.code == -5
     g.close()
+    # a grid sweep re-linearises the mean (Gaussian mode): the PITC pass,
+    # linearised at the hyperprior mean, refuses; with relinearize = 0 it runs
+    g = E.EP(dict(cfg, leaf_size=48, mean_fn="disc_bump"), raw["xyz"], a, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    g.sweep()
+    for call in (lambda: g.pitc_sweep(1.0), lambda: g.pitc_setup(blocks, u, nb)):
+        with pytest.raises(E.EPError) as ei:
+            call()
+        assert ei.value.code == -5
+    g.close()
+    g = E.EP(dict(cfg, leaf_size=48, mean_fn="disc_bump", relinearize=0), raw["xyz"], a, raw["sigma"])
+    g.sweep()
+    g.pitc_setup(blocks, u, nb)
+    g.pitc_sweep(1.0)
+    g.close()
 
 
 def test_pitc_theta_full_size_properties():
