@@ -187,9 +187,15 @@ __device__ __forceinline__ int64_t xcd_task(int64_t n) {
 // inverses, selected inversion).  One block of eight waves per CU, two waves
 // per SIMD; wave w owns the 64 x 64 quadrant (row quarter w >> 1, column
 // half w & 1) as 4 x 4 v_mfma_f64_16x16x4f64 blocks.  K advances in slabs of
-// 16 through two LDS buffers and two register stages: a slab's global loads
-// (16-byte pairs) are issued two MFMA phases before they are stored to LDS;
-// one barrier per slab.
+// 16 through a ring of three LDS buffers and one register stage.  Within
+// slab h: MFMA groups 0 and 1 (k 0-7), then slab h + 1 goes from registers
+// to LDS and slab h + 2's global loads (16-byte pairs) are issued, then the
+// slab's one barrier, then groups 2 and 3.  Each group's operands are read
+// from LDS while the previous group's MFMAs run, and group 0 of slab h + 1
+// (visible after the barrier) while group 3 of slab h runs, so the matrix
+// units do not wait on LDS at the barrier.  Three buffers make the middle
+// barrier enough: a buffer is rewritten two slabs after it was last read,
+// with a barrier in between.
 // ---------------------------------------------------------------------------
 constexpr int BM = 256;              // output rows per block (op(A) side)
 constexpr int BN = 128;              // output columns per block (op(B) side)
@@ -240,9 +246,9 @@ __device__ __forceinline__ void slab_load(double* r, const T* M, int ld, bool kc
     }
 }
 
-// Write a slab to LDS as s[k][i] (row stride LD), scaled by sgn.
+// Write a slab to LDS as s[k][i] (row stride LD).
 template <int R, int LD>
-__device__ __forceinline__ void slab_store(const double* r, double* s, bool kc, double sgn) {
+__device__ __forceinline__ void slab_store(const double* r, double* s, bool kc) {
     constexpr int NP = R * KH / 2 / GT_THREADS;
     const int t = threadIdx.x;
     if (!kc) {
@@ -250,105 +256,115 @@ __device__ __forceinline__ void slab_store(const double* r, double* s, bool kc, 
         constexpr int KS = GT_THREADS / PR;
         const int p = t % PR, k0 = t / PR;
 #pragma unroll
-        for (int q = 0; q < NP; q++) {
-            s[(k0 + KS * q) * LD + 2 * p] = sgn * r[2 * q];
-            s[(k0 + KS * q) * LD + 2 * p + 1] = sgn * r[2 * q + 1];
-        }
+        for (int q = 0; q < NP; q++) *(double2*)&s[(k0 + KS * q) * LD + 2 * p] = double2{r[2 * q], r[2 * q + 1]};
     } else {
         const int kp = t & 7, i0 = t >> 3;
 #pragma unroll
         for (int q = 0; q < NP; q++) {
-            s[(2 * kp) * LD + i0 + 64 * q] = sgn * r[2 * q];
-            s[(2 * kp + 1) * LD + i0 + 64 * q] = sgn * r[2 * q + 1];
+            s[(2 * kp) * LD + i0 + 64 * q] = r[2 * q];
+            s[(2 * kp + 1) * LD + i0 + 64 * q] = r[2 * q + 1];
         }
     }
 }
 
-// acc (this wave's quadrant) += sum over the slab's k of sA[k][i] sB[k][j]
-__device__ __forceinline__ void slab_mma(d4 acc[4][4], const double* sA, const double* sB) {
+// This wave's operands of group g (k = 4g .. 4g + 3) of a slab in LDS.
+__device__ __forceinline__ void group_read(double a[4], double b[4], const double* sA, const double* sB, int g) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
     const int li = lane & 15, lk = lane >> 4;
+    const double* ra = sA + (4 * g + lk) * LDA2 + wr + li;
+    const double* rb = sB + (4 * g + lk) * LDB2 + wc + li;
 #pragma unroll
-    for (int kk = 0; kk < KH; kk += 4) {
-        const double* ra = sA + (kk + lk) * LDA2 + wr + li;
-        const double* rb = sB + (kk + lk) * LDB2 + wc + li;
-        double a[4], b[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            a[q] = ra[16 * q];
-            b[q] = rb[16 * q];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; x++)
-#pragma unroll
-            for (int y = 0; y < 4; y++)
-                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    for (int q = 0; q < 4; q++) {
+        a[q] = ra[16 * q];
+        b[q] = rb[16 * q];
     }
 }
 
-// One segment: acc += sum over its K of op(A) op(B).  smem holds two
-// buffers of (A slab, B slab); two register stages hold the next two
-// slabs.  Ends with a barrier after the last read of smem.
-template <typename TA>
-__device__ __forceinline__ void seg_run(d4 acc[4][4], double* smem, const TA* A, const double* B, const GemmSeg& S,
-                                        bool active) {
-    const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
-    const double sgn = (S.flags & 4) ? -1.0 : 1.0;
+// acc (this wave's quadrant) += one group's rank-4 update
+__device__ __forceinline__ void group_mma(d4 acc[4][4], const double a[4], const double b[4]) {
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+}
+
+__device__ __forceinline__ void acc_negate(d4 acc[4][4]) {
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) acc[x][y] = -acc[x][y];
+}
+
+// One segment: acc += sum over its K of op(A) op(B) (acc -= with the negate
+// flag: acc is negated before and after, which rounds exactly as adding the
+// negated product).  ACT: this wave's quadrant is present; waves without one
+// load, store and wait like the others but issue no MFMA and read no LDS.
+// All 512 threads take every barrier; ends with a barrier after the last
+// read of smem.
+template <bool ACT, typename TA>
+__device__ __forceinline__ void seg_run(d4 acc[4][4], double* smem, const TA* A, const double* B, const GemmSeg& S) {
+    const int sflags = S.flags, lda = S.lda, ldb = S.ldb;
     // op(A)(i, k): transposed A has k contiguous; op(B)(k, j): plain B has k contiguous
-    const bool kca = ta, kcb = !tb;
+    const bool kca = sflags & 1, kcb = !(sflags & 2);
+    const bool neg = (sflags & 4) != 0;
     const int nh = (TS / KH) * S.nk;
     const int64_t ha = S.sa / (TS / KH), hb = S.sb / (TS / KH);
     if (nh <= 0) return;
-    double* U0 = smem;
-    double* U1 = smem + SLA + SLB;
-    double a0[BM * KH / GT_THREADS], b0[BN * KH / GT_THREADS];
-    double a1[BM * KH / GT_THREADS], b1[BN * KH / GT_THREADS];
-    slab_load<BM>(a0, A, S.lda, kca);
-    slab_load<BN>(b0, B, S.ldb, kcb);
+    if (ACT && neg) acc_negate(acc);
+    double ra[BM * KH / GT_THREADS], rb[BN * KH / GT_THREADS];
+    slab_load<BM>(ra, A, lda, kca);
+    slab_load<BN>(rb, B, ldb, kcb);
+    slab_store<BM, LDA2>(ra, smem, kca);
+    slab_store<BN, LDB2>(rb, smem + SLA, kcb);
     if (nh > 1) {
-        slab_load<BM>(a1, A + ha, S.lda, kca);
-        slab_load<BN>(b1, B + hb, S.ldb, kcb);
-    }
-    slab_store<BM, LDA2>(a0, U0, kca, sgn);
-    slab_store<BN, LDB2>(b0, U0 + SLA, kcb, 1.0);
-    if (nh > 2) {
-        slab_load<BM>(a0, A + 2 * ha, S.lda, kca);
-        slab_load<BN>(b0, B + 2 * hb, S.ldb, kcb);
+        slab_load<BM>(ra, A + ha, lda, kca);
+        slab_load<BN>(rb, B + hb, ldb, kcb);
     }
     __syncthreads();
-    for (int h = 0; h < nh; h += 2) {
-        // slab h in U0; slab h + 1 in stage 1, slab h + 2 in stage 0
-        if (active) slab_mma(acc, U0, U0 + SLA);
+    // x: operands of groups 0 and 2, y: of groups 1 and 3
+    double xa[4], xb[4], ya[4], yb[4];
+    if (ACT) group_read(xa, xb, smem, smem + SLA, 0);
+    double* cur = smem;
+    double* nxt = smem + (SLA + SLB);
+    double* spare = smem + 2 * (SLA + SLB);
+    for (int h = 0; h < nh; h++) {
+        if (ACT) {
+            group_read(ya, yb, cur, cur + SLA, 1);
+            group_mma(acc, xa, xb);
+            group_read(xa, xb, cur, cur + SLA, 2);
+            group_mma(acc, ya, yb);
+        }
         if (h + 1 < nh) {
-            slab_store<BM, LDA2>(a1, U1, kca, sgn);
-            slab_store<BN, LDB2>(b1, U1 + SLA, kcb, 1.0);
-            if (h + 3 < nh) {
-                slab_load<BM>(a1, A + (h + 3) * ha, S.lda, kca);
-                slab_load<BN>(b1, B + (h + 3) * hb, S.ldb, kcb);
+            slab_store<BM, LDA2>(ra, nxt, kca);
+            slab_store<BN, LDB2>(rb, nxt + SLA, kcb);
+            if (h + 2 < nh) {
+                slab_load<BM>(ra, A + (h + 2) * ha, lda, kca);
+                slab_load<BN>(rb, B + (h + 2) * hb, ldb, kcb);
             }
         }
         __syncthreads();
-        if (h + 1 >= nh) break;
-        // slab h + 1 in U1; slab h + 2 in stage 0, slab h + 3 in stage 1
-        if (active) slab_mma(acc, U1, U1 + SLA);
-        if (h + 2 < nh) {
-            slab_store<BM, LDA2>(a0, U0, kca, sgn);
-            slab_store<BN, LDB2>(b0, U0 + SLA, kcb, 1.0);
-            if (h + 4 < nh) {
-                slab_load<BM>(a0, A + (h + 4) * ha, S.lda, kca);
-                slab_load<BN>(b0, B + (h + 4) * hb, S.ldb, kcb);
-            }
+        if (ACT) {
+            group_read(ya, yb, cur, cur + SLA, 3);
+            group_mma(acc, xa, xb);
+            if (h + 1 < nh) group_read(xa, xb, nxt, nxt + SLA, 0);
+            group_mma(acc, ya, yb);
         }
-        __syncthreads();
+        double* t = cur;
+        cur = nxt;
+        nxt = spare;
+        spare = t;
     }
+    // the last slab's buffer is the next segment's first
+    __syncthreads();
+    if (ACT && neg) acc_negate(acc);
 }
 
 // A32: the launch's tasks have one segment whose A operand is in the FP32
 // copy of the factor (mixed precision), upcast on load; B is FP64.
 template <bool A32>
 __global__ __launch_bounds__(GT_THREADS) void k_gemm_tasks(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
-    __shared__ double smem[2 * (SLA + SLB)];
+    __shared__ double smem[3 * (SLA + SLB)];
     const int64_t t = xcd_task(n);
     if (t >= n) return;
     const GemmTask& T = tasks[t];
@@ -365,15 +381,19 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemm_tasks(const GemmTask* __res
         for (int y = 0; y < 4; y++) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     if (A32) {
         const GemmSeg& S = T.s[0];
-        seg_run(acc, smem, bufs.F32 + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S, mine);
+        const float* A = bufs.F32 + S.a;
+        const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
+        if (mine) seg_run<true>(acc, smem, A, B, S);
+        else seg_run<false>(acc, smem, A, B, S);
     } else {
         const int nseg = (T.flags >> 4) & 3;
-#pragma unroll
         for (int q = 0; q < 2; q++) {
             if (q >= nseg) break;
             const GemmSeg& S = T.s[q];
-            seg_run(acc, smem, buf_of(bufs, (S.flags >> 8) & 3) + S.a, buf_of(bufs, (S.flags >> 10) & 3) + S.b, S,
-                    mine);
+            const double* A = buf_of(bufs, (S.flags >> 8) & 3) + S.a;
+            const double* B = buf_of(bufs, (S.flags >> 10) & 3) + S.b;
+            if (mine) seg_run<true>(acc, smem, A, B, S);
+            else seg_run<false>(acc, smem, A, B, S);
         }
     }
     if (!mine) return;
