@@ -118,6 +118,14 @@ typedef struct ep_config {
                                   with DISC_BUMP draws around m(x; theta_prior). */
     double sun_radius_pc;      /* R0 (default 8000) */
     double bump_width_pc;      /* w, the bump's fixed standard deviation (default 400) */
+    /* linearisation step r in (0, 1] (default 1): after a sweep the
+     * linearisation point moves the fraction r of the way to the posterior
+     * mean, fhat <- fhat + r (mu - fhat) (with DISC_BUMP the same step for
+     * deltahat and phihat).  r = 1 puts it at the mean; r < 1 is a damped
+     * Gauss-Newton step with the same fixed points, for fields whose full
+     * steps settle into a 2-cycle.  Extinction and GMM likelihoods with
+     * relinearize = 1 only. */
+    double relin_step;
 } ep_config;
 
 /* Kinds of timed kernel launches (ep_sweep_stats.kernel_ms, with

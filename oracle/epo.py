@@ -292,7 +292,8 @@ class DenseEP:
       2. Q = Q0 + sum tau_n g_n g_n^T,  b = Q0 m0 1 + sum (nu_n - tau_n c_n) g_n;
       3. mu = Q^{-1} b,  Sigma = Q^{-1};
       4. for every star, from the same q: cavity, tilted moments, new site;
-      5. fhat = mu.
+      5. fhat = mu, or with a linearisation step r < 1 (a damped
+         Gauss-Newton step, same fixed points) fhat <- (1 - r) fhat + r mu.
     """
 
     def __init__(self, cfg: dict, xyz, A_obs, sigma, sightlines: Sightlines | None = None,
@@ -311,6 +312,7 @@ class DenseEP:
         self.m0 = float(cfg["prior_mean"])
         self.fhat = np.full(self.grid.N, self.m0)
         self.damping = float(cfg.get("damping", 1.0))
+        self.relin_step = float(cfg.get("relin_step", 1.0))
         self.vfloor = float(cfg.get("cavity_var_floor", 0.0))
         self.Q0 = self.vec.Q0_dense()
         self.b0 = self.Q0 @ np.full(self.grid.N, self.m0)
@@ -355,11 +357,17 @@ class DenseEP:
         self.nu = np.where(good, (1 - d) * self.nu + d * nu_new, self.nu)
         dmu = float(np.max(np.abs(mu - self.fhat)))
         if self.relin:
-            self.fhat = mu
+            self.relinearise(mu)
         return dict(updated=int(good.sum()), skipped_cavity=int((~ok).sum()),
                     skipped_negsite=int((ok & ~good).sum()),
                     max_dtau=float(np.max(np.abs(self.tau - old_tau))), max_dmu=dmu,
                     cav_mu=mu_c, cav_var=v_c, lnZ=lnZ, tilted_mean=mh, tilted_var=vh)
+
+    def relinearise(self, mu):
+        """Step 5: move the linearisation point to mu, or the fraction r of
+        the way there."""
+        r = self.relin_step
+        self.fhat = mu.copy() if r == 1.0 else (1.0 - r) * self.fhat + r * mu
 
     def posterior_mean(self) -> np.ndarray:
         return self.posterior()[0]

@@ -209,7 +209,7 @@ class DenseEPGMM(DenseEP):
         self.nu = np.where(good, (1 - d) * self.nu + d * nu_new, self.nu)
         dmu = float(np.max(np.abs(mu - self.fhat)))
         if self.relin:
-            self.fhat = mu
+            self.relinearise(mu)
         return dict(updated=int(good.sum()), skipped_cavity=int((~ok).sum()),
                     skipped_negsite=int((ok & ~good).sum()), max_dtau=float(np.max(np.abs(self.tau - old_tau))),
                     max_dmu=dmu, cav_mu=mu_c, cav_var=v_c, lnZ=lnZ, tilted_mean=mh, tilted_var=vh)

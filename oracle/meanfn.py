@@ -27,7 +27,8 @@ h_n = J^T g_n and c'_n = c_n + g_n.mhat - h_n.phihat.  The posterior of
 (delta, phi) is then Gaussian with precision
     [[Q0 + G^T T G, G^T T H], [H^T T G, S0^{-1} + H^T T H]]
 and the cavities, tilted moments and site updates are those of the
-fixed-mean EP.  After the sweep deltahat, phihat <- the posterior means.
+fixed-mean EP.  After the sweep deltahat, phihat <- the posterior means
+(with a linearisation step r < 1: move the fraction r of the way there).
 """
 from __future__ import annotations
 
@@ -175,9 +176,19 @@ class DenseEPTheta(DenseEP):
         self.nu = np.where(good, (1 - d) * self.nu + d * nu_new, self.nu)
         N = self.grid.N
         if self.relin:
-            self.phihat = mu[N:].copy()
+            # deltahat = fhat - m(phihat) and phihat move the fraction r of the
+            # way to the posterior means (r = 1: onto them), then
+            # fhat = m(phihat) + deltahat
+            r = self.relin_step
+            if r == 1.0:
+                self.phihat = mu[N:].copy()
+                dhat = mu[:N]
+            else:
+                mold, _ = self.mean(self.phihat)
+                dhat = (1.0 - r) * (self.fhat - mold) + r * mu[:N]
+                self.phihat = (1.0 - r) * self.phihat + r * mu[N:]
             mnew, _ = self.mean(self.phihat)
-            self.fhat = mnew + mu[:N]
+            self.fhat = mnew + dhat
         elif self.relin_mean:
             # Gaussian mode: a damped Gauss-Newton step of the mean's
             # linearisation point (full steps can cycle when the bump is

@@ -623,6 +623,7 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
     }
     if (!(c->los_step_pc > 0)) { err = "los_step_pc must be > 0"; return EP_ERR_INVALID_ARG; }
     if (!(c->damping > 0 && c->damping <= 1)) { err = "damping must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
+    if (!(c->relin_step > 0 && c->relin_step <= 1)) { err = "relin_step must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
     if (c->likelihood != EP_LIK_EXTINCTION && c->likelihood != EP_LIK_GAUSS_LINEAR && c->likelihood != EP_LIK_GMM) {
         err = "unknown likelihood";
         return EP_ERR_INVALID_ARG;
@@ -1441,13 +1442,26 @@ static int sweep_impl(ep_ctx* ctx, ep_sweep_stats* stats) {
             return EP_ERR_NUMERIC;
         }
     if (!frozen(ctx)) {
+        const double r = ctx->cfg.relin_step;
         if (ctx->M) {
-            // relinearise the mean at the posterior mean of phi: fhat = m(mu_phi) + mu_delta
-            for (int j = 0; j < NTHETA; j++) ctx->phihat[j] = ctx->border.mu_phi[j];
-            enqueue_mean(ctx);
-            launch_sum2(st, ctx->d_mhat, ctx->d_mu, ctx->d_fhat, N);
-        } else {
+            // relinearise: deltahat <- (1 - r) deltahat + r mu_delta (deltahat =
+            // fhat - m(phihat)), phihat <- (1 - r) phihat + r mu_phi, then
+            // fhat = m(phihat) + deltahat; r = 1: fhat = m(mu_phi) + mu_delta
+            if (r == 1.0) {
+                for (int j = 0; j < NTHETA; j++) ctx->phihat[j] = ctx->border.mu_phi[j];
+                enqueue_mean(ctx);
+                launch_sum2(st, ctx->d_mhat, ctx->d_mu, ctx->d_fhat, N);
+            } else {
+                launch_relin_step(st, ctx->d_fhat, ctx->d_mhat, ctx->d_mu, r, ctx->d_t, N);
+                for (int j = 0; j < NTHETA; j++)
+                    ctx->phihat[j] = (1.0 - r) * ctx->phihat[j] + r * ctx->border.mu_phi[j];
+                enqueue_mean(ctx);
+                launch_sum2(st, ctx->d_mhat, ctx->d_t, ctx->d_fhat, N);
+            }
+        } else if (r == 1.0) {
             HIPCHK(hipMemcpyAsync(ctx->d_fhat, ctx->d_mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        } else {
+            launch_relin_step(st, ctx->d_fhat, nullptr, ctx->d_mu, r, ctx->d_fhat, N);
         }
     } else if (ctx->M && ctx->cfg.relinearize) {
         // Gaussian mode: the sightlines stay at the prior mean (the observation
@@ -1608,6 +1622,7 @@ void ep_config_default(ep_config* c) {
     c->damping = 1.0;
     c->cavity_var_floor = 0.0;
     c->relinearize = 1;
+    c->relin_step = 1.0;
     c->device = 0;
     c->stream = nullptr;
     c->leaf_size = 0;

@@ -235,6 +235,9 @@ void launch_ext_sample(hipStream_t st, GridDev g, const int32_t* T, const double
                        double* s2, int64_t N);
 void launch_ext_plugin(hipStream_t st, GridDev g, const int32_t* T, const double* f, double* centre, int64_t N);
 void launch_sum2(hipStream_t st, const double* a, const double* b, double* out, int64_t n);
+// out = (1 - r) (f - m) + r mu (m may be null); out may alias f
+void launch_relin_step(hipStream_t st, const double* f, const double* m, const double* mu, double r, double* out,
+                       int64_t n);
 void launch_sample_var(hipStream_t st, const double* s1, const double* s2, double* var, int K, int64_t n);
 void launch_density(hipStream_t st, const double* mu, const double* var, double* m, double* v, int64_t n);
 void launch_point_pred(hipStream_t st, GridDev g, FrontsDev F, const double* fronts, const int32_t* iperm,

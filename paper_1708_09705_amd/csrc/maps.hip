@@ -165,6 +165,12 @@ __global__ void k_axpy_add(const double* a, const double* b, double* out, int64_
         out[i] = a[i] + b[i];
 }
 
+// out = (1 - r) (f - m) + r mu, m optional (null: 0)
+__global__ void k_relin_step(const double* f, const double* m, const double* mu, double r, double* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (1.0 - r) * (f[i] - (m ? m[i] : 0.0)) + r * mu[i];
+}
+
 __global__ void k_sample_var(const double* s1, const double* s2, double* var, int K, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         var[i] = (s2[i] - s1[i] * s1[i] / K) / (K - 1);
@@ -275,6 +281,11 @@ void launch_ext_sample(hipStream_t st, GridDev g, const int32_t* T, const double
 
 void launch_sum2(hipStream_t st, const double* a, const double* b, double* out, int64_t n) {
     if (n > 0) hipLaunchKernelGGL(k_axpy_add, dim3(grid_n(n)), dim3(256), 0, st, a, b, out, n);
+}
+
+void launch_relin_step(hipStream_t st, const double* f, const double* m, const double* mu, double r, double* out,
+                       int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_relin_step, dim3(grid_n(n)), dim3(256), 0, st, f, m, mu, r, out, n);
 }
 
 void launch_sample_var(hipStream_t st, const double* s1, const double* s2, double* var, int K, int64_t n) {

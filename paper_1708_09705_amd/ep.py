@@ -62,6 +62,7 @@ class ep_config(ctypes.Structure):
         ("theta_prior", ctypes.c_double * 5),
         ("sun_radius_pc", ctypes.c_double),
         ("bump_width_pc", ctypes.c_double),
+        ("relin_step", ctypes.c_double),
     ]
 
 

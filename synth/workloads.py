@@ -51,6 +51,7 @@ class Workload:
     precision: str = "fp64"
     moments: str = "quadrature"
     damping: float = 1.0
+    relin_step: float = 1.0     # linearisation step (1: onto the posterior mean)
     cavity_var_floor: float = 0.0
     seed_id: int = 1
 
@@ -75,7 +76,7 @@ class Workload:
             vecchia_radius_pc=self.vecchia_radius_pc or self.support_pc,
             los_step_pc=self.los_step_pc, likelihood=self.likelihood,
             precision=self.precision, moments=self.moments,
-            damping=self.damping, cavity_var_floor=self.cavity_var_floor)
+            damping=self.damping, relin_step=self.relin_step, cavity_var_floor=self.cavity_var_floor)
 
 
 PRESETS = {
@@ -83,19 +84,19 @@ PRESETS = {
                 star_law="uniform", noise_law="const", noise_a=0.05, seed_id=1),
     2: Workload("cfg2-64cube-100k", n=64, box_pc=4000.0, n_stars=100_000, sweeps=20,
                 star_law="disc", d_max_pc=4000.0, noise_law="uniform",
-                noise_a=0.05, noise_b=0.2, seed_id=2),
+                noise_a=0.05, noise_b=0.2, relin_step=0.5, seed_id=2),
     3: Workload("cfg3-128cube-1M", n=128, box_pc=8000.0, n_stars=1_000_000, sweeps=20,
                 star_law="disc", d_max_pc=8000.0, noise_law="linear",
-                noise_a=0.02, noise_b=0.03, precision="mixed", seed_id=3),
+                noise_a=0.02, noise_b=0.03, precision="mixed", relin_step=0.5, seed_id=3),
     4: Workload("cfg4-128cube-1M-surrogate", n=128, box_pc=8000.0, n_stars=1_000_000, sweeps=20,
                 star_law="disc", d_max_pc=8000.0, noise_law="linear",
-                noise_a=0.02, noise_b=0.03, precision="mixed", moments="surrogate", seed_id=4),
+                noise_a=0.02, noise_b=0.03, precision="mixed", moments="surrogate", relin_step=0.5, seed_id=4),
     # positions from the disc law; the G < 17 magnitude cut needs the
     # extinction along each sightline and is applied when observations are
     # simulated, not here
     5: Workload("cfg5-256cube-10M", n=256, box_pc=8000.0, n_stars=10_000_000, sweeps=10,
                 star_law="disc", d_max_pc=8000.0, noise_law="uniform", noise_a=0.03, noise_b=0.3,
-                support_pc=120.0, precision="mixed", moments="surrogate", seed_id=5),
+                support_pc=120.0, precision="mixed", moments="surrogate", relin_step=0.5, seed_id=5),
 }
 
 

@@ -39,7 +39,7 @@ def test_config_default_and_struct_size():
     c = E.make_config()
     assert c.n == 16 and c.box_pc == 1000.0 and c.prior_mean == -7.0
     assert tuple(c.observer_pc) == (500.0, 0.0, 500.0)
-    assert c.damping == 1.0 and c.relinearize == 1 and c.los_step_pc == 2.0
+    assert c.damping == 1.0 and c.relinearize == 1 and c.los_step_pc == 2.0 and c.relin_step == 1.0
 
 
 def test_invalid_inputs_rejected_before_device_work():
@@ -54,7 +54,8 @@ def test_invalid_inputs_rejected_before_device_work():
         with pytest.raises(E.EPError) as ei:
             E.ep_init(cfg, bad.get("xyz", xyz), bad.get("A", A), bad.get("s", s))
         assert ei.value.code == -1
-    for field, val in (("n", 1), ("damping", 0.0), ("box_pc", -1.0), ("precision", 7)):
+    for field, val in (("n", 1), ("damping", 0.0), ("box_pc", -1.0), ("precision", 7), ("relin_step", 0.0),
+                       ("relin_step", 1.5)):
         c = E.make_config(**{field: val})
         with pytest.raises(E.EPError) as ei:
             E.ep_init(c, xyz, A, s)

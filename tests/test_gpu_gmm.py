@@ -25,11 +25,13 @@ def _case(n=9, L=700.0, stars=200, leaf=48, seed=31):
     return w, cfg, gcfg, cat, vec
 
 
-@pytest.mark.parametrize("n,L,stars,leaf", [(8, 500.0, 80, 32), (10, 700.0, 200, 48), (12, 800.0, 300, 64)])
-def test_gmm_ep_matches_oracle(n, L, stars, leaf):
+@pytest.mark.parametrize("n,L,stars,leaf,relin_step", [(8, 500.0, 80, 32, 1.0), (10, 700.0, 200, 48, 1.0),
+                                                        (12, 800.0, 300, 64, 1.0), (10, 700.0, 200, 48, 0.5)])
+def test_gmm_ep_matches_oracle(n, L, stars, leaf, relin_step):
     from paper_1708_09705_amd import ep as E
     w, cfg, gcfg, cat, vec = _case(n=n, L=L, stars=stars, leaf=leaf)
-    print(f"case n={n} L={L} stars={stars}", flush=True)
+    cfg["relin_step"] = gcfg["relin_step"] = relin_step
+    print(f"case n={n} L={L} stars={stars} relin_step={relin_step}", flush=True)
     ora = gmm.DenseEPGMM(cfg, cat["xyz"], cat["comps"], vecchia=vec)
     g = E.EP(gcfg, cat["xyz"])
     g.set_gmm(cat["comps"])

@@ -55,6 +55,7 @@ def _run_pair(cfg, gcfg, raw, A, sl, sweeps):
         assert sg["updated"] == so["updated"]
         assert np.allclose(tg, ora.tau, rtol=1e-8, atol=1e-10)
         assert np.allclose(ng, ora.nu, rtol=1e-8, atol=1e-8)
+    assert relerr(g.linpoint(), ora.fhat) < 1e-8
     mo, vo = ora.posterior_mean(), ora.marginal_var()
     mg, vg = g.posterior_mean(), g.marginal_var()
     print(f"posterior: mean {relerr(mg, mo):.2e} var {relerr(vg, vo):.2e}", flush=True)
@@ -67,6 +68,14 @@ def _run_pair(cfg, gcfg, raw, A, sl, sweeps):
 def test_ep_extinction_matches_oracle(n, L, stars, leaf):
     cfg, gcfg, raw, f, A, sl = small_case(n=n, L=L, stars=stars, leaf=leaf)
     _run_pair(cfg, gcfg, raw, A, sl, sweeps=3)
+
+
+def test_ep_partial_linearisation_step_matches_oracle():
+    """relin_step 0.5 with site damping 0.7: the linearisation point moves
+    half-way to the posterior mean after each sweep, on both sides."""
+    cfg, gcfg, raw, f, A, sl = small_case(n=10, L=600.0, stars=200, leaf=48, damping=0.7)
+    cfg["relin_step"] = gcfg["relin_step"] = 0.5
+    _run_pair(cfg, gcfg, raw, A, sl, sweeps=4)
 
 
 def test_ep_gaussian_is_exact_in_one_sweep():

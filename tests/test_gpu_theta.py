@@ -32,11 +32,13 @@ def _rel_phi(a, b):
     return float(np.max(np.abs(np.asarray(a) - b) / np.maximum(np.abs(b), 1.0)))
 
 
-@pytest.mark.parametrize("n,L,stars,leaf", [(8, 1000.0, 120, 32), (9, 1200.0, 200, 48), (11, 1200.0, 300, 64)])
-def test_theta_ep_matches_oracle(n, L, stars, leaf):
+@pytest.mark.parametrize("n,L,stars,leaf,relin_step", [(8, 1000.0, 120, 32, 1.0), (9, 1200.0, 200, 48, 1.0),
+                                                        (11, 1200.0, 300, 64, 1.0), (9, 1200.0, 200, 48, 0.5)])
+def test_theta_ep_matches_oracle(n, L, stars, leaf, relin_step):
     from paper_1708_09705_amd import ep as E
     cfg, gcfg, raw, A, sl = _case(n=n, L=L, stars=stars, leaf=leaf)
-    print(f"case n={n} L={L} stars={stars}", flush=True)
+    cfg["relin_step"] = gcfg["relin_step"] = relin_step
+    print(f"case n={n} L={L} stars={stars} relin_step={relin_step}", flush=True)
     ora = meanfn.DenseEPTheta(cfg, raw["xyz"], A, raw["sigma"], sightlines=sl)
     g = E.EP(gcfg, raw["xyz"], A, raw["sigma"])
     for s in range(3):
@@ -60,6 +62,7 @@ def test_theta_ep_matches_oracle(n, L, stars, leaf):
     # the linearisation point carries phihat
     lp = g.linpoint()
     assert lp.shape == (n ** 3 + 5,) and np.allclose(lp[-5:], ora.phihat, rtol=1e-8, atol=1e-10)
+    assert relerr(lp[:-5], ora.fhat) < 1e-8
     # density moments of f
     dm, dv = g.density_moments()
     om, ov = np.exp(mo + vo / 2), np.expm1(vo) * np.exp(2 * mo + vo)

@@ -232,7 +232,8 @@ def _lnA_plain(cfg, xyz, f):
     return lnA, grad
 
 
-def test_relinearised_fixed_point():
+@pytest.mark.parametrize("relin_step", [1.0, 0.5])
+def test_relinearised_fixed_point(relin_step):
     """With the sightlines re-linearised at the posterior mean every sweep
     (the linearisation of the log-extinction likelihood in a_n about the
     current field), iterate damped EP to its fixed point and check what the
@@ -245,6 +246,7 @@ def test_relinearised_fixed_point():
       * the fixed point is not the frozen-projection one (so a stale
         linearisation would fail the checks above)."""
     w, cfg = _small(n=7, L=420.0, stars=30, relinearize=True, damping=0.5)
+    cfg = dict(cfg, relin_step=relin_step)
     raw = draw(w)
     f_true, A_obs, sl = epo.simulate(cfg, raw)
     sig = raw["sigma"]
@@ -253,12 +255,14 @@ def test_relinearised_fixed_point():
     m0b = ep.Q0 @ np.full(sl.grid.N, cfg["prior_mean"])
     # the iterates: each sweep moves the point to the mean of the posterior
     # built, with the sites it started from, at the point it started from
+    # (the fraction relin_step of the way there)
     for _ in range(3):
-        lnA, Gp = _lnA_plain(cfg, raw["xyz"], ep.fhat)
+        f0 = ep.fhat.copy()
+        lnA, Gp = _lnA_plain(cfg, raw["xyz"], f0)
         Q = ep.Q0 + Gp.T @ (ep.tau[:, None] * Gp)
-        mu_next = np.linalg.solve(Q, m0b + Gp.T @ (ep.nu - ep.tau * (lnA - Gp @ ep.fhat)))
+        mu_next = np.linalg.solve(Q, m0b + Gp.T @ (ep.nu - ep.tau * (lnA - Gp @ f0)))
         ep.sweep()
-        assert np.allclose(ep.fhat, mu_next, rtol=1e-11, atol=1e-11)
+        assert np.allclose(ep.fhat, f0 + relin_step * (mu_next - f0), rtol=1e-11, atol=1e-11)
     for it in range(400):
         st = ep.sweep()
         if st["max_dtau"] < 1e-10 and st["max_dmu"] < 1e-10:
@@ -291,6 +295,15 @@ def test_relinearised_fixed_point():
         if fz.sweep()["max_dtau"] < 1e-10:
             break
     assert np.max(np.abs(fz.posterior_mean() - mu)) > 1e-3
+    # (5) a partial linearisation step changes the path, not the fixed point
+    if relin_step != 1.0:
+        full = epo.DenseEP(dict(cfg, relin_step=1.0), raw["xyz"], A_obs, sig, sightlines=sl)
+        for _ in range(400):
+            st1 = full.sweep()
+            if st1["max_dtau"] < 1e-10 and st1["max_dmu"] < 1e-10:
+                break
+        assert np.allclose(full.fhat, ep.fhat, rtol=0, atol=1e-8)
+        assert np.allclose(full.tau, ep.tau, rtol=1e-8, atol=1e-8)
 
 
 def test_posterior_uses_current_linearisation_point():

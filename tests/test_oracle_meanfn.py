@@ -132,6 +132,33 @@ def test_vanishing_hyperprior_variance_gives_the_fixed_mean_ep():
     assert 30 < worst[1e-6] / worst[1e-8] < 300
 
 
+def test_partial_linearisation_step_keeps_the_fixed_point():
+    """With the inferred mean and the extinction likelihood, moving the
+    linearisation point (deltahat and phihat) only part of the way to the
+    posterior means each sweep changes the path, not the EP fixed point."""
+    cfg, raw = _small(6, 500.0, 60, "extinction")
+    cfg.update(sun_radius_pc=8000.0, bump_width_pc=200.0, theta_prior=meanfn.DEFAULT_PRIOR, damping=0.5)
+    f_true, A, sl = meanfn.simulate(cfg, raw, np.array([2500.0, 200.0, 1.2e-3, 300.0, 0.1]))
+    out = {}
+    for r in (1.0, 0.5):
+        ep = meanfn.DenseEPTheta(dict(cfg, relin_step=r), raw["xyz"], A, raw["sigma"], sightlines=sl)
+        for it in range(400):
+            f0, t0 = ep.fhat.copy(), ep.tau.copy()
+            ep.sweep()
+            if np.max(np.abs(ep.fhat - f0)) < 1e-11 and np.max(np.abs(ep.tau - t0)) < 1e-10:
+                break
+        assert it < 399, r
+        m, _ = ep.mean(ep.phihat)
+        mu = ep.posterior_mean()
+        # at the fixed point the linearisation point is the posterior mean
+        assert np.max(np.abs(mu - ep.fhat)) < 1e-9
+        out[r] = (ep.fhat, ep.phihat, ep.tau, it)
+    print("sweeps to converge: r = 1:", out[1.0][3], " r = 0.5:", out[0.5][3])
+    assert np.allclose(out[1.0][0], out[0.5][0], rtol=0, atol=1e-8)
+    assert np.allclose(out[1.0][1], out[0.5][1], rtol=0, atol=1e-8)
+    assert np.allclose(out[1.0][2], out[0.5][2], rtol=1e-7, atol=1e-8)
+
+
 def test_recovers_the_density_scale_on_synthetic_data():
     w = Workload("t", n=10, box_pc=4000.0, n_stars=500, sweeps=4, star_law="disc", d_max_pc=4000.0,
                  noise_law="const", noise_a=0.05, likelihood="extinction", seed_id=11)
