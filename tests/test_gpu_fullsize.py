@@ -105,3 +105,42 @@ def test_config2_gaussian_mode_properties(cfg2):
     print(f"config 2 gaussian: relative residual {res:.2e}", flush=True)
     assert res < 1e-10
     assert np.all(var > 0) and np.all(var < 1.1 * cfg["prior_var"])
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "cfg2_sweep1.npz")
+
+
+def test_config2_after_sweep1_against_oracle_pcg(cfg2):
+    """64^3 / 100,000 stars with the sites of sweep 1 loaded, so every star's
+    clique is assembled (the 24k-wide fronts, the split-K atomic GEMM tasks
+    and the nine-level tree all carry data): the posterior mean at every
+    node, the marginal variance at 64 nodes (nearest the observer, on the
+    planes x = L/2 and z = L/2 through it, random) and the cavities of 64
+    stars (nearest, longest sightlines, random) against the oracle's
+    matrix-free PCG solves of the same Q and b, written by
+    tests/golden/make_cfg2_sweep1.py.  FP64 bar: 1e-8 relative."""
+    E = _E()
+    gd = np.load(GOLDEN)
+    w, cfg, raw, vec = cfg2
+    f_true, A, sl = epo.simulate(cfg, raw)
+    g = E.EP(dict(cfg, leaf_size=512), raw["xyz"], A, raw["sigma"])
+    g.set_sites(gd["tau"], gd["nu"])
+    mu = g.posterior_mean()
+    var = g.marginal_var()
+    nodes, stars = gd["nodes"], gd["stars"]
+    perm = g.ordering()
+    rank = np.empty(len(perm), dtype=np.int64)
+    rank[perm] = np.arange(len(perm))
+    last = int(np.sum(rank[nodes] >= len(perm) - 16384))
+    em, ev = relerr(mu, gd["mu"]), relerr(var[nodes], gd["var"])
+    print(f"config 2 after sweep 1: mean (all nodes) {em:.2e}, variance (64 nodes, {last} in the last 16384 "
+          f"eliminated) {ev:.2e}", flush=True)
+    assert last >= 4
+    assert em < 1e-8 and ev < 1e-8
+    assert np.all(gd["cav_var"] > 0)
+    g.sweep()    # cavities from the loaded sites at the same linearisation point
+    ss = g.star_state()
+    g.close()
+    ec, ecm = relerr(ss["cav_var"][stars], gd["cav_var"]), relerr(ss["cav_mu"][stars], gd["cav_mu"])
+    print(f"cavities of 64 stars: variance {ec:.2e} mean {ecm:.2e}", flush=True)
+    assert ec < 1e-8 and ecm < 1e-8
