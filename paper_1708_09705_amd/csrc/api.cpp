@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <unordered_map>
 #include <map>
 #include <atomic>
 #include <chrono>
@@ -94,6 +96,18 @@ struct ep_ctx {
     std::string err = "no error";
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
+    // deterministic mode: clique windows, right-hand-side node lists, the
+    // forward solve's per-level update lists and their staging vector
+    int64_t n_win = 0;
+    int32_t *d_wfront = nullptr, *d_istar = nullptr, *d_ilo = nullptr, *d_ihi = nullptr, *d_nstar = nullptr;
+    int64_t *d_wptr = nullptr, *d_nptr = nullptr, *d_nslot = nullptr;
+    double* d_stage = nullptr;
+    struct DetLevel {
+        int64_t n = 0;
+        int32_t* tgt = nullptr;
+        int64_t *tptr = nullptr, *src = nullptr;
+    };
+    std::vector<DetLevel> det_lv;
 
     std::vector<int64_t> xoff;   // X block offset per front
     double *d_fronts = nullptr, *d_X = nullptr, *d_W = nullptr;
@@ -344,8 +358,10 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                         }
             };
             // pieces of at least 8 K tiles, enough to give ~2 blocks per CU
-            auto split_for = [](int64_t nblocks, int nk) {
-                if (nblocks <= 0) return 1;
+            // (none in the deterministic mode: the pieces add atomically)
+            const bool nosplit = ctx->cfg.deterministic != 0;
+            auto split_for = [nosplit](int64_t nblocks, int nk) {
+                if (nblocks <= 0 || nosplit) return 1;
                 int64_t sp = (512 + nblocks - 1) / nblocks;
                 sp = std::min<int64_t>(sp, std::max(1, nk / 8));
                 return (int)std::max<int64_t>(1, sp);
@@ -624,6 +640,11 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
     if (!(c->los_step_pc > 0)) { err = "los_step_pc must be > 0"; return EP_ERR_INVALID_ARG; }
     if (!(c->damping > 0 && c->damping <= 1)) { err = "damping must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
     if (!(c->relin_step > 0 && c->relin_step <= 1)) { err = "relin_step must be in (0, 1]"; return EP_ERR_INVALID_ARG; }
+    if (c->deterministic != 0 && c->deterministic != 1) { err = "deterministic must be 0 or 1"; return EP_ERR_INVALID_ARG; }
+    if (c->deterministic && (c->precision != EP_PREC_FP64 || c->mean_fn != EP_MEAN_CONSTANT)) {
+        err = "deterministic needs precision FP64 and mean_fn CONSTANT";
+        return EP_ERR_INVALID_ARG;
+    }
     if (c->likelihood != EP_LIK_EXTINCTION && c->likelihood != EP_LIK_GAUSS_LINEAR && c->likelihood != EP_LIK_GMM) {
         err = "unknown likelihood";
         return EP_ERR_INVALID_ARG;
@@ -707,6 +728,119 @@ static Phi5 phi5(const double* v) {
     Phi5 p{};
     for (int j = 0; j < NTHETA; j++) p.v[j] = v[j];
     return p;
+}
+
+// The deterministic mode's fixed summation orders (host, once):
+//  * clique windows: for every front, 4-column windows; a window lists the
+//    stars of the front with support nodes in its columns, in star order,
+//    with the range of the star's sorted slots that falls in it; windows are
+//    ordered heaviest first (their pairs), so the long ones start early;
+//  * right-hand side: for every node, its slots in star order;
+//  * forward solve: for every level, every updated row with the positions
+//    (rptr + local row) of the level's fronts that update it, in front order.
+// columns per clique window: at 64^3 / 100k the assembly takes 223, 166, 138
+// and 130 ms per sweep with 64-, 16-, 8- and 4-column windows (the chains of
+// stars through the busiest columns set the time)
+constexpr int DET_WINDOW = 4;
+static int build_deterministic(ep_ctx* ctx, const std::vector<int32_t>& sord) {
+    const Symbolic& sym = ctx->sym;
+    const int64_t S = ctx->S, N = ctx->g.N();
+    const auto& ptr = ctx->sup.ptr;
+    {
+        std::unordered_map<int64_t, int64_t> key;
+        std::vector<int32_t> wf;
+        std::vector<std::vector<std::array<int32_t, 3>>> inc;
+        std::vector<double> weight;
+        for (int64_t st = 0; st < S; st++) {
+            const int64_t p0 = ptr[st];
+            const int cnt = (int)(ptr[st + 1] - p0);
+            const int32_t f = sym.star_front[st];
+            int k = 0;
+            while (k < cnt) {
+                const int32_t w = sym.star_loc[p0 + sord[p0 + k]] / DET_WINDOW;
+                int k1 = k + 1;
+                while (k1 < cnt && sym.star_loc[p0 + sord[p0 + k1]] / DET_WINDOW == w) k1++;
+                const int64_t kk = ((int64_t)f << 32) | (uint32_t)w;
+                auto it = key.find(kk);
+                int64_t wi;
+                if (it == key.end()) {
+                    wi = (int64_t)wf.size();
+                    key.emplace(kk, wi);
+                    wf.push_back(f);
+                    inc.emplace_back();
+                    weight.push_back(0.0);
+                } else {
+                    wi = it->second;
+                }
+                inc[wi].push_back({(int32_t)st, k, k1});
+                for (int b = k; b < k1; b++) weight[wi] += (double)(cnt - b);
+                weight[wi] += 64.0;   // the wait between stars
+                k = k1;
+            }
+        }
+        std::vector<int64_t> ord(wf.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return weight[a] > weight[b]; });
+        std::vector<int32_t> wfront, istar, ilo, ihi;
+        std::vector<int64_t> wptr(1, 0);
+        for (int64_t wi : ord) {
+            wfront.push_back(wf[wi]);
+            for (const auto& e : inc[wi]) {
+                istar.push_back(e[0]);
+                ilo.push_back(e[1]);
+                ihi.push_back(e[2]);
+            }
+            wptr.push_back((int64_t)istar.size());
+        }
+        ctx->n_win = (int64_t)wfront.size();
+        TRY(upload(ctx, &ctx->d_wfront, wfront));
+        TRY(upload(ctx, &ctx->d_wptr, wptr));
+        TRY(upload(ctx, &ctx->d_istar, istar));
+        TRY(upload(ctx, &ctx->d_ilo, ilo));
+        TRY(upload(ctx, &ctx->d_ihi, ihi));
+    }
+    {
+        std::vector<int64_t> nptr((size_t)N + 1, 0);
+        for (int64_t q = 0; q < (int64_t)ctx->sup.nodes.size(); q++) nptr[(size_t)ctx->sup.nodes[q] + 1]++;
+        for (int64_t p = 0; p < N; p++) nptr[p + 1] += nptr[p];
+        std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1), nslot(ctx->sup.nodes.size());
+        std::vector<int32_t> nstar(ctx->sup.nodes.size());
+        for (int64_t st = 0; st < S; st++)
+            for (int64_t q = ptr[st]; q < ptr[st + 1]; q++) {
+                const int64_t at = fill[ctx->sup.nodes[q]]++;
+                nslot[at] = q;
+                nstar[at] = (int32_t)st;
+            }
+        TRY(upload(ctx, &ctx->d_nptr, nptr));
+        TRY(upload(ctx, &ctx->d_nslot, nslot));
+        TRY(upload(ctx, &ctx->d_nstar, nstar));
+    }
+    {
+        ctx->det_lv.assign(sym.nlevels, ep_ctx::DetLevel{});
+        std::vector<std::vector<int32_t>> lv(sym.nlevels);
+        for (int32_t f = 0; f < (int32_t)sym.fronts.size(); f++) lv[sym.fronts[f].level].push_back(f);
+        for (int l = 0; l < sym.nlevels; l++) {
+            std::map<int64_t, std::vector<int64_t>> rows;   // updated row -> stage positions, front order
+            for (int32_t f : lv[l]) {
+                const Front& Fr = sym.fronts[f];
+                for (int a = 0; a < Fr.nr; a++) rows[sym.rrows[Fr.rptr + a]].push_back(Fr.rptr + a);
+            }
+            std::vector<int32_t> tgt;
+            std::vector<int64_t> tptr(1, 0), src;
+            for (const auto& kv : rows) {
+                tgt.push_back((int32_t)kv.first);
+                src.insert(src.end(), kv.second.begin(), kv.second.end());
+                tptr.push_back((int64_t)src.size());
+            }
+            ep_ctx::DetLevel& D = ctx->det_lv[l];
+            D.n = (int64_t)tgt.size();
+            TRY(upload(ctx, &D.tgt, tgt));
+            TRY(upload(ctx, &D.tptr, tptr));
+            TRY(upload(ctx, &D.src, src));
+        }
+        TRY(dev_alloc(ctx, &ctx->d_stage, (int64_t)sym.rrows.size()));
+    }
+    return EP_OK;
 }
 
 static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const double* sig) {
@@ -904,6 +1038,7 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     }
     TRY(upload(ctx, &ctx->d_sfront, sym.star_front));
     TRY(upload(ctx, &ctx->d_nsamp, ctx->sup.nsamp));
+    if (c.deterministic) TRY(build_deterministic(ctx, sord));
     const int64_t nG = (int64_t)ctx->sup.nodes.size();
     TRY(dev_alloc(ctx, &ctx->d_g, nG));
     double** sarr[] = {&ctx->d_lnA, &ctx->d_c, &ctx->d_tau, &ctx->d_nu, &ctx->d_cmu, &ctx->d_cvar, &ctx->d_lnZ,
@@ -1025,6 +1160,15 @@ static int enqueue_assemble(ep_ctx* ctx) {
     // 30.5 ms per sweep at 64^3 / 100k)
     StarsDev sd = ctx->SD;
     sd.order = nullptr;
+    if (ctx->cfg.deterministic) {
+        kt_begin(ctx, ctx->S);
+        launch_assemble_windows(st, sd, ctx->F, ctx->d_fronts, ctx->d_wfront, ctx->d_wptr, ctx->d_istar, ctx->d_ilo,
+                                ctx->d_ihi, ctx->n_win);
+        kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
+        HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));
+        launch_assemble_b_nodes(st, sd, ctx->d_nptr, ctx->d_nslot, ctx->d_nstar, ctx->d_borig, ctx->g.N());
+        return EP_OK;
+    }
     kt_begin(ctx, ctx->S);
     launch_assemble_stars(st, sd, ctx->F, ctx->d_fronts, ctx->max_support);
     kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
@@ -1107,8 +1251,13 @@ static void enqueue_tri_solve(ep_ctx* ctx, double* out) {
                       ctx->d_t);
         kt_end(ctx, P.fwd_xv.ntasks, EP_KK_SOLVE);
         kt_begin(ctx, P.fwd_r.ntasks);
+        const bool det = ctx->cfg.deterministic != 0;
         launch_fwd_r(st, ctx->d_batches + P.fwd_r.be_off, P.fwd_r.nbe, P.fwd_r.ntasks, ctx->F, b, ctx->d_t,
-                     ctx->d_y);
+                     ctx->d_y, det ? ctx->d_stage : nullptr);
+        if (det) {
+            const ep_ctx::DetLevel& D = ctx->det_lv[lvl];
+            launch_gather_sub(st, D.tgt, D.tptr, D.src, D.n, ctx->d_stage, ctx->d_y);
+        }
         kt_end(ctx, P.fwd_r.ntasks, EP_KK_SOLVE);
         launch_copy_v(st, ctx->d_flists + P.fronts.off, P.fronts.n, ctx->F, ctx->d_t, ctx->d_y);
     }
@@ -1623,6 +1772,7 @@ void ep_config_default(ep_config* c) {
     c->cavity_var_floor = 0.0;
     c->relinearize = 1;
     c->relin_step = 1.0;
+    c->deterministic = 0;
     c->device = 0;
     c->stream = nullptr;
     c->leaf_size = 0;

@@ -100,7 +100,10 @@ void launch_zero_lower(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntas
 void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                    const double* y, double* t);
 void launch_fwd_r(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
-                  const double* t, double* y);
+                  const double* t, double* y, double* stage = nullptr);
+// y[tgt[i]] -= stage[src[e]] for e in [tptr[i], tptr[i+1]), in that order
+void launch_gather_sub(hipStream_t st, const int32_t* tgt, const int64_t* tptr, const int64_t* src, int64_t n,
+                       const double* stage, double* y);
 void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y);
 void launch_bwd_t(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
                   const double* y, const double* x, double* t);
@@ -186,6 +189,12 @@ void launch_f_mean(hipStream_t st, const double* mhat, const double* J, const do
 void launch_f_var(hipStream_t st, const double* W, const double* J, BorderDev b, double* var, int64_t N);
 void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int max_support);
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b);
+// deterministic forms of the two above (fixed summation order, no atomics)
+void launch_assemble_windows(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, const int32_t* wfront,
+                             const int64_t* wptr, const int32_t* istar, const int32_t* ilo, const int32_t* ihi,
+                             int64_t nwin);
+void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, const int64_t* nslot,
+                             const int32_t* nstar, double* b, int64_t N);
 void launch_gather_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);
 void launch_scatter_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);
 void launch_diag(hipStream_t st, const int32_t* perm, const int32_t* snode, FrontsDev F, const double* fronts,

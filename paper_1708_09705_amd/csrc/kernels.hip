@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 
 #include "kernels.h"
 
@@ -714,10 +715,12 @@ __global__ __launch_bounds__(256) void k_fwd_xv(const BatchEnt* __restrict__ be,
     }
 }
 
+// y[update rows] -= L21 z; with stage, the products go to stage[rptr + row]
+// instead (no atomics) and k_gather_sub applies them in a fixed order
 template <typename LT>
 __global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
                                                FrontsDev F, const LT* __restrict__ Lbuf, const double* __restrict__ z,
-                                               double* __restrict__ y) {
+                                               double* __restrict__ y, double* __restrict__ stage) {
     __shared__ double v[TS];
     __shared__ double part[4][TS];
     const int64_t t = blockIdx.x;
@@ -747,7 +750,21 @@ __global__ __launch_bounds__(256) void k_fwd_r(const BatchEnt* __restrict__ be, 
     if (threadIdx.x < TS) {
         int a = TS * i + threadIdx.x;
         double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
-        if (a < nr) atomicAdd(y + F.rrows[F.rptr[f] + a], -s);
+        if (a < nr) {
+            if (stage) stage[F.rptr[f] + a] = s;
+            else atomicAdd(y + F.rrows[F.rptr[f] + a], -s);
+        }
+    }
+}
+
+// y[tgt[i]] -= sum over e in [tptr[i], tptr[i+1]) of stage[src[e]], in that order
+__global__ void k_gather_sub(const int32_t* __restrict__ tgt, const int64_t* __restrict__ tptr,
+                             const int64_t* __restrict__ src, int64_t n, const double* __restrict__ stage,
+                             double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = y[tgt[i]];
+        for (int64_t e = tptr[i]; e < tptr[i + 1]; e++) v -= stage[src[e]];
+        y[tgt[i]] = v;
     }
 }
 
@@ -855,14 +872,21 @@ void launch_fwd_xv(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
     hipLaunchKernelGGL(k_fwd_xv, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F, b, y, t);
 }
 void launch_fwd_r(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b,
-                  const double* t, double* y) {
+                  const double* t, double* y, double* stage) {
     if (ntasks <= 0) return;
     if (b.F32)
         hipLaunchKernelGGL(k_fwd_r<float>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
-                           (const float*)b.F32, t, y);
+                           (const float*)b.F32, t, y, (double*)nullptr);
     else
         hipLaunchKernelGGL(k_fwd_r<double>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, F,
-                           (const double*)b.fronts, t, y);
+                           (const double*)b.fronts, t, y, stage);
+}
+
+void launch_gather_sub(hipStream_t st, const int32_t* tgt, const int64_t* tptr, const int64_t* src, int64_t n,
+                       const double* stage, double* y) {
+    if (n <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_gather_sub, dim3(blocks), dim3(256), 0, st, tgt, tptr, src, n, stage, y);
 }
 void launch_copy_v(hipStream_t st, const int32_t* flist, int nf, FrontsDev F, const double* t, double* y) {
     if (nf <= 0) return;
@@ -1073,6 +1097,73 @@ __global__ void k_assemble_b(StarsDev s, double* b) {
     const int64_t p0 = s.ptr[star];
     const int cnt = (int)(s.ptr[star + 1] - p0);
     for (int k = lane; k < cnt; k += 64) atomicAdd(b + s.nodes[p0 + k], coef * s.g[p0 + k]);
+}
+
+// Deterministic clique assembly: one wave per column window of a front;
+// the window's incidences (stars of the front with support nodes in those
+// columns, in star order; the star's sorted slots [b_lo, b_hi) fall in the
+// window) are applied one after the other.  Within one star every entry
+// (a, b), a >= b, is distinct, so the lanes add without atomics; the wait
+// between stars orders the read-modify-writes of one entry by star.
+__global__ __launch_bounds__(64) void k_assemble_windows(StarsDev s, FrontsDev F, double* fronts,
+                                                         const int32_t* __restrict__ wfront,
+                                                         const int64_t* __restrict__ wptr,
+                                                         const int32_t* __restrict__ istar,
+                                                         const int32_t* __restrict__ ilo,
+                                                         const int32_t* __restrict__ ihi, int64_t nwin) {
+    const int64_t w = blockIdx.x;
+    if (w >= nwin) return;
+    const int lane = threadIdx.x;
+    const int f = wfront[w];
+    double* base = fronts + F.off[f];
+    const int64_t m = F.m[f];
+    for (int64_t e = wptr[w]; e < wptr[w + 1]; e++) {
+        const int32_t star = istar[e];
+        const double tau = s.tau[star];
+        if (tau == 0.0) continue;
+        const int64_t p0 = s.ptr[star];
+        const int cnt = (int)(s.ptr[star + 1] - p0);
+        for (int b = ilo[e]; b < ihi[e]; b++) {
+            const int sb = s.sord[p0 + b];
+            const double tg = tau * s.g[p0 + sb];
+            double* col = base + (int64_t)s.loc[p0 + sb] * m;
+            for (int a = b + lane; a < cnt; a += 64) {
+                const int sa = s.sord[p0 + a];
+                double* p = col + s.loc[p0 + sa];
+                *p = *p + tg * s.g[p0 + sa];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Deterministic right-hand side: b[node] += sum over the node's slots (in
+// star order) of (nu - tau c) g, one thread per node.
+__global__ void k_assemble_b_nodes(StarsDev s, const int64_t* __restrict__ nptr, const int64_t* __restrict__ nslot,
+                                   const int32_t* __restrict__ nstar, double* b, int64_t N) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        double v = b[p];
+        for (int64_t e = nptr[p]; e < nptr[p + 1]; e++) {
+            const int32_t star = nstar[e];
+            v += (s.nu[star] - s.tau[star] * s.c[star]) * s.g[nslot[e]];
+        }
+        b[p] = v;
+    }
+}
+
+void launch_assemble_windows(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, const int32_t* wfront,
+                             const int64_t* wptr, const int32_t* istar, const int32_t* ilo, const int32_t* ihi,
+                             int64_t nwin) {
+    if (nwin <= 0) return;
+    hipLaunchKernelGGL(k_assemble_windows, dim3((unsigned)nwin), dim3(64), 0, st, s, F, fronts, wfront, wptr, istar,
+                       ilo, ihi, nwin);
+}
+
+void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, const int64_t* nslot,
+                             const int32_t* nstar, double* b, int64_t N) {
+    if (N <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_assemble_b_nodes, dim3(blocks), dim3(256), 0, st, s, nptr, nslot, nstar, b, N);
 }
 
 void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int cap) {

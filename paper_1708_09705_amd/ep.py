@@ -63,6 +63,7 @@ class ep_config(ctypes.Structure):
         ("sun_radius_pc", ctypes.c_double),
         ("bump_width_pc", ctypes.c_double),
         ("relin_step", ctypes.c_double),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
