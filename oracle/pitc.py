@@ -329,3 +329,127 @@ class DensePITCTheta(DensePITC):
             var[nodes] = (np.diag(self.K)[nodes] - np.einsum("ij,ij->j", kst, w)
                           + np.einsum("ij,ij->j", b, Vz @ b))
         return mean, var
+
+
+class DensePITCExt:
+    """PITC with the extinction likelihood: parallel EP with one Gaussian
+    site per star on a_n (as on the grid path, Sec. 4.1), the prior of a
+    being the PITC approximation instead of the grid's (App. A.1): a ~
+    N(mu_a, Q), Q = Sigma_k on the sub-catalogue blocks and rho_k C^{-1}
+    rho_l^T between them, a_n = c_n + g_n . f linearised at the prior mean
+    (frozen, as in the Gaussian PITC pass), A_n | a_n ~ N(e^{a_n}, sigma_n^2).
+
+    Readings: the paper forms one site per sub-catalogue over (u, Theta) and
+    samples the tilted distributions; here every star keeps its own site, so
+    the tilted distributions are the one-dimensional ones of the grid path
+    and the sub-catalogues enter through the prior.  With one sub-catalogue
+    and an exact prior this is the grid path's EP with frozen sightlines.
+    Given the sites the posterior is Gaussian, and so are q(u) and the PIC
+    predictive: those of the Gaussian pass with pseudo-observations nu/tau
+    of variance 1/tau, written in the scaled form s = sqrt(tau) so that stars
+    without a site (tau = 0) carry no information.  Mean parameters are not
+    inferred here (constant prior mean)."""
+
+    def __init__(self, cfg: dict, xyz, A_obs, sigma, blocks, inducing, node_block=None,
+                 sightlines: epo.Sightlines | None = None, K: np.ndarray | None = None):
+        self.cfg = dict(cfg)
+        self.m0 = float(cfg["prior_mean"])
+        self.sl = sightlines or epo.Sightlines(cfg, xyz)
+        self.grid = self.sl.grid
+        N = self.grid.N
+        self.K = node_cov(cfg) if K is None else K
+        gval, _, c = self.sl.linearise(np.full(N, self.m0))
+        self.G = self.sl.G_dense(gval)
+        self.A_obs = np.asarray(A_obs, dtype=np.float64)
+        self.sigma = np.asarray(sigma, dtype=np.float64)
+        self.mu_a = c + self.G @ np.full(N, self.m0)
+        self.blocks = np.asarray(blocks)
+        self.nblk = int(self.blocks.max()) + 1 if self.blocks.size else 0
+        self.members = [np.nonzero(self.blocks == k)[0] for k in range(self.nblk)]
+        self.u = np.asarray(inducing, dtype=np.int64)
+        self.node_block = None if node_block is None else np.asarray(node_block)
+        self.m_u = np.full(len(self.u), self.m0)
+        self.C = self.K[np.ix_(self.u, self.u)]
+        self.Cinv = np.linalg.inv(self.C)
+        self.rho = self.G @ self.K[:, self.u]
+        Q = self.rho @ self.Cinv @ self.rho.T
+        for idx in self.members:
+            Q[np.ix_(idx, idx)] = self.G[idx] @ self.K @ self.G[idx].T
+        self.Q = 0.5 * (Q + Q.T)
+        S = len(self.A_obs)
+        self.tau = np.zeros(S)
+        self.nu = np.zeros(S)
+        self.vfloor = float(cfg.get("cavity_var_floor", 0.0))
+
+    def _scaled(self):
+        """s = sqrt(tau), B = I + S Q S and r~ = (nu - tau mu_a) / s (0 where tau = 0)."""
+        s = np.sqrt(self.tau)
+        B = np.eye(len(s)) + s[:, None] * self.Q * s[None, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rt = np.where(s > 0, (self.nu - self.tau * self.mu_a) / np.where(s > 0, s, 1.0), 0.0)
+        return s, B, rt
+
+    def posterior_a(self):
+        """(mean, cov) of q(a) = N(mu_a, Q) prod_n N(a_n; nu_n/tau_n, 1/tau_n)."""
+        s, B, rt = self._scaled()
+        SQ = s[:, None] * self.Q
+        cov = self.Q - SQ.T @ np.linalg.solve(B, SQ)
+        cov = 0.5 * (cov + cov.T)
+        mean = self.mu_a + SQ.T @ np.linalg.solve(B, rt)
+        return mean, cov
+
+    def sweep(self, damping: float = 1.0) -> dict:
+        """Every star from the same q (App. A.2): cavity, tilted moments,
+        new site; the skip rules and the cavity floor of the grid path."""
+        m, P = self.posterior_a()
+        v = np.diag(P).copy()
+        tau_c = 1.0 / v - self.tau
+        nu_c = m / v - self.nu
+        ok = tau_c > 0.0
+        v_c = np.where(ok, np.maximum(1.0 / np.where(ok, tau_c, 1.0), self.vfloor), 1.0)
+        mu_c = np.where(ok, nu_c / np.where(ok, tau_c, 1.0), 0.0)
+        tau_c, nu_c = 1.0 / v_c, mu_c / v_c
+        lnZ, mh, vh = epo.tilted(epo.LIK_EXTINCTION, mu_c, v_c, self.A_obs, self.sigma)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tau_new = 1.0 / vh - tau_c
+            nu_new = mh / vh - nu_c
+        good = ok & np.isfinite(tau_new) & np.isfinite(nu_new) & (tau_new >= 0.0)
+        d = float(damping)
+        old = self.tau.copy()
+        self.tau = np.where(good, (1 - d) * self.tau + d * tau_new, self.tau)
+        self.nu = np.where(good, (1 - d) * self.nu + d * nu_new, self.nu)
+        return dict(updated=int(good.sum()), skipped_cavity=int((~ok).sum()),
+                    skipped_negsite=int((ok & ~good).sum()), max_dtau=float(np.max(np.abs(self.tau - old))),
+                    marg_mean=m, marg_var=v, lnZ=lnZ, tilted_mean=mh, tilted_var=vh)
+
+    def posterior_u(self):
+        """(mean, cov) of q(u): (u, a) jointly Gaussian under PITC, cov(u, a) = rho^T."""
+        s, B, rt = self._scaled()
+        Sr = s[:, None] * self.rho
+        mean = self.m_u + Sr.T @ np.linalg.solve(B, rt)
+        cov = self.C - Sr.T @ np.linalg.solve(B, Sr)
+        return mean, 0.5 * (cov + cov.T)
+
+    def predict(self):
+        """PIC predictive (mean, var) of f at every node from its block's
+        scaled pseudo-observations and u, integrated over q(u)."""
+        N = self.grid.N
+        mean, var = np.zeros(N), np.zeros(N)
+        mu_u, V_u = self.posterior_u()
+        s, _, rt = self._scaled()
+        for i in range(self.nblk):
+            nodes = np.nonzero(self.node_block == i)[0]
+            if nodes.size == 0:
+                continue
+            idx = self.members[i]
+            si = s[idx]
+            Bi = np.eye(len(idx)) + si[:, None] * self.Q[np.ix_(idx, idx)] * si[None, :]
+            rho = si[:, None] * self.rho[idx]
+            J = np.block([[Bi, rho], [rho.T, self.C]])
+            kst = np.vstack([si[:, None] * (self.G[idx] @ self.K[:, nodes]), self.K[np.ix_(self.u, nodes)]])
+            w = np.linalg.solve(J, kst)
+            wa, wu = w[: len(idx)], w[len(idx):]
+            mean[nodes] = self.m0 + wa.T @ rt[idx] + wu.T @ (mu_u - self.m_u)
+            var[nodes] = (np.diag(self.K)[nodes] - np.einsum("ij,ij->j", kst, w)
+                          + np.einsum("ij,ij->j", wu, V_u @ wu))
+        return mean, var

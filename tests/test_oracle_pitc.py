@@ -299,3 +299,89 @@ def test_theta_sites_damping():
     for t in range(1, 3):
         half.sweep(0.5)
         assert _rel(half.Lam, (1 - 0.5 ** t) * full.Lam) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the extinction likelihood: one Gaussian site per star under the PITC prior
+# ---------------------------------------------------------------------------
+def _ext_case(n=5, L=400.0, stars=40, n_lon=3, n_lat=1, R=10, seed=7, exact_prior=False):
+    w = Workload("pitcx", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law="uniform", d_max_pc=L,
+                 noise_law="const", noise_a=0.05, likelihood="extinction", seed_id=seed)
+    cfg = w.ep_fields()
+    if exact_prior:
+        # conditioning on every earlier node: the Vecchia factor is the exact
+        # (tapered) prior, so the grid path's EP sees the same prior of a
+        cfg["vecchia_radius_pc"] = cfg["support_pc"] = 4.0 * L
+    raw = draw(w)
+    f_true, A, sl = epo.simulate(cfg, raw)
+    blocks = sky_cells(w, raw["xyz"], n_lon, n_lat)
+    node_block = sky_cells(w, node_positions(w), n_lon, n_lat)
+    rng = np.random.default_rng(seed)
+    u = np.sort(rng.choice(w.N, size=R, replace=False))
+    return w, cfg, raw, A, sl, blocks, node_block, u
+
+
+def test_ext_one_block_with_the_exact_prior_is_the_grid_ep():
+    """One sub-catalogue holding every star and an exact prior: PITC is then
+    exact, so the star sites, the posterior of a and the predictive of f must
+    be those of the grid path's EP with sightlines frozen at the prior mean
+    (which works in f with the Vecchia precision)."""
+    w, cfg, raw, A, sl, blocks, nb, u = _ext_case(exact_prior=True)
+    one = np.zeros_like(blocks)
+    o = pitc.DensePITCExt(cfg, raw["xyz"], A, raw["sigma"], one, u, np.zeros(w.N, dtype=int), sightlines=sl)
+    g = epo.DenseEP(dict(cfg, relinearize=False), raw["xyz"], A, raw["sigma"], sightlines=sl)
+    for d in (1.0, 0.7, 0.7, 1.0):
+        so = o.sweep(d)
+        g.damping = d
+        sg = g.sweep()
+        assert so["updated"] == sg["updated"]
+        assert np.allclose(o.tau, g.tau, rtol=1e-8, atol=1e-10) and np.allclose(o.nu, g.nu, rtol=1e-8, atol=1e-8)
+    pm, pv = o.predict()
+    assert _rel(pm, g.posterior_mean()) < 1e-9
+    assert np.allclose(pv, g.marginal_var(), rtol=1e-8)
+
+
+def test_ext_scaled_forms_match_the_plain_gaussian_conditioning():
+    """q(a) and q(u) from the scaled forms against the plain definition: the
+    joint Gaussian of (u, a) under PITC times the sites, conditioned with
+    explicit inverses (every site set after a sweep)."""
+    w, cfg, raw, A, sl, blocks, nb, u = _ext_case()
+    o = pitc.DensePITCExt(cfg, raw["xyz"], A, raw["sigma"], blocks, u, nb, sightlines=sl)
+    o.sweep(1.0)
+    o.sweep(0.8)
+    assert np.all(o.tau > 0)
+    R, S = len(u), len(A)
+    Jc = np.block([[o.C, o.rho.T], [o.rho, o.Q]])
+    P = np.linalg.inv(Jc)
+    P[R:, R:] += np.diag(o.tau)
+    V = np.linalg.inv(P)
+    m0 = np.concatenate([o.m_u, o.mu_a])
+    mean = V @ (np.linalg.solve(Jc, m0) + np.concatenate([np.zeros(R), o.nu]))
+    ma, Pa = o.posterior_a()
+    mu_, Vu = o.posterior_u()
+    assert _rel(ma, mean[R:]) < 1e-9 and np.allclose(Pa, V[R:, R:], rtol=1e-7, atol=1e-12)
+    assert _rel(mu_, mean[:R]) < 1e-9 and np.allclose(Vu, V[:R, :R], rtol=1e-7, atol=1e-12)
+
+
+def test_ext_moment_matching_at_convergence():
+    """At the fixed point the marginals of q(a) equal the tilted moments of
+    the cavities they define (App. A.2), and the sub-catalogue structure
+    matters: the sites differ from the one-block ones."""
+    w, cfg, raw, A, sl, blocks, nb, u = _ext_case()
+    o = pitc.DensePITCExt(cfg, raw["xyz"], A, raw["sigma"], blocks, u, nb, sightlines=sl)
+    for it in range(200):
+        st = o.sweep(0.7)
+        if st["max_dtau"] < 1e-10:
+            break
+    assert st["max_dtau"] < 1e-10, it
+    m, P = o.posterior_a()
+    v = np.diag(P)
+    tau_c, nu_c = 1 / v - o.tau, m / v - o.nu
+    assert np.all(tau_c > 0)
+    _, mh, vh = epo.tilted(epo.LIK_EXTINCTION, nu_c / tau_c, 1 / tau_c, A, raw["sigma"])
+    assert np.allclose(m, mh, rtol=1e-8, atol=1e-9) and np.allclose(v, vh, rtol=1e-7)
+    one = pitc.DensePITCExt(cfg, raw["xyz"], A, raw["sigma"], np.zeros_like(blocks), u, np.zeros(w.N, dtype=int),
+                            sightlines=sl)
+    for _ in range(60):
+        one.sweep(0.7)
+    assert np.max(np.abs(one.tau - o.tau) / o.tau) > 1e-3
