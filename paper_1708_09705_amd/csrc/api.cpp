@@ -2357,8 +2357,21 @@ int ep_simulate(const ep_config* cfg, int64_t n_stars, const double* xyz, const 
 // ---------------------------------------------------------------------------
 // PITC sub-catalogue EP and the PIC predictive (pitc.cpp)
 // ---------------------------------------------------------------------------
+// the sightlines at the constant prior mean (the PITC pass with the
+// extinction likelihood linearises there, as the Gaussian pass does)
+static void linearise_at_prior_mean(ep_ctx* ctx) {
+    launch_fill(ctx->stream, ctx->d_t, ctx->g.N(), ctx->pp.mean);
+    launch_los(ctx->stream, ctx->GD, ctx->SD, ctx->d_t, ctx->max_support);
+    ctx->linearised = false;
+}
+
 static PitcBorrow pitc_borrow(ep_ctx* ctx) {
     PitcBorrow b{};
+    b.ext = ctx->cfg.likelihood == EP_LIK_EXTINCTION;
+    b.d_tau = ctx->d_tau;
+    b.d_nu = ctx->d_nu;
+    b.d_qmean = ctx->d_cmu;
+    b.d_qvar = ctx->d_cvar;
     b.st = ctx->stream;
     b.g = &ctx->g;
     b.pp = &ctx->pp;
@@ -2412,8 +2425,12 @@ int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int6
         g_tls_err = "ep_pitc_setup: null context";
         return EP_ERR_INVALID_ARG;
     }
-    if (ctx->cfg.likelihood != EP_LIK_GAUSS_LINEAR) {
-        ctx->err = "ep_pitc_setup: needs likelihood GAUSS_LINEAR";
+    if (ctx->cfg.likelihood != EP_LIK_GAUSS_LINEAR && ctx->cfg.likelihood != EP_LIK_EXTINCTION) {
+        ctx->err = "ep_pitc_setup: needs likelihood GAUSS_LINEAR or EXTINCTION";
+        return EP_ERR_INVALID_ARG;
+    }
+    if (ctx->cfg.likelihood == EP_LIK_EXTINCTION && ctx->M) {
+        ctx->err = "ep_pitc_setup: with the extinction likelihood the pass takes mean_fn CONSTANT";
         return EP_ERR_INVALID_ARG;
     }
     if (n_blocks < 1 || n_inducing < 1 || !star_block || !inducing || !node_block) {
@@ -2428,7 +2445,10 @@ int ep_pitc_setup(ep_ctx* ctx, int32_t n_blocks, const int32_t* star_block, int6
     HIPCHK(host_view(dev, inducing, n_inducing, hu));
     HIPCHK(host_view(dev, node_block, ctx->g.N(), hn));
     HIPCHK(hipSetDevice(ctx->cfg.device));
-    enqueue_linearise(ctx);   // the frozen sightline weights (and h_n) at the prior mean
+    if (ctx->cfg.likelihood == EP_LIK_EXTINCTION)
+        linearise_at_prior_mean(ctx);
+    else
+        enqueue_linearise(ctx);   // the frozen sightline weights (and h_n) at the prior mean
     HIPCHK(hipStreamSynchronize(ctx->stream));
     pitc_free(ctx->pitc);
     ctx->pitc = nullptr;
@@ -2448,7 +2468,19 @@ int ep_pitc_sweep(ep_ctx* ctx, double damping, double* lnZ) {
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
     double lz = 0;
+    const bool ext = ctx->cfg.likelihood == EP_LIK_EXTINCTION;
+    // grid sweeps re-linearise the context's sightlines; the pass takes them
+    // at the prior mean
+    if (ext) linearise_at_prior_mean(ctx);
     const int rc = pitc_sweep(ctx->pitc, pitc_borrow(ctx), damping, &lz, err);
+    if (rc == EP_OK && ext) {
+        // the pass left every star's posterior marginal of a_n in the cavity
+        // arrays: cavity, tilted moments and damped site update as on the grid
+        EpParams p{0, damping, ctx->cfg.cavity_var_floor};
+        launch_tilted_update(ctx->stream, ctx->SD, p);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+    }
     if (rc == EP_OK && lnZ) *lnZ = lz;
     return pitc_status(ctx, rc, err);
 }
@@ -2461,6 +2493,7 @@ int ep_pitc_inducing(ep_ctx* ctx, double* mean, double* cov) {
     TRY(pitc_mean_at_prior(ctx, "ep_pitc_inducing"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
+    if (ctx->cfg.likelihood == EP_LIK_EXTINCTION) linearise_at_prior_mean(ctx);
     return pitc_status(ctx, pitc_inducing(ctx->pitc, pitc_borrow(ctx), mean, cov, kind_out(ctx), err), err);
 }
 
@@ -2483,6 +2516,7 @@ int ep_pitc_predict(ep_ctx* ctx, double* mean, double* var) {
     TRY(pitc_mean_at_prior(ctx, "ep_pitc_predict"));
     HIPCHK(hipSetDevice(ctx->cfg.device));
     std::string err;
+    if (ctx->cfg.likelihood == EP_LIK_EXTINCTION) linearise_at_prior_mean(ctx);
     return pitc_status(ctx, pitc_predict(ctx->pitc, pitc_borrow(ctx), mean, var, kind_out(ctx), err), err);
 }
 

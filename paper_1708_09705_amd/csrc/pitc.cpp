@@ -59,6 +59,7 @@ struct Blk {
     int64_t star0 = 0, v0 = 0, p0 = 0;     // offsets into the star list / id list
     int npad = 0, vpad = 0, ppad = 0;
     int64_t G = 0, KV = 0, KuP = 0, M1 = 0, F = 0, Kt = 0, At = 0, SAt = 0;
+    int64_t ZM = 0, TM = 0, TV = 0, CD = 0;   // extinction likelihood only
     int m = 0;
 };
 
@@ -95,7 +96,8 @@ struct PitcState {
     PitcCovDev cov{};
     FrontsDev F{};
     FactorPlan facC, facB, facQE;
-    Range tM1, tZt, tB, tKt, tD, tLam, tSig, tMu, tT1, tSigU, tMuU, tAt, tSAt;
+    Range tM1, tZt, tB, tKt, tD, tLam, tSig, tMu, tT1, tSigU, tMuU, tAt, tSAt, tPW, tTM;
+    bool ext = false;   // extinction likelihood: star sites under the PITC prior
     std::vector<void*> allocs;
     double m0 = 0, k0 = 0;
     bool swept = false;
@@ -366,6 +368,7 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         return rc;
     };
     s->cap_bytes = b.cap_bytes;
+    s->ext = b.ext;
     s->K = n_blocks;
     s->R = (int)R;
     s->rpad = (int)pad64(R);
@@ -442,8 +445,18 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     }
     s->nG = w - s->offG;
     for (auto& B : s->blk) {
-        B.m = B.npad + rpad + hb + TS + B.ppad;
+        B.m = B.npad + rpad + hb + TS + B.ppad + (s->ext ? B.npad : 0);
         maxld = std::max({maxld, B.m, B.vpad, B.npad, B.ppad});
+        if (s->ext) {
+            B.ZM = w;
+            w += (int64_t)B.npad * rpad;
+            B.TM = w;
+            w += (int64_t)B.npad * rpad;
+            B.TV = w;
+            w += B.npad;
+            B.CD = w;
+            w += B.npad;
+        }
         B.KV = w;
         w += (int64_t)B.vpad * (B.vpad + rpad + B.ppad);
         B.KuP = w;
@@ -719,6 +732,24 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
            false, nullptr, nullptr, 0, false, B.np, R + b.M, R + b.M, 0);
     end(s->tSAt);
     balance_xcd(tasks, s->tSAt.off, s->tSAt.n);
+    if (s->ext) {
+        // the marginals of a: M = Z - P^T W_Z (zm holds Z), P = L_B^{-1} S C
+        // in the extra rows, W_Z^T in the Z^T rows; then M Sigma~
+        begin(s->tPW);
+        for (const Blk& B : s->blk) {
+            const int crow = B.npad + rpad + hb + TS + B.ppad;
+            gs(B.ZM, B.npad, B.npad, rpad, false, false, false, Op{B.F + crow, B.m, false}, Op{B.F + B.npad, B.m, true},
+               B.npad, true, nullptr, nullptr, 0, false, B.nst, R, B.nst, 0);
+        }
+        end(s->tPW);
+        balance_xcd(tasks, s->tPW.off, s->tPW.n);
+        begin(s->tTM);
+        for (const Blk& B : s->blk)
+            gs(B.TM, B.npad, B.npad, rpad, true, false, false, Op{B.ZM, B.npad, false}, Op{s->offSig, xdim, false}, rpad,
+               false, nullptr, nullptr, 0, false, B.nst, R, R, 0);
+        end(s->tTM);
+        balance_xcd(tasks, s->tTM.off, s->tTM.n);
+    }
     s->flops_sweep = fs;
     s->flops_pred = fp;
 
@@ -744,6 +775,11 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
         d.npred = B.np;
         d.star0 = B.star0;
         d.pred0 = B.p0;
+        d.crow = B.npad + rpad + hb + TS + B.ppad;
+        d.zm = B.ZM;
+        d.tm = B.TM;
+        d.tv = B.TV;
+        d.cd = B.CD;
         predbase[k] = pt;
         pt += B.np;
     }
@@ -787,11 +823,12 @@ int pitc_setup(PitcState** out, const PitcBorrow& b, int32_t n_blocks, const int
     return EP_OK;
 }
 
-int pitc_sweep(PitcState* s, const PitcBorrow& b, double damping, double* lnZ, std::string& err) {
-    if (!(damping > 0.0) || damping > 1.0) {
-        err = "pitc_sweep: damping must lie in (0, 1]";
-        return EP_ERR_INVALID_ARG;
-    }
+// Everything of a pass up to q(x) = N(mu~, Sigma~): the covariance fills,
+// the fronts of C and of every sub-catalogue, the sites on x (damped by
+// 'damping' for the Gaussian likelihood; recomputed whole from the star
+// sites for the extinction likelihood), the factor of the posterior
+// precision; lnZ for the Gaussian likelihood.
+static int pass_posterior(PitcState* s, const PitcBorrow& b, double damping, std::string& err) {
     hipStream_t st = b.st;
     const int rpad = s->rpad;
     PCHK(hipMemsetAsync(s->d_err, 0, sizeof(int), st));
@@ -803,28 +840,57 @@ int pitc_sweep(PitcState* s, const PitcBorrow& b, double damping, double* lnZ, s
     for (const Range* r : {&s->tM1, &s->tZt, &s->tB, &s->tKt}) gemm_range(s, st, *r);
     if (s->M) launch_pitc_kt_j(st, s->d_blk, s->d_predbase, s->K, s->npred_tasks, s->d_ids, s->mean, s->ws);
     gemm_range(s, st, s->tD);
-    launch_pitc_block_prep(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, b.d_A, b.d_sigma, s->mean, s->ws);
+    if (s->ext)
+        launch_pitc_ext_prep(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, b.d_tau, b.d_nu, s->m0, s->ws);
+    else
+        launch_pitc_block_prep(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, b.d_A, b.d_sigma, s->mean,
+                               s->ws);
     enqueue_factor(s, st, s->facB);
     gemm_range(s, st, s->tLam);
     const int64_t e1 = s->xdim + TS;
     launch_pitc_sum_blocks(st, s->ws + s->offLam, s->K, e1 * e1, s->ws + s->offSnew);
-    launch_pitc_sites_fronts(st, s->ws + s->offSnew, s->ws + s->offSsites, damping, !s->swept, s->ws + s->offQ, s->mQ,
-                             s->ws + s->offE, s->mE, rpad, s->xdim, s->prior);
+    // with the extinction likelihood the sub-catalogues' terms on x follow
+    // from the star sites and are taken whole (the star sites are damped)
+    launch_pitc_sites_fronts(st, s->ws + s->offSnew, s->ws + s->offSsites, s->ext ? 1.0 : damping, s->ext || !s->swept,
+                             s->ws + s->offQ, s->mQ, s->ws + s->offE, s->mE, rpad, s->xdim, s->prior);
     enqueue_factor(s, st, s->facQE);
     gemm_range(s, st, s->tSig);
     gemm_range(s, st, s->tMu);
-    launch_pitc_lnz(st, s->d_blk, s->K, s->ws, s->ws + s->offE, s->mE, s->xdim, s->ws + s->offSnew, s->S,
-                    s->ln_det_s0, s->ws + s->offLnz);
+    if (!s->ext)
+        launch_pitc_lnz(st, s->d_blk, s->K, s->ws, s->ws + s->offE, s->mE, s->xdim, s->ws + s->offSnew, s->S,
+                        s->ln_det_s0, s->ws + s->offLnz);
     int bad = 0;
-    double lz = 0;
     PCHK(hipMemcpyAsync(&bad, s->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    PCHK(hipMemcpyAsync(&lz, s->ws + s->offLnz, sizeof(double), hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
     PCHK(hipGetLastError());
     if (bad) {
-        err = "pitc_sweep: a sub-catalogue or inducing covariance is not positive definite";
+        err = "pitc: a sub-catalogue or inducing covariance is not positive definite";
         return EP_ERR_NOT_PD;
     }
+    return EP_OK;
+}
+
+int pitc_sweep(PitcState* s, const PitcBorrow& b, double damping, double* lnZ, std::string& err) {
+    if (!(damping > 0.0) || damping > 1.0) {
+        err = "pitc_sweep: damping must lie in (0, 1]";
+        return EP_ERR_INVALID_ARG;
+    }
+    hipStream_t st = b.st;
+    const int rc = pass_posterior(s, b, damping, err);
+    if (rc != EP_OK) return rc;
+    double lz = std::nan("");
+    if (s->ext) {
+        // the posterior marginal of every star's a_n, for the caller's site update
+        launch_pitc_ext_mean(st, s->d_blk, s->K, s->d_stars, b.d_sptr, b.d_g, b.d_c, s->m0, s->ws + s->offMu, s->ws,
+                             b.d_qmean);
+        gemm_range(s, st, s->tPW);
+        gemm_range(s, st, s->tTM);
+        launch_pitc_ext_var(st, s->d_blk, s->K, s->d_stars, s->ws, b.d_qvar);
+    } else {
+        PCHK(hipMemcpyAsync(&lz, s->ws + s->offLnz, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    PCHK(hipStreamSynchronize(st));
+    PCHK(hipGetLastError());
     s->swept = true;
     if (lnZ) *lnZ = lz;
     return EP_OK;
@@ -836,6 +902,10 @@ int pitc_inducing(PitcState* s, const PitcBorrow& b, double* mean, double* cov, 
         return EP_ERR_STATE;
     }
     hipStream_t st = b.st;
+    if (s->ext) {   // q(x) from the current star sites
+        const int rc = pass_posterior(s, b, 1.0, err);
+        if (rc != EP_OK) return rc;
+    }
     launch_pitc_build_t(st, s->ws + s->offC, s->mC, s->d_ids + s->u0, s->R, s->rpad, s->xdim, s->mean,
                         s->ws + s->offT);
     for (const Range* r : {&s->tT1, &s->tSigU, &s->tMuU}) gemm_range(s, st, *r);
@@ -874,6 +944,10 @@ int pitc_predict(PitcState* s, const PitcBorrow& b, double* mean, double* var, h
         return EP_ERR_STATE;
     }
     hipStream_t st = b.st;
+    if (s->ext) {   // q(x) and the scaled fronts from the current star sites
+        const int rc = pass_posterior(s, b, 1.0, err);
+        if (rc != EP_OK) return rc;
+    }
     PCHK(hipMemcpyAsync(s->ws + s->offAt, s->ws + s->offKt, sizeof(double) * s->nKt, hipMemcpyDeviceToDevice, st));
     gemm_range(s, st, s->tAt);
     gemm_range(s, st, s->tSAt);

@@ -45,6 +45,12 @@ struct PitcBlockDev {
     int32_t m, npad, rpad, ppad, xdim, rrow, drow;
     int32_t nstars, npred;
     int64_t star0, pred0;
+    // extinction likelihood: npad more front rows from crow holding (S C)^T
+    // (C = Sigma_k - Z Z^T, S = diag sqrt(tau)), the unscaled Z (zm, then
+    // Z - P^T W_Z; npad x rpad), T = (Z - P^T W_Z) Sigma~ (tm), a vector of
+    // npad (tv: sqrt(tau), then w_r - W_Z mu~) and diag C (cd)
+    int32_t crow;
+    int64_t zm, tm, tv, cd;
 };
 
 // The prior mean of the field: constant m0, or (with the mean parameters in
@@ -91,6 +97,19 @@ void launch_pitc_add_mean(hipStream_t st, double* out, const int32_t* unodes, in
 // phi = phihat + mu~[rpad .. rpad + M), then Sigma~ of those slots (row-major): out (M + M^2)
 void launch_pitc_theta_out(hipStream_t st, const double* mu_t, const double* sig_t, int xdim, int rpad, int M,
                            Phi5 phihat, double* out);
+// Extinction likelihood (sites tau, nu per star; constant prior mean m0):
+// copy (S C)^T into the extra rows, diag C and the unscaled Z^T, sqrt(tau)
+// into tv; then scale B (I + S C S), Z^T, D^T by S and set the residual
+// r~ = (nu - tau mu_a) / sqrt(tau) (0 without a site).
+void launch_pitc_ext_prep(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const int64_t* sptr,
+                          const double* g, const double* c, const double* tau, const double* nu, double m0,
+                          double* ws);
+// After q(v): the posterior mean of every star's a_n (before zm turns into
+// Z - P^T W_Z), then (after that product and T) its variance.
+void launch_pitc_ext_mean(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const int64_t* sptr,
+                          const double* g, const double* c, double m0, const double* mu_t, double* ws, double* qmean);
+void launch_pitc_ext_var(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const double* ws,
+                         double* qvar);
 
 // What the block pass borrows from the EP context.
 struct PitcBorrow {
@@ -113,6 +132,13 @@ struct PitcBorrow {
     const double* d_h;
     double s0sq[8];
     double phihat[8];
+    // extinction likelihood: the pass reads the star sites and writes the
+    // posterior marginals of every a_n (the grid path's cavity arrays)
+    bool ext = false;
+    const double* d_tau = nullptr;
+    const double* d_nu = nullptr;
+    double* d_qmean = nullptr;
+    double* d_qvar = nullptr;
 };
 
 struct PitcState;

@@ -267,6 +267,122 @@ unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
+
+// ---- the extinction likelihood: star sites under the PITC prior ----------
+// The prior mean of a_n, c_n + m0 sum_q g_nq.
+__device__ __forceinline__ double ext_prior_mean(const int64_t* sptr, const double* g, const double* c, double m0,
+                                                 int32_t s) {
+    double sg = 0.0;
+    for (int64_t q = sptr[s]; q < sptr[s + 1]; q++) sg += g[q];
+    return c[s] + m0 * sg;
+}
+
+// Before the scaling (one block of threads per sub-catalogue, a thread per
+// front column i): the extra rows get column i of (S C)^T, i.e. row j holds
+// s_i C_ij, with C read from the lower tiles of the unscaled B region; diag
+// C, the unscaled Z^T (transposed into zm: element (n, r) at n + r npad) and
+// s into tv.
+__global__ __launch_bounds__(256) void k_ext_copy(const PitcBlockDev* __restrict__ blk,
+                                                  const int32_t* __restrict__ stars,
+                                                  const double* __restrict__ tau, double* __restrict__ ws) {
+    const PitcBlockDev B = blk[blockIdx.x];
+    double* F = ws + B.front;
+    const int64_t m = B.m;
+    for (int i = threadIdx.x; i < B.npad; i += blockDim.x) {
+        const bool real = i < B.nstars;
+        const double si = real ? sqrt(tau[stars[B.star0 + i]]) : 0.0;
+        for (int j = 0; j < B.npad; j++) {
+            const double cij = j >= i ? F[j + (int64_t)i * m] : F[i + (int64_t)j * m];
+            F[B.crow + j + (int64_t)i * m] = (real && j < B.nstars) ? si * cij : 0.0;
+        }
+        ws[B.cd + i] = real ? F[i + (int64_t)i * m] : 0.0;
+        ws[B.tv + i] = si;
+        for (int r = 0; r < B.rpad; r++) ws[B.zm + i + (int64_t)r * B.npad] = F[B.npad + r + (int64_t)i * m];
+    }
+}
+
+// The scaling, a thread per front column n: B <- I + S B S (the lower tiles
+// and the padding diagonal), Z^T and D^T columns times s_n, the residual
+// r~_n = (nu_n - tau_n mu_n) / s_n (0 where s_n = 0) in the residual row.
+__global__ __launch_bounds__(256) void k_ext_scale(const PitcBlockDev* __restrict__ blk,
+                                                   const int32_t* __restrict__ stars, const int64_t* __restrict__ sptr,
+                                                   const double* __restrict__ g, const double* __restrict__ c,
+                                                   const double* __restrict__ tau, const double* __restrict__ nu,
+                                                   double m0, double* __restrict__ ws) {
+    const PitcBlockDev B = blk[blockIdx.x];
+    double* F = ws + B.front;
+    const int64_t m = B.m;
+    const double* sv = ws + B.tv;
+    double* rt = F + B.rrow;
+    for (int n = threadIdx.x; n < B.npad; n += blockDim.x) {
+        const double sn = sv[n];
+        double* col = F + (int64_t)n * m;
+        for (int i = 0; i < B.npad; i++) col[i] = (i == n ? 1.0 : 0.0) + sv[i] * sn * col[i];
+        for (int r = 0; r < B.rpad; r++) col[B.npad + r] *= sn;
+        for (int p = 0; p < B.ppad; p++) col[B.drow + p] *= sn;
+        double res = 0.0;
+        if (n < B.nstars && sn > 0.0) {
+            const int32_t s = stars[B.star0 + n];
+            res = (nu[s] - tau[s] * ext_prior_mean(sptr, g, c, m0, s)) / sn;
+        }
+        rt[(int64_t)n * m] = res;
+        for (int r = 1; r < TS; r++) rt[r + (int64_t)n * m] = 0.0;
+    }
+}
+
+// tv <- w_r - W_Z mu~ (rows i of the factored front: w_r in the residual row,
+// W_Z^T in the Z^T rows), a thread per row.
+__global__ __launch_bounds__(256) void k_ext_tvec(const PitcBlockDev* __restrict__ blk, const double* __restrict__ mu_t,
+                                                  double* __restrict__ ws) {
+    const PitcBlockDev B = blk[blockIdx.x];
+    const double* F = ws + B.front;
+    const int64_t m = B.m;
+    for (int i = threadIdx.x; i < B.npad; i += blockDim.x) {
+        const double* col = F + (int64_t)i * m;
+        double t = col[B.rrow];
+        for (int r = 0; r < B.rpad; r++) t -= col[B.npad + r] * mu_t[r];
+        ws[B.tv + i] = t;
+    }
+}
+
+// E[a_n] = mu_n + Z_n . mu~ + sum_i P_in t_i, a thread per star (P_in at
+// row crow + n of column i).
+__global__ __launch_bounds__(256) void k_ext_mean(const PitcBlockDev* __restrict__ blk,
+                                                  const int32_t* __restrict__ stars, const int64_t* __restrict__ sptr,
+                                                  const double* __restrict__ g, const double* __restrict__ c, double m0,
+                                                  const double* __restrict__ mu_t, const double* __restrict__ ws,
+                                                  double* __restrict__ qmean) {
+    const PitcBlockDev B = blk[blockIdx.x];
+    const double* F = ws + B.front;
+    const int64_t m = B.m;
+    for (int n = threadIdx.x; n < B.nstars; n += blockDim.x) {
+        const int32_t s = stars[B.star0 + n];
+        double v = ext_prior_mean(sptr, g, c, m0, s);
+        for (int r = 0; r < B.rpad; r++) v += ws[B.zm + n + (int64_t)r * B.npad] * mu_t[r];
+        for (int i = 0; i < B.npad; i++) v += F[B.crow + n + (int64_t)i * m] * ws[B.tv + i];
+        qmean[s] = v;
+    }
+}
+
+// Var[a_n] = C_nn - |P_.n|^2 + (M Sigma~)_n . M_n with M = Z - P^T W_Z in zm
+// and M Sigma~ in tm, a thread per star.
+__global__ __launch_bounds__(256) void k_ext_var(const PitcBlockDev* __restrict__ blk, const int32_t* __restrict__ stars,
+                                                 const double* __restrict__ ws, double* __restrict__ qvar) {
+    const PitcBlockDev B = blk[blockIdx.x];
+    const double* F = ws + B.front;
+    const int64_t m = B.m;
+    for (int n = threadIdx.x; n < B.nstars; n += blockDim.x) {
+        double v = ws[B.cd + n];
+        for (int i = 0; i < B.npad; i++) {
+            const double p = F[B.crow + n + (int64_t)i * m];
+            v -= p * p;
+        }
+        for (int r = 0; r < B.rpad; r++)
+            v += ws[B.tm + n + (int64_t)r * B.npad] * ws[B.zm + n + (int64_t)r * B.npad];
+        qvar[stars[B.star0 + n]] = v;
+    }
+}
+
 }  // namespace
 
 void launch_pitc_kfill(hipStream_t st, const PitcKJob* jobs, const int64_t* base, int njobs, int64_t ntiles,
@@ -319,6 +435,23 @@ void launch_pitc_theta_out(hipStream_t st, const double* mu_t, const double* sig
 }
 void launch_pitc_add_mean(hipStream_t st, double* out, const int32_t* unodes, int R, PitcMeanDev mean) {
     if (R > 0) hipLaunchKernelGGL(k_add_mean, dim3(grid_for(R)), dim3(256), 0, st, out, unodes, R, mean);
+}
+void launch_pitc_ext_prep(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const int64_t* sptr,
+                          const double* g, const double* c, const double* tau, const double* nu, double m0,
+                          double* ws) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(k_ext_copy, dim3(nblk), dim3(256), 0, st, blk, stars, tau, ws);
+    hipLaunchKernelGGL(k_ext_scale, dim3(nblk), dim3(256), 0, st, blk, stars, sptr, g, c, tau, nu, m0, ws);
+}
+void launch_pitc_ext_mean(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const int64_t* sptr,
+                          const double* g, const double* c, double m0, const double* mu_t, double* ws, double* qmean) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(k_ext_tvec, dim3(nblk), dim3(256), 0, st, blk, mu_t, ws);
+    hipLaunchKernelGGL(k_ext_mean, dim3(nblk), dim3(256), 0, st, blk, stars, sptr, g, c, m0, mu_t, ws, qmean);
+}
+void launch_pitc_ext_var(hipStream_t st, const PitcBlockDev* blk, int nblk, const int32_t* stars, const double* ws,
+                         double* qvar) {
+    if (nblk > 0) hipLaunchKernelGGL(k_ext_var, dim3(nblk), dim3(256), 0, st, blk, stars, ws, qvar);
 }
 
 }  // namespace ep

@@ -21,9 +21,9 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
 
 
-def _case(n, L, stars, n_lon, n_lat, R, law="uniform", seed=31, inducing="random"):
+def _case(n, L, stars, n_lon, n_lat, R, law="uniform", seed=31, inducing="random", lik="gauss_linear"):
     w = Workload("pitc", n=n, box_pc=L, n_stars=stars, sweeps=1, star_law=law, d_max_pc=L,
-                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood="gauss_linear", seed_id=seed)
+                 noise_law="uniform", noise_a=0.05, noise_b=0.15, likelihood=lik, seed_id=seed)
     cfg = w.ep_fields()
     raw = draw(w)
     from oracle import epo
@@ -151,7 +151,7 @@ def test_pitc_errors():
     assert ei.value.code == -2
     gc.sweep()                                     # the context is still usable
     gc.close()
-    ge = E.EP(dict(cfg, likelihood="extinction", leaf_size=48), raw["xyz"], np.exp(a), raw["sigma"])
+    ge = E.EP(dict(cfg, likelihood="gmm", leaf_size=48), raw["xyz"])   # unknown distances: not on this path
     with pytest.raises(E.EPError) as ei:
         ge.pitc_setup(blocks, u, nb)
     assert ei.value.code == -1
@@ -325,3 +325,86 @@ def test_pitc_theta_full_size_properties():
     print(f"lnZ {lz1:.3f}; phi {np.round(t1, 3)}; predictive var in [{pv.min():.3e}, {pv.max():.3e}]", flush=True)
     assert np.all(np.isfinite(pm)) and np.all(pv > 0)
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# the extinction likelihood: one site per star under the PITC prior
+# ---------------------------------------------------------------------------
+EXT_CASES = [
+    dict(n=8, L=600.0, stars=150, n_lon=3, n_lat=2, R=40, lik="extinction"),
+    dict(n=9, L=800.0, stars=400, n_lon=3, n_lat=1, R=150, seed=33, lik="extinction"),
+    dict(n=10, L=1000.0, stars=500, n_lon=4, n_lat=2, R=0, law="disc", seed=35,
+         inducing=(250.0, 500.0, 750.0, 1000.0), lik="extinction"),
+]
+
+
+@pytest.mark.parametrize("kw", EXT_CASES, ids=["n8-6blk", "n9-3blk-3tiles", "n10-disc-boundary"])
+def test_pitc_extinction_matches_oracle(kw):
+    """Star sites after three damped passes, q(u) and the PIC predictive
+    against pitc.DensePITCExt; the sites live in the context's star sites."""
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, A, sl, blocks, u, nb = _case(**kw)
+    print(f"case n={kw['n']} stars={kw['stars']} blocks={blocks.max() + 1} R={len(u)}", flush=True)
+    ora = pitc.DensePITCExt(cfg, raw["xyz"], A, raw["sigma"], blocks, u, nb, sightlines=sl)
+    g = E.EP(dict(cfg, leaf_size=48), raw["xyz"], A, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    for d in (1.0, 0.7, 0.7):
+        so = ora.sweep(d)
+        lz = g.pitc_sweep(d)
+        tau, nu = g.sites()
+        print(f"sweep d={d}: tau {relerr(tau, ora.tau):.2e} nu {_rel(nu, ora.nu):.2e} "
+              f"updated {so['updated']}", flush=True)
+        assert np.allclose(tau, ora.tau, rtol=1e-8, atol=1e-10)
+        assert np.allclose(nu, ora.nu, rtol=1e-8, atol=1e-8)
+    assert np.isnan(lz)
+    om, oV = ora.posterior_u()
+    gm, gV = g.pitc_inducing()
+    pm, pv = g.pitc_predict()
+    qm, qv = ora.predict()
+    print(f"q(u): mean {relerr(gm, om):.2e} cov {_rel(gV, oV):.2e}; predictive: mean {relerr(pm, qm):.2e} "
+          f"var {relerr(pv, qv):.2e}", flush=True)
+    assert relerr(gm, om) < 1e-8 and _rel(gV, oV) < 1e-8
+    assert relerr(pm, qm) < 1e-8 and relerr(pv, qv) < 1e-8
+    g.close()
+
+
+def test_pitc_extinction_errors():
+    from paper_1708_09705_amd import ep as E
+    w, cfg, raw, A, sl, blocks, u, nb = _case(n=8, L=600.0, stars=100, n_lon=2, n_lat=1, R=20, lik="extinction")
+    g = E.EP(dict(cfg, leaf_size=48, mean_fn="disc_bump"), raw["xyz"], A, raw["sigma"])
+    with pytest.raises(E.EPError) as ei:
+        g.pitc_setup(blocks, u, nb)
+    assert ei.value.code == -1
+    g.close()
+
+
+def test_pitc_extinction_full_size_properties():
+    """The bench shape with the extinction likelihood (64^3 grid, 100,000 disc
+    stars, 160 on-sky sub-catalogues, boundary inducing nodes): after damped
+    passes every site is finite and non-negative, every star's posterior
+    marginal of a_n has a positive variance, q(u) is symmetric positive
+    definite and the predictive variances lie in (0, prior variance]."""
+    from paper_1708_09705_amd import ep as E
+    w = preset(2)
+    cfg = w.ep_fields()
+    raw = draw(w)
+    f, A = E.ep_simulate(E.make_config(cfg), raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+    blocks = sky_cells(w, raw["xyz"], 40, 4)
+    u = boundary_inducing(w, 40, 4, (1000.0, 2000.0, 3000.0, 4000.0))
+    nb = sky_cells(w, node_positions(w), 40, 4)
+    g = E.EP(dict(cfg, leaf_size=512), raw["xyz"], A, raw["sigma"])
+    g.pitc_setup(blocks, u, nb)
+    for _ in range(4):
+        g.pitc_sweep(0.7)
+    tau, nu = g.sites()
+    st = g.star_state()
+    mu_u, Vu = g.pitc_inducing()
+    pm, pv = g.pitc_predict()
+    g.close()
+    print(f"sites > 0: {int((tau > 0).sum())} of {tau.size}; predictive var {pv.min():.3e}..{pv.max():.3e}", flush=True)
+    assert np.all(np.isfinite(tau)) and np.all(np.isfinite(nu)) and np.all(tau >= 0)
+    assert (tau > 0).sum() > 0.99 * tau.size
+    assert np.all(st["cav_var"][tau > 0] > 0)
+    assert np.allclose(Vu, Vu.T, rtol=0, atol=1e-12 * np.abs(Vu).max())
+    assert np.linalg.eigvalsh(Vu).min() > 0
+    assert np.all(np.isfinite(pm)) and np.all(pv > 0) and np.all(pv <= cfg["prior_var"] * (1 + 1e-9))
