@@ -457,7 +457,8 @@ int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *o
  * predictive (Sec. 4.1, App. A.1, App. B, App. C) ----
  * Needs a context with likelihood GAUSS_LINEAR: the observed
  * log-extinctions a~_n ~ N(a_n, sigma_n^2) with a_n = c_n + g_n . f the
- * sightline linearised at the prior mean (Sec. 4.1's Gaussian case),
+ * sightline linearised at the prior mean (Sec. 4.1's Gaussian case), or
+ * EXTINCTION with mean_fn CONSTANT (below),
  * f ~ N(m, K), K the tapered covariance between nodes (not the Vecchia
  * precision: this path is the paper's alternative to it).  Stars are split
  * into sub-catalogues k; u = f at R inducing nodes.  Blocks are independent
@@ -469,15 +470,26 @@ int ep_point_predict(ep_ctx *ctx, int64_t n_pairs, const double *xyz2, double *o
  * and the sites are on (u, psi) (the paper's q(u, Theta)), psi = ln theta -
  * phihat with its log-normal hyperprior.  Every block's tilted distribution
  * is Gaussian, so one undamped sweep reaches the fixed point.
+ * With the extinction likelihood, A_n ~ N(e^{a_n}, sigma_n^2), every star
+ * keeps its own Gaussian site on a_n (the context's star sites, as on the
+ * grid path; ep_sites / ep_set_sites read and write them) and the
+ * sub-catalogues enter through the PITC prior of a: a pass builds q(u) and
+ * each star's posterior marginal of a_n from the current sites, then updates
+ * every site from its cavity and tilted moments (damped by 'damping'; the
+ * grid path's skip rules and cavity_var_floor).  Several passes are needed;
+ * lnZ is NaN; ep_pitc_inducing and ep_pitc_predict rebuild q(u) from the
+ * current sites.  (The paper keeps one site per sub-catalogue and samples
+ * its tilted distribution.)
  * Memory: per sub-catalogue O((N_k + R + P_k) N_k + V_k (V_k + R + P_k))
- * doubles, V_k the nodes its sightlines touch and P_k the nodes it predicts.
+ * doubles, V_k the nodes its sightlines touch and P_k the nodes it predicts
+ * (with the extinction likelihood N_k more rows of N_k).
  *
  * ep_pitc_setup: star_block (n_stars int32, values 0..n_blocks-1, every
  * block non-empty), inducing (n_inducing >= 1 distinct node ids),
  * node_block (n^3 int32: the sub-catalogue whose stars each node's
  * prediction conditions on).  Plans and allocates; replaces an earlier set-up
  * and its sites.  Errors: INVALID_ARG (ranges, empty block, duplicate
- * inducing node, wrong likelihood), OOM/DEVICE.
+ * inducing node, likelihood GMM, EXTINCTION with DISC_BUMP), OOM/DEVICE.
  * With the mean parameters the pass takes the context's mean linearised at
  * the hyperprior mean; once grid sweeps (ep_sweep) have moved that
  * linearisation (the Gaussian mode re-linearises the mean unless relinearize
