@@ -96,6 +96,7 @@ struct ep_ctx {
     std::string err = "no error";
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
+    int64_t n_cu = 256;   // compute units of the device (the GEMM schedules' round size)
     // deterministic mode: clique windows, right-hand-side node lists, the
     // forward solve's per-level update lists and their staging vector
     int64_t n_win = 0;
@@ -357,14 +358,27 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
                             tasks.push_back(t);
                         }
             };
-            // pieces of at least 8 K tiles, enough to give ~2 blocks per CU
-            // (none in the deterministic mode: the pieces add atomically)
+            // K pieces per block: the launch's blocks are dealt to the CUs in
+            // rounds (one block per CU at a time), so with equal tasks its
+            // time is rounds x (per-task start and store + K tiles per
+            // piece); the start and store cost about two K tiles.  Pieces of
+            // at least 4 tiles; none in the deterministic mode (the pieces add
+            // atomically).
             const bool nosplit = ctx->cfg.deterministic != 0;
-            auto split_for = [nosplit](int64_t nblocks, int nk) {
+            const int64_t ncu = ctx->n_cu;
+            auto split_for = [nosplit, ncu](int64_t nblocks, int nk) {
                 if (nblocks <= 0 || nosplit) return 1;
-                int64_t sp = (512 + nblocks - 1) / nblocks;
-                sp = std::min<int64_t>(sp, std::max(1, nk / 8));
-                return (int)std::max<int64_t>(1, sp);
+                int best = 1;
+                double tbest = 1e300;
+                for (int sp = 1; sp <= std::max(1, nk / 4); sp++) {
+                    const int64_t rounds = (nblocks * sp + ncu - 1) / ncu;
+                    const double t = (double)rounds * (2.0 + (double)((nk + sp - 1) / sp));
+                    if (t < tbest * (1.0 - 1e-9)) {
+                        tbest = t;
+                        best = sp;
+                    }
+                }
+                return best;
             };
             TaskRange pt, ft;
             pt.off = (int64_t)tasks.size();
@@ -887,6 +901,11 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     std::vector<int32_t> flists;
     std::vector<BatchEnt> batches;
     std::vector<GemmTask> tasks;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess && cus > 0)
+            ctx->n_cu = cus;
+    }
     TRY(build_plans(ctx, flists, batches, tasks));
     // Q0 entries -> front positions
     Q0Table q0;
