@@ -34,8 +34,8 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE x 1.000), divided by 186.  Taken for the kernel and task lists
 # as they are; set to None whenever either changes until the counters are
 # taken again.
-TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 1.4934e12 / 186, "write_bytes_per_launch": 7.6525e10 / 186,
-                      "bytes_per_launch": (1.4934e12 + 7.6525e10) / 186, "launches_per_sweep": 186,
+TRAFFIC_GEMM_TASKS = {"fetch_bytes_per_launch": 1.5179e12 / 186, "write_bytes_per_launch": 8.6965e10 / 186,
+                      "bytes_per_launch": (1.5179e12 + 8.6965e10) / 186, "launches_per_sweep": 186,
                       "source": "profiles/k_gemm_tasks_64cube_100k_traffic.md"}
 
 
