@@ -441,6 +441,16 @@ static int build_plans(ep_ctx* ctx, std::vector<int32_t>& flists, std::vector<Ba
             fx.emplace_back(f, P_of(f));
             fr.emplace_back(f, MR);
         }
+        // the in-panel update of step k factors step k + 1's diagonal tiles
+        // inside a panel: its launch must hold exactly that step's fronts
+        for (int k = 0; k + 1 < (int)P.potrf.size(); k++) {
+            if ((k + 1) % PW == 0) continue;
+            const Launch& in = P.inner[k];
+            const FList& nx = P.potrf[k + 1];
+            if (in.nbe != nx.n) return EP_ERR_INVALID_ARG;
+            for (int q = 0; q < in.nbe; q++)
+                if (batches[in.be_off + q].front != flists[nx.off + q]) return EP_ERR_INVALID_ARG;
+        }
         P.extend = mk_launch(ea);
         {   // group r: the r-th child (in this level) of every parent
             std::map<int, int> rank;
@@ -1227,14 +1237,19 @@ static void enqueue_factor(ep_ctx* ctx) {
             kt_begin(ctx, pu.n);
             launch_gemm_tasks(st, ctx->d_tasks + pu.off, pu.n, b, false);
             kt_end(ctx, pu.n, EP_KK_TRAIL);
-            launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
+            // inside a panel the diagonal tile of step k was factored by step
+            // k - 1's in-panel update, whose launch holds the same fronts
+            if (k % PW == 0)
+                launch_potrf(st, ctx->d_flists + P.potrf[k].off, P.potrf[k].n, (int)k, ctx->F, b, ctx->d_err);
             const Launch& t = P.trsm[k];
             kt_begin(ctx, t.ntasks);
             launch_trsm_step(st, ctx->d_batches + t.be_off, t.nbe, t.ntasks, (int)k, ctx->F, b);
             kt_end(ctx, t.ntasks, EP_KK_TRSM);
             const Launch& s = P.inner[k];
+            const bool factor_next = (k + 1) % PW != 0 && k + 1 < P.potrf.size();
             kt_begin(ctx, s.ntasks);
-            launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b);
+            launch_syrk_inner(st, ctx->d_batches + s.be_off, s.nbe, s.ntasks, (int)k, ctx->F, b,
+                              factor_next ? ctx->d_err : nullptr);
             kt_end(ctx, s.ntasks, EP_KK_INNER);
             const TaskRange& fu = P.finalT[k];
             kt_begin(ctx, fu.n);

@@ -88,7 +88,10 @@ void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, boo
 void launch_gemm_tasks_f32(hipStream_t st, const GemmTask* t, int64_t n, float* F32);
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
-void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b);
+// factor_err non-null: the launch also factors the diagonal tile of column
+// kk + 1 of every front in it (the next step's potrf), errors as launch_potrf
+void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b,
+                       int* factor_err = nullptr);
 void launch_extend_add(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);
 // the same with at most one child per parent in the launch: no atomics
 void launch_extend_add_plain(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, FrontsDev F, Bufs b);

@@ -444,17 +444,30 @@ template <typename FT> __device__ __forceinline__ FT* fronts_of(const Bufs& b);
 template <> __device__ __forceinline__ double* fronts_of<double>(const Bufs& b) { return b.fronts; }
 template <> __device__ __forceinline__ float* fronts_of<float>(const Bufs& b) { return b.F32; }
 
+// LDS ordering within one wave: the lanes' LDS writes are seen by the
+// lanes' later reads (one wave, so no barrier is needed beyond keeping the
+// compiler and the counters in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wave (lane = threadIdx.x & 63): Cholesky of tile (k, k) of front f in
+// place, and the inverse of the factor into X.  T: TS x LDP doubles of LDS,
+// dinv: TS doubles of LDS.
 template <typename FT>
-__global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
-                                              int* err) {
-    __shared__ double T[TS * LDP];
-    const int f = flist[blockIdx.x];
+__device__ __forceinline__ void potrf_tile(int f, int k, const FrontsDev& F, const Bufs& bufs, int* err, double* T,
+                                           double* dinv) {
     const int m = F.m[f];
     FT* A = fronts_of<FT>(bufs) + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
-    const int i = threadIdx.x;
+    const int i = threadIdx.x & 63;
     double a[TS];
 #pragma unroll
-    for (int c = 0; c < TS; c++) a[c] = (double)A[i + (int64_t)c * m];
+    for (int c = 0; c < TS; c++) {
+        a[c] = (double)A[i + (int64_t)c * m];
+        if (c % 16 == 15) __builtin_amdgcn_sched_barrier(0);   // 16 loads in flight at a time
+    }
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < TS; j++) {
@@ -467,6 +480,7 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
         a[j] = (i == j) ? l : a[j] / l;   // rows above j hold unused values
 #pragma unroll
         for (int c = j + 1; c < TS; c++) a[c] -= a[j] * lane_bcast(a[j], c);
+        __builtin_amdgcn_sched_barrier(0);
     }
     // L (zeros above the diagonal) to the front and to LDS
 #pragma unroll
@@ -475,9 +489,9 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
         A[i + (int64_t)c * m] = (FT)v;
         T[i * LDP + c] = v;
     }
-    __shared__ double dinv[TS];
+    wave_sync();
     dinv[i] = 1.0 / T[i * LDP + i];
-    __syncthreads();
+    wave_sync();
     // X = L^{-1}: lane j solves L x = e_j column by column, so the updates of
     // one step are independent (no chain of dependent FMAs through a sum)
     double x[TS];
@@ -488,16 +502,28 @@ __global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist,
         x[q] *= dinv[q];
 #pragma unroll
         for (int r = q + 1; r < TS; r++) x[r] -= T[r * LDP + q] * x[q];
+        __builtin_amdgcn_sched_barrier(0);   // keeps the LDS reads of later steps from piling up in registers
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int r = 0; r < TS; r++) T[r * LDP + i] = x[r];
-    __syncthreads();
+    wave_sync();
     double* Xk = bufs.X + F.xoff[f] + (int64_t)TS * k + (int64_t)TS * k * F.nvpad[f];
     const int ldx = F.nvpad[f];
 #pragma unroll
-    for (int c = 0; c < TS; c++) Xk[i + (int64_t)c * ldx] = T[i * LDP + c];
+    for (int c = 0; c < TS; c++) {
+        Xk[i + (int64_t)c * ldx] = T[i * LDP + c];
+        if (c % 16 == 15) __builtin_amdgcn_sched_barrier(0);
+    }
     if (i == 0 && bad) atomicCAS(err, 0, f + 1);
+}
+
+template <typename FT>
+__global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
+                                              int* err) {
+    __shared__ double T[TS * LDP];
+    __shared__ double dinv[TS];
+    potrf_tile<FT>(flist[blockIdx.x], k, F, bufs, err, T, dinv);
 }
 
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
@@ -531,8 +557,12 @@ __global__ __launch_bounds__(256) void k_trsm_step(const BatchEnt* __restrict__ 
 // In-panel update at pivot step kk (left-looking): column j = kk + 1 of the
 // panel, rows i >= j, takes the updates of the panel's pivot columns
 // k0 .. kk (K = kk - k0 + 1 tiles), once, after the column solve of kk.
-__global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks, int kk,
-                                                    FrontsDev F, Bufs bufs) {
+// FACTOR: the block of the diagonal tile (j, j), whose update is then
+// complete, goes on to factor it (the next pivot step's diagonal tile) with
+// its first wave while the other blocks update the rest of the column.
+template <bool FACTOR>
+__global__ __launch_bounds__(256, 2) void k_syrk_inner(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
+                                                       int kk, FrontsDev F, Bufs bufs, int* err) {
     __shared__ double sA[TS * LDP];
     __shared__ double sB[TS * LDP];
     const int64_t t = blockIdx.x;
@@ -548,15 +578,25 @@ __global__ __launch_bounds__(256) void k_syrk_inner(const BatchEnt* __restrict__
     seg_run(acc, sA, sB, base + (int64_t)TS * i + (int64_t)TS * k0 * m, (int64_t)TS * m, m, false, -1.0,
             base + (int64_t)TS * j + (int64_t)TS * k0 * m, (int64_t)TS * m, m, true, kk - k0 + 1);
     tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
+    if (FACTOR && i == j) {   // uniform over the block
+        __syncthreads();      // the tile's stores are visible to the block
+        if (threadIdx.x < 64) potrf_tile<double>(f, j, F, bufs, err, sA, sB);
+    }
 }
 
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(k_trsm_step, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, k, F, b);
 }
-void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b) {
+void launch_syrk_inner(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int kk, FrontsDev F, Bufs b,
+                       int* factor_err) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_syrk_inner, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b);
+    if (factor_err)
+        hipLaunchKernelGGL(k_syrk_inner<true>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b,
+                           factor_err);
+    else
+        hipLaunchKernelGGL(k_syrk_inner<false>, dim3((unsigned)ntasks), dim3(256), 0, st, be, nbe, ntasks, kk, F, b,
+                           factor_err);
 }
 
 // ---------------------------------------------------------------------------
