@@ -453,43 +453,57 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One wave (lane = threadIdx.x & 63): Cholesky of tile (k, k) of front f in
-// place, and the inverse of the factor into X.  T: TS x LDP doubles of LDS,
-// dinv: TS doubles of LDS.
+// A block of four waves, all of whose threads call this: Cholesky of tile
+// (k, k) of front f in place, and the inverse of the factor into X.  Lane i
+// holds row i and wave w the columns c = 4 t + w (t = 0..15), so each pivot
+// step updates about a quarter of the later columns per wave.  The pivot
+// column goes through LDS (C; row i at (i mod 4) 16 + i / 4, so that the
+// entries of a wave's columns are contiguous), one barrier per step.  The
+// inverse is forward substitution by the first wave, lane j solving for
+// column j of X.  T: TS x LDP doubles of LDS; C: TS x TS + TS doubles.
 template <typename FT>
 __device__ __forceinline__ void potrf_tile(int f, int k, const FrontsDev& F, const Bufs& bufs, int* err, double* T,
-                                           double* dinv) {
+                                           double* C) {
     const int m = F.m[f];
     FT* A = fronts_of<FT>(bufs) + F.off[f] + (int64_t)TS * k + (int64_t)TS * k * m;
-    const int i = threadIdx.x & 63;
-    double a[TS];
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int pi = (i & 3) * 16 + (i >> 2);
+    double a[16];
 #pragma unroll
-    for (int c = 0; c < TS; c++) {
-        a[c] = (double)A[i + (int64_t)c * m];
-        if (c % 16 == 15) __builtin_amdgcn_sched_barrier(0);   // 16 loads in flight at a time
-    }
+    for (int t = 0; t < 16; t++) a[t] = (double)A[i + (int64_t)(4 * t + w) * m];
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < TS; j++) {
-        double d = lane_bcast(a[j], j);
-        if (!(d > 0.0) || !isfinite(d)) {
-            bad = true;
-            d = 1.0;
+        const int s = j >> 2;
+        if (w == (j & 3)) {   // the wave holding column j
+            double d = lane_bcast(a[s], j);
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = true;
+                d = 1.0;
+            }
+            const double l = sqrt(d);
+            a[s] = (i == j) ? l : a[s] / l;   // rows above j hold unused values
+            C[j * TS + pi] = a[s];
         }
-        const double l = sqrt(d);
-        a[j] = (i == j) ? l : a[j] / l;   // rows above j hold unused values
+        __syncthreads();
+        const double lij = C[j * TS + pi];
+        const double* cj = C + j * TS + 16 * w;   // L(4 t + w, j) at cj[t]
+        if (w > (j & 3)) a[s] -= lij * cj[s];     // column 4 s + w comes after j
 #pragma unroll
-        for (int c = j + 1; c < TS; c++) a[c] -= a[j] * lane_bcast(a[j], c);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int t = s + 1; t < 16; t++) a[t] -= lij * cj[t];
     }
     // L (zeros above the diagonal) to the front and to LDS
 #pragma unroll
-    for (int c = 0; c < TS; c++) {
-        const double v = (i >= c) ? a[c] : 0.0;
+    for (int t = 0; t < 16; t++) {
+        const int c = 4 * t + w;
+        const double v = (i >= c) ? a[t] : 0.0;
         A[i + (int64_t)c * m] = (FT)v;
         T[i * LDP + c] = v;
     }
-    wave_sync();
+    if (i == 0 && bad) atomicCAS(err, 0, f + 1);
+    __syncthreads();
+    if (w != 0) return;
+    double* dinv = C + TS * TS;
     dinv[i] = 1.0 / T[i * LDP + i];
     wave_sync();
     // X = L^{-1}: lane j solves L x = e_j column by column, so the updates of
@@ -515,20 +529,19 @@ __device__ __forceinline__ void potrf_tile(int f, int k, const FrontsDev& F, con
         Xk[i + (int64_t)c * ldx] = T[i * LDP + c];
         if (c % 16 == 15) __builtin_amdgcn_sched_barrier(0);
     }
-    if (i == 0 && bad) atomicCAS(err, 0, f + 1);
 }
 
 template <typename FT>
-__global__ __launch_bounds__(64) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
-                                              int* err) {
+__global__ __launch_bounds__(256) void k_potrf(const int32_t* __restrict__ flist, int k, FrontsDev F, Bufs bufs,
+                                               int* err) {
     __shared__ double T[TS * LDP];
-    __shared__ double dinv[TS];
-    potrf_tile<FT>(flist[blockIdx.x], k, F, bufs, err, T, dinv);
+    __shared__ double C[TS * TS + TS];
+    potrf_tile<FT>(flist[blockIdx.x], k, F, bufs, err, T, C);
 }
 
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_potrf<double>, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
+    hipLaunchKernelGGL(k_potrf<double>, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -558,8 +571,8 @@ __global__ __launch_bounds__(256) void k_trsm_step(const BatchEnt* __restrict__ 
 // panel, rows i >= j, takes the updates of the panel's pivot columns
 // k0 .. kk (K = kk - k0 + 1 tiles), once, after the column solve of kk.
 // FACTOR: the block of the diagonal tile (j, j), whose update is then
-// complete, goes on to factor it (the next pivot step's diagonal tile) with
-// its first wave while the other blocks update the rest of the column.
+// complete, goes on to factor it (the next pivot step's diagonal tile)
+// while the other blocks update the rest of the column.
 template <bool FACTOR>
 __global__ __launch_bounds__(256, 2) void k_syrk_inner(const BatchEnt* __restrict__ be, int nbe, int64_t ntasks,
                                                        int kk, FrontsDev F, Bufs bufs, int* err) {
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_inner(const BatchEnt* __restric
     tile_store(acc, sA, base + (int64_t)TS * i + (int64_t)TS * j * m, m, 0);
     if (FACTOR && i == j) {   // uniform over the block
         __syncthreads();      // the tile's stores are visible to the block
-        if (threadIdx.x < 64) potrf_tile<double>(f, j, F, bufs, err, sA, sB);
+        potrf_tile<double>(f, j, F, bufs, err, sA, sB);
     }
 }
 
@@ -1748,7 +1761,7 @@ void launch_to_f32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, 
 }
 void launch_potrf32(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err) {
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_potrf<float>, dim3(nf), dim3(64), 0, st, flist, k, F, b, err);
+    hipLaunchKernelGGL(k_potrf<float>, dim3(nf), dim3(256), 0, st, flist, k, F, b, err);
 }
 void launch_trsm32(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b) {
     if (ntasks <= 0) return;
