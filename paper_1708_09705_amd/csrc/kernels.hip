@@ -426,11 +426,8 @@ void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, boo
 // Diagonal tile: Cholesky of tile (k,k) of each listed front, and the
 // inverse of the factor (kept in X as the diagonal tile of L11^{-1}).
 // ---------------------------------------------------------------------------
-// One wave per tile, lane i holding row i of the tile in registers.  The
-// right-looking column steps broadcast the pivot and the column entries with
-// readlane (the loops are fully unrolled, so every register index is static);
-// the inverse is forward substitution with lane j holding column j of X and
-// the rows of L read from LDS at wave-uniform addresses.
+// One block of four waves per tile (potrf_tile below); the loops are fully
+// unrolled, so every register index is static.
 __device__ __forceinline__ double lane_bcast(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
