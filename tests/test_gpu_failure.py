@@ -33,6 +33,33 @@ def test_not_pd_leaves_state_unchanged():
     g.close()
 
 
+def test_not_pd_at_pivots_inside_panels():
+    """Fronts of several pivot tiles (16^3 nodes, leaves of up to 512): the
+    diagonal tiles after a panel's first are factored inside the in-panel
+    update's launch.  One strongly negative site at a time puts the first
+    failing pivot wherever that star's clique is eliminated; each sweep must
+    raise NOT_PD and leave the sites and the linearisation point unchanged."""
+    E = _E()
+    cfg, gcfg, raw, f, A, sl = small_case(n=16, L=1000.0, stars=200, leaf=512)
+    g = E.EP(gcfg, raw["xyz"], A, raw["sigma"])
+    g.sweep()
+    tau, nu = g.sites()
+    f0 = g.linpoint()
+    for s in range(0, 200, 25):
+        bad = tau.copy()
+        bad[s] = -1e8
+        g.set_sites(bad, nu)
+        with pytest.raises(E.EPError) as ei:
+            g.sweep()
+        assert ei.value.name == "NOT_PD", (s, ei.value.name)
+        t2, n2 = g.sites()
+        assert np.array_equal(t2, bad) and np.array_equal(n2, nu)
+        assert np.array_equal(g.linpoint(), f0)
+    g.set_sites(tau, nu)
+    g.sweep()
+    g.close()
+
+
 def test_allocation_cap_gives_oom():
     E = _E()
     cfg, gcfg, raw, f, A, sl = small_case(n=8, L=500.0, stars=60, leaf=32)
