@@ -97,11 +97,19 @@ struct ep_ctx {
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
     int64_t n_cu = 256;   // compute units of the device (the GEMM schedules' round size)
-    // deterministic mode: clique windows, right-hand-side node lists, the
-    // forward solve's per-level update lists and their staging vector
-    int64_t n_win = 0;
-    int32_t *d_wfront = nullptr, *d_istar = nullptr, *d_ilo = nullptr, *d_ihi = nullptr, *d_nstar = nullptr;
-    int64_t *d_wptr = nullptr, *d_nptr = nullptr, *d_nslot = nullptr;
+    // clique assembly by tile owner: incidences, chunks, multi-chunk tiles,
+    // partial tiles, local rows in each star's sorted slot order, and g in
+    // that order (refreshed every sweep)
+    TileInc* d_tinc = nullptr;
+    TileChunk* d_tch = nullptr;
+    TileRed* d_tred = nullptr;
+    double *d_tpart = nullptr, *d_gsort = nullptr;
+    int32_t* d_lsort = nullptr;
+    int64_t n_tch = 0, n_tred = 0;
+    // deterministic mode: right-hand-side node lists, the forward solve's
+    // per-level update lists and their staging vector
+    int32_t* d_nstar = nullptr;
+    int64_t *d_nptr = nullptr, *d_nslot = nullptr;
     double* d_stage = nullptr;
     struct DetLevel {
         int64_t n = 0;
@@ -754,75 +762,133 @@ static Phi5 phi5(const double* v) {
     return p;
 }
 
+// Clique assembly by tile owner (host, once).  A star's slots, sorted by
+// local row in its front, fall into runs by 64-row tile; every pair of runs
+// (u >= v) is an incidence of tile (run u's tile, run v's tile).  The
+// incidences are grouped by tile (star order inside a tile) and cut into
+// chunks of bounded work for one wave each; a tile with several chunks gets
+// partial tiles that a second launch sums in chunk order.  Chunks are
+// launched heaviest first.  Work of an incidence: its 8 x 8 pair blocks and
+// the staging of its slots.
+constexpr int64_t TILE_CHUNK_WORK = 4096;
+static int build_tile_assembly(ep_ctx* ctx, const std::vector<int32_t>& sord) {
+    const Symbolic& sym = ctx->sym;
+    const int64_t S = ctx->S;
+    const auto& ptr = ctx->sup.ptr;
+    const int64_t nslots = (int64_t)ctx->sup.nodes.size();
+    std::vector<int32_t> lsort((size_t)nslots);
+    for (int64_t st = 0; st < S; st++)
+        for (int64_t q = ptr[st]; q < ptr[st + 1]; q++) lsort[q] = sym.star_loc[ptr[st] + sord[q]];
+    const int64_t nf = (int64_t)sym.fronts.size();
+    std::vector<int64_t> tbase((size_t)nf + 1, 0);
+    for (int64_t f = 0; f < nf; f++) {
+        const int64_t M = sym.fronts[f].m / TS;
+        tbase[f + 1] = tbase[f] + M * (M + 1) / 2;
+    }
+    const int64_t ntiles = tbase[nf];
+    // runs of one star: (tile, first sorted position, count)
+    auto runs = [&](int64_t st, std::vector<std::array<int64_t, 3>>& r) {
+        r.clear();
+        for (int64_t q = ptr[st]; q < ptr[st + 1]; q++) {
+            const int64_t t = lsort[q] / TS;
+            if (r.empty() || r.back()[0] != t) r.push_back({t, q, 0});
+            r.back()[2]++;
+        }
+    };
+    auto tile_id = [&](int64_t f, int64_t tu, int64_t tv) { return tbase[f] + tu * (tu + 1) / 2 + tv; };
+    std::vector<int64_t> cnt((size_t)ntiles + 1, 0);
+    std::vector<std::array<int64_t, 3>> r;
+    for (int64_t st = 0; st < S; st++) {
+        runs(st, r);
+        const int64_t f = sym.star_front[st];
+        for (size_t u = 0; u < r.size(); u++)
+            for (size_t v = 0; v <= u; v++) cnt[tile_id(f, r[u][0], r[v][0]) + 1]++;
+    }
+    for (int64_t t = 0; t < ntiles; t++) cnt[t + 1] += cnt[t];
+    const int64_t ninc = cnt[ntiles];
+    std::vector<TileInc> incs((size_t)ninc);
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t st = 0; st < S; st++) {
+            runs(st, r);
+            const int64_t f = sym.star_front[st];
+            for (size_t u = 0; u < r.size(); u++)
+                for (size_t v = 0; v <= u; v++) {
+                    TileInc& I = incs[(size_t)fill[tile_id(f, r[u][0], r[v][0])]++];
+                    I.rpos = r[u][1];
+                    I.cpos = r[v][1];
+                    I.star = (int32_t)st;
+                    I.nr = (int16_t)r[u][2];
+                    I.nc = (int16_t)r[v][2];
+                }
+        }
+    }
+    std::vector<TileChunk> chunks;
+    std::vector<int64_t> work;
+    std::vector<TileRed> reds;
+    int32_t nparts = 0;
+    for (int64_t f = 0; f < nf; f++) {
+        const int64_t M = sym.fronts[f].m / TS;
+        for (int64_t ti = 0; ti < M; ti++)
+            for (int64_t tj = 0; tj <= ti; tj++) {
+                const int64_t id = tile_id(f, ti, tj);
+                if (cnt[id + 1] == cnt[id]) continue;
+                const size_t c0 = chunks.size();
+                int64_t e = cnt[id];
+                while (e < cnt[id + 1]) {
+                    TileChunk C{};
+                    C.i0 = e;
+                    C.f = (int32_t)f;
+                    C.ti = (int32_t)ti;
+                    C.tj = (int32_t)tj;
+                    C.part = -1;
+                    int64_t w = 0;
+                    while (e < cnt[id + 1] && (w == 0 || w < TILE_CHUNK_WORK)) {
+                        const TileInc& I = incs[(size_t)e];
+                        w += 2 + (int64_t)((I.nr + 7) / 8) * ((I.nc + 7) / 8);
+                        e++;
+                    }
+                    C.n = (int32_t)(e - C.i0);
+                    chunks.push_back(C);
+                    work.push_back(w);
+                }
+                const int np = (int)(chunks.size() - c0);
+                if (np > 1) {
+                    TileRed R{};
+                    R.f = (int32_t)f;
+                    R.ti = (int32_t)ti;
+                    R.tj = (int32_t)tj;
+                    R.p0 = nparts;
+                    R.np = np;
+                    reds.push_back(R);
+                    for (int q = 0; q < np; q++) chunks[c0 + q].part = nparts++;
+                }
+            }
+    }
+    std::vector<int64_t> ord(chunks.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+    std::vector<TileChunk> sorted(chunks.size());
+    for (size_t q = 0; q < ord.size(); q++) sorted[q] = chunks[(size_t)ord[q]];
+    ctx->n_tch = (int64_t)sorted.size();
+    ctx->n_tred = (int64_t)reds.size();
+    TRY(upload(ctx, &ctx->d_lsort, lsort));
+    TRY(upload(ctx, &ctx->d_tinc, incs));
+    TRY(upload(ctx, &ctx->d_tch, sorted));
+    TRY(upload(ctx, &ctx->d_tred, reds));
+    TRY(dev_alloc(ctx, &ctx->d_tpart, (int64_t)nparts * TS * TS));
+    TRY(dev_alloc(ctx, &ctx->d_gsort, nslots));
+    return EP_OK;
+}
+
 // The deterministic mode's fixed summation orders (host, once):
-//  * clique windows: for every front, 4-column windows; a window lists the
-//    stars of the front with support nodes in its columns, in star order,
-//    with the range of the star's sorted slots that falls in it; windows are
-//    ordered heaviest first (their pairs), so the long ones start early;
 //  * right-hand side: for every node, its slots in star order;
 //  * forward solve: for every level, every updated row with the positions
 //    (rptr + local row) of the level's fronts that update it, in front order.
-// columns per clique window: at 64^3 / 100k the assembly takes 223, 166, 138
-// and 130 ms per sweep with 64-, 16-, 8- and 4-column windows (the chains of
-// stars through the busiest columns set the time)
-constexpr int DET_WINDOW = 4;
-static int build_deterministic(ep_ctx* ctx, const std::vector<int32_t>& sord) {
+static int build_deterministic(ep_ctx* ctx) {
     const Symbolic& sym = ctx->sym;
     const int64_t S = ctx->S, N = ctx->g.N();
     const auto& ptr = ctx->sup.ptr;
-    {
-        std::unordered_map<int64_t, int64_t> key;
-        std::vector<int32_t> wf;
-        std::vector<std::vector<std::array<int32_t, 3>>> inc;
-        std::vector<double> weight;
-        for (int64_t st = 0; st < S; st++) {
-            const int64_t p0 = ptr[st];
-            const int cnt = (int)(ptr[st + 1] - p0);
-            const int32_t f = sym.star_front[st];
-            int k = 0;
-            while (k < cnt) {
-                const int32_t w = sym.star_loc[p0 + sord[p0 + k]] / DET_WINDOW;
-                int k1 = k + 1;
-                while (k1 < cnt && sym.star_loc[p0 + sord[p0 + k1]] / DET_WINDOW == w) k1++;
-                const int64_t kk = ((int64_t)f << 32) | (uint32_t)w;
-                auto it = key.find(kk);
-                int64_t wi;
-                if (it == key.end()) {
-                    wi = (int64_t)wf.size();
-                    key.emplace(kk, wi);
-                    wf.push_back(f);
-                    inc.emplace_back();
-                    weight.push_back(0.0);
-                } else {
-                    wi = it->second;
-                }
-                inc[wi].push_back({(int32_t)st, k, k1});
-                for (int b = k; b < k1; b++) weight[wi] += (double)(cnt - b);
-                weight[wi] += 64.0;   // the wait between stars
-                k = k1;
-            }
-        }
-        std::vector<int64_t> ord(wf.size());
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return weight[a] > weight[b]; });
-        std::vector<int32_t> wfront, istar, ilo, ihi;
-        std::vector<int64_t> wptr(1, 0);
-        for (int64_t wi : ord) {
-            wfront.push_back(wf[wi]);
-            for (const auto& e : inc[wi]) {
-                istar.push_back(e[0]);
-                ilo.push_back(e[1]);
-                ihi.push_back(e[2]);
-            }
-            wptr.push_back((int64_t)istar.size());
-        }
-        ctx->n_win = (int64_t)wfront.size();
-        TRY(upload(ctx, &ctx->d_wfront, wfront));
-        TRY(upload(ctx, &ctx->d_wptr, wptr));
-        TRY(upload(ctx, &ctx->d_istar, istar));
-        TRY(upload(ctx, &ctx->d_ilo, ilo));
-        TRY(upload(ctx, &ctx->d_ihi, ihi));
-    }
     {
         std::vector<int64_t> nptr((size_t)N + 1, 0);
         for (int64_t q = 0; q < (int64_t)ctx->sup.nodes.size(); q++) nptr[(size_t)ctx->sup.nodes[q] + 1]++;
@@ -1067,7 +1133,8 @@ static int init_impl(ep_ctx* ctx, const double* xyz, const double* A, const doub
     }
     TRY(upload(ctx, &ctx->d_sfront, sym.star_front));
     TRY(upload(ctx, &ctx->d_nsamp, ctx->sup.nsamp));
-    if (c.deterministic) TRY(build_deterministic(ctx, sord));
+    TRY(build_tile_assembly(ctx, sord));
+    if (c.deterministic) TRY(build_deterministic(ctx));
     const int64_t nG = (int64_t)ctx->sup.nodes.size();
     TRY(dev_alloc(ctx, &ctx->d_g, nG));
     double** sarr[] = {&ctx->d_lnA, &ctx->d_c, &ctx->d_tau, &ctx->d_nu, &ctx->d_cmu, &ctx->d_cvar, &ctx->d_lnZ,
@@ -1184,24 +1251,19 @@ static int enqueue_assemble(ep_ctx* ctx) {
     kt_end(ctx, ctx->zero_lower.ntasks, EP_KK_ZERO);
     launch_scatter_set(st, ctx->d_fronts, ctx->d_q0_dest, ctx->d_q0_val, ctx->n_q0);
     launch_scatter_const(st, ctx->d_fronts, ctx->d_pad_dest, ctx->n_pad, 1.0);
-    // the atomic adds of the cliques contend less in the stars' input order
-    // than in the grouped order the cavity reads in (measured 28.5 against
-    // 30.5 ms per sweep at 64^3 / 100k)
     StarsDev sd = ctx->SD;
     sd.order = nullptr;
+    kt_begin(ctx, ctx->S);
+    launch_sort_g(st, sd, ctx->d_gsort, (int64_t)ctx->sup.nodes.size());
+    launch_assemble_tiles(st, ctx->d_tch, ctx->n_tch, ctx->d_tinc, ctx->d_tau, ctx->d_gsort, ctx->d_lsort, ctx->F,
+                          ctx->d_fronts, ctx->d_tpart);
+    launch_tiles_reduce(st, ctx->d_tred, ctx->n_tred, ctx->d_tpart, ctx->F, ctx->d_fronts);
+    kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
+    HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));
     if (ctx->cfg.deterministic) {
-        kt_begin(ctx, ctx->S);
-        launch_assemble_windows(st, sd, ctx->F, ctx->d_fronts, ctx->d_wfront, ctx->d_wptr, ctx->d_istar, ctx->d_ilo,
-                                ctx->d_ihi, ctx->n_win);
-        kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
-        HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));
         launch_assemble_b_nodes(st, sd, ctx->d_nptr, ctx->d_nslot, ctx->d_nstar, ctx->d_borig, ctx->g.N());
         return EP_OK;
     }
-    kt_begin(ctx, ctx->S);
-    launch_assemble_stars(st, sd, ctx->F, ctx->d_fronts, ctx->max_support);
-    kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
-    HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));
     launch_assemble_b(st, sd, ctx->d_borig);
     return EP_OK;
 }

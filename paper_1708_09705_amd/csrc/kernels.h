@@ -64,6 +64,32 @@ struct FrontsDev {
     const int32_t* relmap;  // R rows as local rows of the parent front
 };
 
+// Clique assembly by tile owner.  A star's clique entries that fall in one
+// 64 x 64 tile of its front form an incidence: the star's slots, sorted by
+// local row, whose rows lie in the tile's row range (nr of them, from rpos)
+// and those whose rows lie in its column range (nc, from cpos).
+struct TileInc {
+    int64_t rpos;   // absolute position of the first row slot in the sorted slot arrays
+    int64_t cpos;   // same, first column slot
+    int32_t star;
+    int16_t nr, nc;
+};
+// A run of one tile's incidences, applied in order by one wave.
+struct TileChunk {
+    int64_t i0;     // first incidence
+    int32_t n;      // incidences
+    int32_t f;      // front
+    int32_t ti, tj; // tile row and column in the front (ti >= tj)
+    int32_t part;   // -1: the tile has this chunk only and it adds into the front; else its partial-tile slot
+    int32_t pad;
+};
+// A tile assembled in several chunks: their partial tiles, summed in order.
+struct TileRed {
+    int32_t f, ti, tj;
+    int32_t p0, np;
+    int32_t pad;
+};
+
 // Per-front task batch entry for implicitly enumerated tile tasks.
 struct BatchEnt {
     int32_t front;
@@ -190,12 +216,15 @@ void launch_cavity_border(hipStream_t st, StarsDev s, const double* W, const dou
 void launch_f_mean(hipStream_t st, const double* mhat, const double* J, const double* mu_d, BorderDev b, double* out,
                    int64_t N);
 void launch_f_var(hipStream_t st, const double* W, const double* J, BorderDev b, double* var, int64_t N);
-void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int max_support);
+// clique assembly: g in the sorted slot order, then the tile chunks, then
+// the sums of the tiles assembled in several chunks (fixed orders throughout)
+void launch_sort_g(hipStream_t st, StarsDev s, double* gs, int64_t nslots);
+void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const double* tau,
+                           const double* gs, const int32_t* ls, FrontsDev F, double* fronts, double* parts);
+void launch_tiles_reduce(hipStream_t st, const TileRed* red, int64_t nred, const double* parts, FrontsDev F,
+                         double* fronts);
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b);
-// deterministic forms of the two above (fixed summation order, no atomics)
-void launch_assemble_windows(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, const int32_t* wfront,
-                             const int64_t* wptr, const int32_t* istar, const int32_t* ilo, const int32_t* ihi,
-                             int64_t nwin);
+// deterministic form of the above (fixed summation order, no atomics)
 void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, const int64_t* nslot,
                              const int32_t* nstar, double* b, int64_t N);
 void launch_gather_perm(hipStream_t st, const int32_t* perm, const double* src, double* dst, int64_t n);

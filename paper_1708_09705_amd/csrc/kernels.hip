@@ -1106,36 +1106,156 @@ void launch_los(hipStream_t st, GridDev g, StarsDev s, const double* f, int cap)
 // Assembly of the sites into the fronts: tau_n g_n g_n^T lands in the front
 // of the star's first-eliminated support node (its whole clique is there).
 // ---------------------------------------------------------------------------
-// One wave per star: its clique P_n x P_n (lower triangle, support nodes in
-// ascending local row) gets tau g g^T.  Column b by column b, the lanes take
-// consecutive rows a >= b, so one wave's atomic adds fall in neighbouring
-// cache lines.
-__global__ __launch_bounds__(256) void k_assemble_stars(StarsDev s, FrontsDev F, double* fronts, int cap) {
-    extern __shared__ char smem[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int32_t* sl = (int32_t*)smem + w * cap;
-    double* sg = (double*)(smem + ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16) + w * cap;
-    const int64_t star = star_of_slot(s, (int64_t)blockIdx.x * 4 + w);
-    if (star < 0) return;
-    const double tau = s.tau[star];
-    if (tau == 0.0) return;
-    const int64_t p0 = s.ptr[star];
-    const int cnt = (int)(s.ptr[star + 1] - p0);
-    for (int k = lane; k < cnt; k += 64) {
-        const int slot = s.sord[p0 + k];
-        sl[k] = s.loc[p0 + slot];
-        sg[k] = s.g[p0 + slot];
-    }
+// Clique assembly by tile owner.  Every front tile that star cliques touch
+// is assembled by one wave (or, when it has many incidences, by several
+// waves whose partial tiles are then summed in order): the wave accumulates
+// tau g_a g_b of each of its incidences in a 64 x 64 LDS tile, incidence after
+// incidence in star order, and adds the tile to the front once.  No global
+// atomics, and every summation order is fixed, so the result is
+// reproducible bit for bit.
+__global__ void k_sort_g(const int64_t* __restrict__ ptr, const int32_t* __restrict__ sord,
+                         const double* __restrict__ g, double* __restrict__ gs, int64_t S) {
+    // one wave per star: gs[p0 + k] = g[p0 + sord[p0 + k]]
+    const int64_t star = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (star >= S) return;
+    const int64_t p0 = ptr[star], p1 = ptr[star + 1];
+    for (int64_t q = p0 + (threadIdx.x & 63); q < p1; q += 64) gs[q] = g[p0 + sord[q]];
+}
+
+__device__ __forceinline__ int64_t lane_bcast64(int64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One incidence's slot data held by the lanes: lane j < nr holds row slot j,
+// lane j < nc column slot j.
+struct IncData {
+    double rg, cg;
+    int32_t rl, cl;
+};
+
+constexpr int TA_DEPTH = 16;   // incidences whose slot data is in flight ahead of the ones applied
+
+// Order of one wave's LDS accesses: the LDS executes a wave's instructions in
+// order, so the compiler only has to keep them in program order (no wait).
+__device__ __forceinline__ void wave_order() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0);
-    const int f = s.front[star];
-    double* base = fronts + F.off[f];
-    const int64_t m = F.m[f];
-    for (int b = 0; b < cnt; b++) {
-        const double tg = tau * sg[b];
-        double* col = base + (int64_t)sl[b] * m;
-        for (int a = b + lane; a < cnt; a += 64) atomicAdd(col + sl[a], tg * sg[a]);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restrict__ ch, const TileInc* __restrict__ inc,
+                                                       const double* __restrict__ tau, const double* __restrict__ gs,
+                                                       const int32_t* __restrict__ ls, FrontsDev F, double* fronts,
+                                                       double* __restrict__ parts) {
+    __shared__ double T[TS * LDP];
+    __shared__ double sr[TS], sc[TS];
+    __shared__ int32_t lr[TS], lc[TS];
+    const TileChunk C = ch[blockIdx.x];
+    const int lane = threadIdx.x;
+    for (int q = lane; q < TS * LDP; q += 64) T[q] = 0.0;
+    const int rb = TS * C.ti, cb = TS * C.tj;
+    const bool diag = C.ti == C.tj;
+    for (int64_t e0 = C.i0; e0 < C.i0 + C.n; e0 += 64) {
+        const int nb = (int)std::min<int64_t>(64, C.i0 + C.n - e0);
+        // lane j holds incidence e0 + j
+        const TileInc I = inc[e0 + (lane < nb ? lane : nb - 1)];
+        const int64_t rp = I.rpos, cp = I.cpos;
+        const int nrc = ((int)I.nr << 16) | (int)I.nc;
+        const double t = tau[I.star];
+        // loads without branches (indices clamped into the incidence and the
+        // batch), so that their waits fall where the data is used
+        auto fetch = [&](int j, IncData& D) {
+            const int jj = j < nb ? j : nb - 1;
+            const int64_t r0 = lane_bcast64(rp, jj), c0 = lane_bcast64(cp, jj);
+            const int x = __builtin_amdgcn_readlane(nrc, jj);
+            const int nr = x >> 16, nc = x & 0xffff;
+            const int ia = lane < nr ? lane : nr - 1, ib = lane < nc ? lane : nc - 1;
+            D.rl = ls[r0 + ia] - rb;
+            D.rg = gs[r0 + ia];
+            D.cl = ls[c0 + ib] - cb;
+            D.cg = gs[c0 + ib];
+        };
+        IncData cur[TA_DEPTH], nxt[TA_DEPTH];
+#pragma unroll
+        for (int d = 0; d < TA_DEPTH; d++) fetch(d, cur[d]);
+        for (int j0 = 0; j0 < nb; j0 += TA_DEPTH) {
+#pragma unroll
+            for (int d = 0; d < TA_DEPTH; d++) fetch(j0 + TA_DEPTH + d, nxt[d]);
+#pragma unroll
+            for (int d = 0; d < TA_DEPTH; d++) {
+                const int j = j0 + d;
+                if (j >= nb) break;
+                const double tj = lane_bcast(t, j);
+                const int x = __builtin_amdgcn_readlane(nrc, j);
+                const int nr = x >> 16, nc = x & 0xffff;
+                if (tj == 0.0) continue;
+                // stage the slots (the previous incidence's reads of the
+                // staging arrays precede these writes in this wave's LDS order)
+                wave_order();
+                lr[lane] = cur[d].rl;
+                sr[lane] = tj * cur[d].rg;
+                lc[lane] = cur[d].cl;
+                sc[lane] = cur[d].cg;
+                wave_order();
+                // lanes take 8 x 8 blocks of (row slot, column slot) pairs; within
+                // one incidence every pair is a different tile entry.  LDS adds
+                // without return: the wave does not wait for them, and the LDS
+                // applies one wave's instructions in order, so every entry's
+                // sum runs in incidence order
+                for (int a0 = 0; a0 < nr; a0 += 8)
+                    for (int b0 = 0; b0 < nc; b0 += 8) {
+                        const int a = a0 + (lane >> 3), b = b0 + (lane & 7);
+                        if (a < nr && b < nc && (!diag || a >= b)) atomicAdd(&T[lr[a] * LDP + lc[b]], sr[a] * sc[b]);
+                    }
+            }
+#pragma unroll
+            for (int d = 0; d < TA_DEPTH; d++) cur[d] = nxt[d];
+        }
     }
+    wave_order();
+    if (C.part < 0) {
+        const int64_t m = F.m[C.f];
+        double* dst = fronts + F.off[C.f] + rb + (int64_t)cb * m;
+#pragma unroll 8
+        for (int c = 0; c < TS; c++) dst[lane + c * m] += T[lane * LDP + c];
+    } else {
+        double* dst = parts + (int64_t)C.part * TS * TS;
+#pragma unroll 8
+        for (int c = 0; c < TS; c++) dst[lane + c * TS] = T[lane * LDP + c];
+    }
+}
+
+// Tiles assembled in several chunks: their partial tiles summed in chunk
+// order and added to the front (one wave per tile, lane = tile row).
+__global__ __launch_bounds__(64) void k_tiles_reduce(const TileRed* __restrict__ red, const double* __restrict__ parts,
+                                                     FrontsDev F, double* fronts) {
+    const TileRed R = red[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int64_t m = F.m[R.f];
+    double* dst = fronts + F.off[R.f] + TS * R.ti + (int64_t)TS * R.tj * m;
+    for (int c = 0; c < TS; c++) {
+        double v = 0.0;
+        for (int q = 0; q < R.np; q++) v += parts[(int64_t)(R.p0 + q) * TS * TS + lane + c * TS];
+        dst[lane + c * m] += v;
+    }
+}
+
+void launch_sort_g(hipStream_t st, StarsDev s, double* gs, int64_t nslots) {
+    (void)nslots;
+    if (s.n <= 0) return;
+    hipLaunchKernelGGL(k_sort_g, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s.ptr, s.sord, s.g, gs, s.n);
+}
+void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const double* tau,
+                           const double* gs, const int32_t* ls, FrontsDev F, double* fronts, double* parts) {
+    if (nch <= 0) return;
+    hipLaunchKernelGGL(k_assemble_tiles, dim3((unsigned)nch), dim3(64), 0, st, ch, inc, tau, gs, ls, F, fronts, parts);
+}
+void launch_tiles_reduce(hipStream_t st, const TileRed* red, int64_t nred, const double* parts, FrontsDev F,
+                         double* fronts) {
+    if (nred <= 0) return;
+    hipLaunchKernelGGL(k_tiles_reduce, dim3((unsigned)nred), dim3(64), 0, st, red, parts, F, fronts);
 }
 
 __global__ void k_assemble_b(StarsDev s, double* b) {
@@ -1147,44 +1267,6 @@ __global__ void k_assemble_b(StarsDev s, double* b) {
     const int64_t p0 = s.ptr[star];
     const int cnt = (int)(s.ptr[star + 1] - p0);
     for (int k = lane; k < cnt; k += 64) atomicAdd(b + s.nodes[p0 + k], coef * s.g[p0 + k]);
-}
-
-// Deterministic clique assembly: one wave per column window of a front;
-// the window's incidences (stars of the front with support nodes in those
-// columns, in star order; the star's sorted slots [b_lo, b_hi) fall in the
-// window) are applied one after the other.  Within one star every entry
-// (a, b), a >= b, is distinct, so the lanes add without atomics; the wait
-// between stars orders the read-modify-writes of one entry by star.
-__global__ __launch_bounds__(64) void k_assemble_windows(StarsDev s, FrontsDev F, double* fronts,
-                                                         const int32_t* __restrict__ wfront,
-                                                         const int64_t* __restrict__ wptr,
-                                                         const int32_t* __restrict__ istar,
-                                                         const int32_t* __restrict__ ilo,
-                                                         const int32_t* __restrict__ ihi, int64_t nwin) {
-    const int64_t w = blockIdx.x;
-    if (w >= nwin) return;
-    const int lane = threadIdx.x;
-    const int f = wfront[w];
-    double* base = fronts + F.off[f];
-    const int64_t m = F.m[f];
-    for (int64_t e = wptr[w]; e < wptr[w + 1]; e++) {
-        const int32_t star = istar[e];
-        const double tau = s.tau[star];
-        if (tau == 0.0) continue;
-        const int64_t p0 = s.ptr[star];
-        const int cnt = (int)(s.ptr[star + 1] - p0);
-        for (int b = ilo[e]; b < ihi[e]; b++) {
-            const int sb = s.sord[p0 + b];
-            const double tg = tau * s.g[p0 + sb];
-            double* col = base + (int64_t)s.loc[p0 + sb] * m;
-            for (int a = b + lane; a < cnt; a += 64) {
-                const int sa = s.sord[p0 + a];
-                double* p = col + s.loc[p0 + sa];
-                *p = *p + tg * s.g[p0 + sa];
-            }
-        }
-        __syncthreads();
-    }
 }
 
 // Deterministic right-hand side: b[node] += sum over the node's slots (in
@@ -1201,14 +1283,6 @@ __global__ void k_assemble_b_nodes(StarsDev s, const int64_t* __restrict__ nptr,
     }
 }
 
-void launch_assemble_windows(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, const int32_t* wfront,
-                             const int64_t* wptr, const int32_t* istar, const int32_t* ilo, const int32_t* ihi,
-                             int64_t nwin) {
-    if (nwin <= 0) return;
-    hipLaunchKernelGGL(k_assemble_windows, dim3((unsigned)nwin), dim3(64), 0, st, s, F, fronts, wfront, wptr, istar,
-                       ilo, ihi, nwin);
-}
-
 void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, const int64_t* nslot,
                              const int32_t* nstar, double* b, int64_t N) {
     if (N <= 0) return;
@@ -1216,11 +1290,6 @@ void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, co
     hipLaunchKernelGGL(k_assemble_b_nodes, dim3(blocks), dim3(256), 0, st, s, nptr, nslot, nstar, b, N);
 }
 
-void launch_assemble_stars(hipStream_t st, StarsDev s, FrontsDev F, double* fronts, int cap) {
-    if (s.n <= 0) return;
-    size_t sh = ((size_t)4 * cap * sizeof(int32_t) + 15) / 16 * 16 + (size_t)4 * cap * sizeof(double);
-    hipLaunchKernelGGL(k_assemble_stars, dim3(star_blocks(s)), dim3(256), sh, st, s, F, fronts, cap);
-}
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b) {
     if (s.n <= 0) return;
     hipLaunchKernelGGL(k_assemble_b, dim3(star_blocks(s)), dim3(256), 0, st, s, b);
