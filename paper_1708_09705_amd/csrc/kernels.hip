@@ -1270,24 +1270,30 @@ __global__ void k_assemble_b(StarsDev s, double* b) {
 }
 
 // Deterministic right-hand side: b[node] += sum over the node's slots (in
-// star order) of (nu - tau c) g, one thread per node.
-__global__ void k_assemble_b_nodes(StarsDev s, const int64_t* __restrict__ nptr, const int64_t* __restrict__ nslot,
-                                   const int32_t* __restrict__ nstar, double* b, int64_t N) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
-        double v = b[p];
-        for (int64_t e = nptr[p]; e < nptr[p + 1]; e++) {
-            const int32_t star = nstar[e];
-            v += (s.nu[star] - s.tau[star] * s.c[star]) * s.g[nslot[e]];
-        }
-        b[p] = v;
+// star order) of (nu - tau c) g, one wave per node: lane l sums the slots
+// l, l + 64, ... in order, then a fixed butterfly adds the lanes.  (The
+// nodes next to the observer lie on every sightline.)
+__global__ __launch_bounds__(256) void k_assemble_b_nodes(StarsDev s, const int64_t* __restrict__ nptr,
+                                                          const int64_t* __restrict__ nslot,
+                                                          const int32_t* __restrict__ nstar, double* b, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= N) return;
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int64_t e = nptr[p] + lane; e < nptr[p + 1]; e += 64) {
+        const int32_t star = nstar[e];
+        v += (s.nu[star] - s.tau[star] * s.c[star]) * s.g[nslot[e]];
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) b[p] += v;
 }
 
 void launch_assemble_b_nodes(hipStream_t st, StarsDev s, const int64_t* nptr, const int64_t* nslot,
                              const int32_t* nstar, double* b, int64_t N) {
     if (N <= 0) return;
-    const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_assemble_b_nodes, dim3(blocks), dim3(256), 0, st, s, nptr, nslot, nstar, b, N);
+    hipLaunchKernelGGL(k_assemble_b_nodes, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, s, nptr, nslot, nstar, b,
+                       N);
 }
 
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b) {
