@@ -139,7 +139,8 @@ def sparse_kernels(st, stats, N) -> dict:
         gbs = b / (ms * 1e-3) / 1e9
         out[k] = {"ms_per_step": ms, "launches_per_step": int(stats[-1]["kernel_launches"][k]),
                   "algorithmic_bytes_per_step": int(b), "GBps": gbs, "frac_of_hbm_peak": gbs / PEAK_HBM_GBS}
-    out["note"] = ("zero: k_zero_lower; assemble: k_assemble_stars (L2 FP64 atomics); extend: k_extend_add; "
+    out["note"] = ("zero: k_zero_lower; assemble: k_sort_g + k_assemble_tiles + k_tiles_reduce (tile owner, LDS); "
+                   "extend: k_extend_add; "
                    "gather: k_sigma_gather; cavity: k_cavity; solve: k_fwd_xv/k_fwd_r/k_bwd_t/k_bwd_x")
     return out
 

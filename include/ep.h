@@ -128,12 +128,12 @@ typedef struct ep_config {
     double relin_step;
     /* 1: a sweep's results are bitwise reproducible run to run on the same
      * device and inputs.  The floating-point atomic adds of the sweep are
-     * replaced by sums in a fixed order: the star cliques are added front
-     * column by column (4-column windows), star by star; the right-hand side node by
-     * node over its stars; the forward solve's update rows node by node over
-     * the level's fronts; the trailing updates are not split along K.
-     * Needs precision FP64 and mean_fn CONSTANT; slower (the assembly above
-     * all).  0: the default, atomic adds (results agree to rounding). */
+     * replaced by sums in a fixed order: the right-hand side node by node
+     * over its stars; the forward solve's update rows node by node over the
+     * level's fronts; the trailing updates are not split along K.  (The star
+     * cliques are summed in a fixed order in either mode.)  Needs precision
+     * FP64 and mean_fn CONSTANT; slower (the unsplit trailing updates).
+     * 0: the default, atomic adds (results agree to rounding). */
     int32_t deterministic;
 } ep_config;
 
