@@ -815,11 +815,11 @@ static int build_tile_assembly(ep_ctx* ctx, const std::vector<int32_t>& sord) {
             for (size_t u = 0; u < r.size(); u++)
                 for (size_t v = 0; v <= u; v++) {
                     TileInc& I = incs[(size_t)fill[tile_id(f, r[u][0], r[v][0])]++];
-                    I.rpos = r[u][1];
-                    I.cpos = r[v][1];
                     I.star = (int32_t)st;
-                    I.nr = (int16_t)r[u][2];
-                    I.nc = (int16_t)r[v][2];
+                    I.r0 = (uint16_t)(r[u][1] - ptr[st]);
+                    I.c0 = (uint16_t)(r[v][1] - ptr[st]);
+                    I.nr = (uint16_t)r[u][2];
+                    I.nc = (uint16_t)r[v][2];
                 }
         }
     }
@@ -1255,8 +1255,8 @@ static int enqueue_assemble(ep_ctx* ctx) {
     sd.order = nullptr;
     kt_begin(ctx, ctx->S);
     launch_sort_g(st, sd, ctx->d_gsort, (int64_t)ctx->sup.nodes.size());
-    launch_assemble_tiles(st, ctx->d_tch, ctx->n_tch, ctx->d_tinc, ctx->d_tau, ctx->d_gsort, ctx->d_lsort, ctx->F,
-                          ctx->d_fronts, ctx->d_tpart);
+    launch_assemble_tiles(st, ctx->d_tch, ctx->n_tch, ctx->d_tinc, ctx->d_sptr, ctx->d_tau, ctx->d_gsort,
+                          ctx->d_lsort, ctx->F, ctx->d_fronts, ctx->d_tpart);
     launch_tiles_reduce(st, ctx->d_tred, ctx->n_tred, ctx->d_tpart, ctx->F, ctx->d_fronts);
     kt_end(ctx, ctx->S, EP_KK_ASSEMBLE);
     HIPCHK(hipMemcpyAsync(ctx->d_borig, ctx->d_b0, sizeof(double) * ctx->g.N(), hipMemcpyDeviceToDevice, st));

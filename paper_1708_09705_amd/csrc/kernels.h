@@ -69,10 +69,9 @@ struct FrontsDev {
 // local row, whose rows lie in the tile's row range (nr of them, from rpos)
 // and those whose rows lie in its column range (nc, from cpos).
 struct TileInc {
-    int64_t rpos;   // absolute position of the first row slot in the sorted slot arrays
-    int64_t cpos;   // same, first column slot
     int32_t star;
-    int16_t nr, nc;
+    uint16_t r0, c0;   // first row slot, first column slot: positions in the star's sorted slots
+    uint16_t nr, nc;
 };
 // A run of one tile's incidences, applied in order by one wave.
 struct TileChunk {
@@ -219,8 +218,9 @@ void launch_f_var(hipStream_t st, const double* W, const double* J, BorderDev b,
 // clique assembly: g in the sorted slot order, then the tile chunks, then
 // the sums of the tiles assembled in several chunks (fixed orders throughout)
 void launch_sort_g(hipStream_t st, StarsDev s, double* gs, int64_t nslots);
-void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const double* tau,
-                           const double* gs, const int32_t* ls, FrontsDev F, double* fronts, double* parts);
+void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const int64_t* ptr,
+                           const double* tau, const double* gs, const int32_t* ls, FrontsDev F, double* fronts,
+                           double* parts);
 void launch_tiles_reduce(hipStream_t st, const TileRed* red, int64_t nred, const double* parts, FrontsDev F,
                          double* fronts);
 void launch_assemble_b(hipStream_t st, StarsDev s, double* b);

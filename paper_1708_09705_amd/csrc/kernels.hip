@@ -1146,9 +1146,9 @@ __device__ __forceinline__ void wave_order() {
 }
 
 __global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restrict__ ch, const TileInc* __restrict__ inc,
-                                                       const double* __restrict__ tau, const double* __restrict__ gs,
-                                                       const int32_t* __restrict__ ls, FrontsDev F, double* fronts,
-                                                       double* __restrict__ parts) {
+                                                       const int64_t* __restrict__ ptr, const double* __restrict__ tau,
+                                                       const double* __restrict__ gs, const int32_t* __restrict__ ls,
+                                                       FrontsDev F, double* fronts, double* __restrict__ parts) {
     __shared__ double T[TS * LDP];
     __shared__ double sr[TS], sc[TS];
     __shared__ int32_t lr[TS], lc[TS];
@@ -1161,7 +1161,8 @@ __global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restri
         const int nb = (int)std::min<int64_t>(64, C.i0 + C.n - e0);
         // lane j holds incidence e0 + j
         const TileInc I = inc[e0 + (lane < nb ? lane : nb - 1)];
-        const int64_t rp = I.rpos, cp = I.cpos;
+        const int64_t p0 = ptr[I.star];
+        const int64_t rp = p0 + I.r0, cp = p0 + I.c0;
         const int nrc = ((int)I.nr << 16) | (int)I.nc;
         const double t = tau[I.star];
         // loads without branches (indices clamped into the incidence and the
@@ -1247,10 +1248,12 @@ void launch_sort_g(hipStream_t st, StarsDev s, double* gs, int64_t nslots) {
     if (s.n <= 0) return;
     hipLaunchKernelGGL(k_sort_g, dim3((unsigned)((s.n + 3) / 4)), dim3(256), 0, st, s.ptr, s.sord, s.g, gs, s.n);
 }
-void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const double* tau,
-                           const double* gs, const int32_t* ls, FrontsDev F, double* fronts, double* parts) {
+void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, const TileInc* inc, const int64_t* ptr,
+                           const double* tau, const double* gs, const int32_t* ls, FrontsDev F, double* fronts,
+                           double* parts) {
     if (nch <= 0) return;
-    hipLaunchKernelGGL(k_assemble_tiles, dim3((unsigned)nch), dim3(64), 0, st, ch, inc, tau, gs, ls, F, fronts, parts);
+    hipLaunchKernelGGL(k_assemble_tiles, dim3((unsigned)nch), dim3(64), 0, st, ch, inc, ptr, tau, gs, ls, F, fronts,
+                       parts);
 }
 void launch_tiles_reduce(hipStream_t st, const TileRed* red, int64_t nred, const double* parts, FrontsDev F,
                          double* fronts) {

@@ -98,12 +98,28 @@ extern "C" int ep_plan(const ep_config* c, int64_t S, const double* xyz, ep_plan
     for (int64_t w : wlev) p.w_elems = std::max(p.w_elems, w);
     // what ep_init allocates beside the fronts, X and W: every dense buffer's
     // read pad, the stars' CSR rows (node, local row, slot order, g), their
-    // per-star state, the node vectors, the prior's rows and the Q0 scatter
-    // list (its entries on the factor's pattern, about half the stencil per
-    // node); the GEMM task lists are not counted
+    // per-star state, the clique assembly's incidences, the node vectors, the
+    // prior's rows and the Q0 scatter list (its entries on the factor's
+    // pattern, about half the stencil per node); the GEMM task lists are not
+    // counted
     const int64_t pad = 256 * sym.max_m + 256;
     const int64_t dense = 8 * (sym.total_elems + p.x_elems + p.w_elems + 3 * pad);
-    const int64_t stars = nnz * (8 + 3 * 4) + S * 30 * 8;
+    // the clique assembly's (star, tile) incidences: a star whose slots fall
+    // in r runs of 64 local rows has r (r + 1) / 2 of them, 12 bytes each,
+    // plus at most 32 bytes each of partial tiles; its sorted local rows and g
+    int64_t incid = 0;
+    {
+        std::vector<int32_t> loc;
+        for (int64_t s = 0; s < S; s++) {
+            loc.assign(sym.star_loc.begin() + sup.ptr[s], sym.star_loc.begin() + sup.ptr[s + 1]);
+            std::sort(loc.begin(), loc.end());
+            int64_t r = 0;
+            for (size_t k = 0; k < loc.size(); k++)
+                if (k == 0 || loc[k] / TS != loc[k - 1] / TS) r++;
+            incid += r * (r + 1) / 2;
+        }
+    }
+    const int64_t stars = nnz * (8 + 3 * 4) + S * 30 * 8 + incid * (12 + 32) + nnz * 12;
     const int64_t vectors = N * 24 * 8 + N * (int64_t)(st.full.size() / 3) * 8;
     p.device_bytes = dense + stars + vectors;
     p.device_bytes_mixed = p.device_bytes + 4 * (sym.total_elems + pad);
