@@ -1135,7 +1135,7 @@ struct IncData {
     int32_t rl, cl;
 };
 
-constexpr int TA_DEPTH = 16;   // incidences whose slot data is in flight ahead of the ones applied
+constexpr int TA_DEPTH = 8;   // incidences whose slot data is in flight ahead of the ones applied
 
 // Order of one wave's LDS accesses: the LDS executes a wave's instructions in
 // order, so the compiler only has to keep them in program order (no wait).
@@ -1145,16 +1145,26 @@ __device__ __forceinline__ void wave_order() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restrict__ ch, const TileInc* __restrict__ inc,
-                                                       const int64_t* __restrict__ ptr, const double* __restrict__ tau,
-                                                       const double* __restrict__ gs, const int32_t* __restrict__ ls,
-                                                       FrontsDev F, double* fronts, double* __restrict__ parts) {
+// One block of four waves per chunk; wave w owns rows 16 w .. 16 w + 15 of
+// the tile and runs through all the chunk's incidences, applying only the
+// pairs whose row is its own (the rows of an incidence are sorted, so they
+// are a contiguous range; a wave with none skips the incidence).  The waves
+// share nothing, so no barrier, and each entry's sum runs in incidence order.
+__global__ __launch_bounds__(256) void k_assemble_tiles(const TileChunk* __restrict__ ch, const TileInc* __restrict__ inc,
+                                                        const int64_t* __restrict__ ptr, const double* __restrict__ tau,
+                                                        const double* __restrict__ gs, const int32_t* __restrict__ ls,
+                                                        FrontsDev F, double* fronts, double* __restrict__ parts) {
     __shared__ double T[TS * LDP];
-    __shared__ double sr[TS], sc[TS];
-    __shared__ int32_t lr[TS], lc[TS];
+    __shared__ double sr_all[4][TS], sc_all[4][TS];
+    __shared__ int32_t lr_all[4][TS], lc_all[4][TS];
     const TileChunk C = ch[blockIdx.x];
-    const int lane = threadIdx.x;
-    for (int q = lane; q < TS * LDP; q += 64) T[q] = 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double* sr = sr_all[w];
+    double* sc = sc_all[w];
+    int32_t* lr = lr_all[w];
+    int32_t* lc = lc_all[w];
+    double* Tw = T + 16 * w * LDP;   // this wave's 16 rows
+    for (int q = lane; q < 16 * LDP; q += 64) Tw[q] = 0.0;
     const int rb = TS * C.ti, cb = TS * C.tj;
     const bool diag = C.ti == C.tj;
     for (int64_t e0 = C.i0; e0 < C.i0 + C.n; e0 += 64) {
@@ -1191,7 +1201,10 @@ __global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restri
                 const double tj = lane_bcast(t, j);
                 const int x = __builtin_amdgcn_readlane(nrc, j);
                 const int nr = x >> 16, nc = x & 0xffff;
-                if (tj == 0.0) continue;
+                // this wave's rows of the incidence: a contiguous range
+                const uint64_t mine = __ballot(lane < nr && (cur[d].rl >> 4) == w);
+                if (tj == 0.0 || mine == 0) continue;
+                const int a_lo = __ffsll((unsigned long long)mine) - 1, na = __popcll(mine);
                 // stage the slots (the previous incidence's reads of the
                 // staging arrays precede these writes in this wave's LDS order)
                 wave_order();
@@ -1200,15 +1213,15 @@ __global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restri
                 lc[lane] = cur[d].cl;
                 sc[lane] = cur[d].cg;
                 wave_order();
-                // lanes take 8 x 8 blocks of (row slot, column slot) pairs; within
+                // lanes take 4 x 16 blocks of (row slot, column slot) pairs; within
                 // one incidence every pair is a different tile entry.  LDS adds
                 // without return: the wave does not wait for them, and the LDS
-                // applies one wave's instructions in order, so every entry's
-                // sum runs in incidence order
-                for (int a0 = 0; a0 < nr; a0 += 8)
-                    for (int b0 = 0; b0 < nc; b0 += 8) {
-                        const int a = a0 + (lane >> 3), b = b0 + (lane & 7);
-                        if (a < nr && b < nc && (!diag || a >= b)) atomicAdd(&T[lr[a] * LDP + lc[b]], sr[a] * sc[b]);
+                // applies one wave's instructions in order
+                for (int a0 = 0; a0 < na; a0 += 4)
+                    for (int b0 = 0; b0 < nc; b0 += 16) {
+                        const int a = a_lo + a0 + (lane >> 4), b = b0 + (lane & 15);
+                        if (a0 + (lane >> 4) < na && b < nc && (!diag || a >= b))
+                            atomicAdd(&T[lr[a] * LDP + lc[b]], sr[a] * sc[b]);
                     }
             }
 #pragma unroll
@@ -1216,15 +1229,17 @@ __global__ __launch_bounds__(64) void k_assemble_tiles(const TileChunk* __restri
         }
     }
     wave_order();
+    // this wave's 16 rows: lane = (column mod 4) x 16 + row
+    const int r = 16 * w + (lane & 15);
     if (C.part < 0) {
         const int64_t m = F.m[C.f];
         double* dst = fronts + F.off[C.f] + rb + (int64_t)cb * m;
-#pragma unroll 8
-        for (int c = 0; c < TS; c++) dst[lane + c * m] += T[lane * LDP + c];
+#pragma unroll 4
+        for (int c = lane >> 4; c < TS; c += 4) dst[r + c * m] += T[r * LDP + c];
     } else {
         double* dst = parts + (int64_t)C.part * TS * TS;
-#pragma unroll 8
-        for (int c = 0; c < TS; c++) dst[lane + c * TS] = T[lane * LDP + c];
+#pragma unroll 4
+        for (int c = lane >> 4; c < TS; c += 4) dst[r + c * TS] = T[r * LDP + c];
     }
 }
 
@@ -1252,7 +1267,7 @@ void launch_assemble_tiles(hipStream_t st, const TileChunk* ch, int64_t nch, con
                            const double* tau, const double* gs, const int32_t* ls, FrontsDev F, double* fronts,
                            double* parts) {
     if (nch <= 0) return;
-    hipLaunchKernelGGL(k_assemble_tiles, dim3((unsigned)nch), dim3(64), 0, st, ch, inc, ptr, tau, gs, ls, F, fronts,
+    hipLaunchKernelGGL(k_assemble_tiles, dim3((unsigned)nch), dim3(256), 0, st, ch, inc, ptr, tau, gs, ls, F, fronts,
                        parts);
 }
 void launch_tiles_reduce(hipStream_t st, const TileRed* red, int64_t nred, const double* parts, FrontsDev F,
