@@ -62,7 +62,13 @@ def test_config2_first_sweep_sites_sampled(cfg2):
     g = E.EP(dict(cfg, leaf_size=512), raw["xyz"], A, raw["sigma"])
     g.sweep()
     tau_g, nu_g = g.sites()
+    # the host plan (the basis of the statements about sizes that do not
+    # fit) against what this context holds on the device
+    held = g.structure()["device_bytes"]
     g.close()
+    planned = E.ep_plan(dict(cfg, leaf_size=512), raw["xyz"])["device_bytes"]
+    print(f"config 2 device bytes: context {held / 1e9:.2f} GB, plan {planned / 1e9:.2f} GB", flush=True)
+    assert abs(planned - held) < 0.02 * held
     idx = np.random.default_rng(5).choice(w.n_stars, 48, replace=False)
     sl = epo.Sightlines(cfg, raw["xyz"][idx])
     gval, lnA, c = sl.linearise(np.full(sl.grid.N, cfg["prior_mean"]))
