@@ -820,6 +820,9 @@ static int build_tile_assembly(ep_ctx* ctx, const std::vector<int32_t>& sord) {
                     I.c0 = (uint16_t)(r[v][1] - ptr[st]);
                     I.nr = (uint16_t)r[u][2];
                     I.nc = (uint16_t)r[v][2];
+                    I.rlo = (uint8_t)(lsort[(size_t)r[u][1]] % TS);
+                    I.rhi = (uint8_t)(lsort[(size_t)(r[u][1] + r[u][2] - 1)] % TS);
+                    I.pad = 0;
                 }
         }
     }

@@ -72,6 +72,8 @@ struct TileInc {
     int32_t star;
     uint16_t r0, c0;   // first row slot, first column slot: positions in the star's sorted slots
     uint16_t nr, nc;
+    uint8_t rlo, rhi;  // tile rows of the first and the last row slot
+    uint16_t pad;
 };
 // A run of one tile's incidences, applied in order by one wave.
 struct TileChunk {

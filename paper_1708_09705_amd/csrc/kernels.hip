@@ -1167,10 +1167,22 @@ __global__ __launch_bounds__(256) void k_assemble_tiles(const TileChunk* __restr
     for (int q = lane; q < 16 * LDP; q += 64) Tw[q] = 0.0;
     const int rb = TS * C.ti, cb = TS * C.tj;
     const bool diag = C.ti == C.tj;
+    __shared__ int32_t list_all[4][64];
+    int32_t* list = list_all[w];
     for (int64_t e0 = C.i0; e0 < C.i0 + C.n; e0 += 64) {
-        const int nb = (int)std::min<int64_t>(64, C.i0 + C.n - e0);
-        // lane j holds incidence e0 + j
-        const TileInc I = inc[e0 + (lane < nb ? lane : nb - 1)];
+        const int nbatch = (int)std::min<int64_t>(64, C.i0 + C.n - e0);
+        // lane j holds incidence e0 + j; the wave keeps those whose row run
+        // reaches its stripe, in order (their positions compacted in LDS)
+        const TileInc I0 = inc[e0 + (lane < nbatch ? lane : nbatch - 1)];
+        const bool member = lane < nbatch && (I0.rlo >> 4) <= w && w <= (I0.rhi >> 4);
+        const uint64_t mm = __ballot(member);
+        const int nb = __popcll(mm);
+        if (nb == 0) continue;
+        wave_order();
+        if (member) list[__builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0))] = lane;
+        wave_order();
+        const int src = list[lane < nb ? lane : nb - 1];
+        const TileInc I = inc[e0 + src];
         const int64_t p0 = ptr[I.star];
         const int64_t rp = p0 + I.r0, cp = p0 + I.c0;
         const int nrc = ((int)I.nr << 16) | (int)I.nc;

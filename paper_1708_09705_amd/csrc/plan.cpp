@@ -105,7 +105,7 @@ extern "C" int ep_plan(const ep_config* c, int64_t S, const double* xyz, ep_plan
     const int64_t pad = 256 * sym.max_m + 256;
     const int64_t dense = 8 * (sym.total_elems + p.x_elems + p.w_elems + 3 * pad);
     // the clique assembly's (star, tile) incidences: a star whose slots fall
-    // in r runs of 64 local rows has r (r + 1) / 2 of them, 12 bytes each,
+    // in r runs of 64 local rows has r (r + 1) / 2 of them, 16 bytes each,
     // plus at most 32 bytes each of partial tiles; its sorted local rows and g
     int64_t incid = 0;
     {
@@ -119,7 +119,7 @@ extern "C" int ep_plan(const ep_config* c, int64_t S, const double* xyz, ep_plan
             incid += r * (r + 1) / 2;
         }
     }
-    const int64_t stars = nnz * (8 + 3 * 4) + S * 30 * 8 + incid * (12 + 32) + nnz * 12;
+    const int64_t stars = nnz * (8 + 3 * 4) + S * 30 * 8 + incid * (16 + 32) + nnz * 12;
     const int64_t vectors = N * 24 * 8 + N * (int64_t)(st.full.size() / 3) * 8;
     p.device_bytes = dense + stars + vectors;
     p.device_bytes_mixed = p.device_bytes + 4 * (sym.total_elems + pad);
