@@ -1225,16 +1225,20 @@ __global__ __launch_bounds__(256) void k_assemble_tiles(const TileChunk* __restr
                 lc[lane] = cur[d].cl;
                 sc[lane] = cur[d].cg;
                 wave_order();
-                // lanes take 4 x 16 blocks of (row slot, column slot) pairs; within
-                // one incidence every pair is a different tile entry.  LDS adds
-                // without return: the wave does not wait for them, and the LDS
-                // applies one wave's instructions in order
-                for (int a0 = 0; a0 < na; a0 += 4)
-                    for (int b0 = 0; b0 < nc; b0 += 16) {
-                        const int a = a_lo + a0 + (lane >> 4), b = b0 + (lane & 15);
-                        if (a0 + (lane >> 4) < na && b < nc && (!diag || a >= b))
-                            atomicAdd(&T[lr[a] * LDP + lc[b]], sr[a] * sc[b]);
-                    }
+                // the na x nc (row slot, column slot) pairs dealt to the lanes
+                // row after row, 64 at a time (pair k: row k / nc, column
+                // k mod nc; the quotient from a float product, exact since
+                // k < 1024 keeps (k + 1/2) / nc at least 1/128 from an
+                // integer); within one incidence every pair is a different tile
+                // entry.  LDS adds without return: the wave does not wait for
+                // them, and the LDS applies one wave's instructions in order
+                const int npair = na * nc;
+                const float inv_nc = 1.0f / (float)nc;
+                for (int k = lane; k < npair; k += 64) {
+                    const int ai = (int)(((float)k + 0.5f) * inv_nc);
+                    const int a = a_lo + ai, b = k - ai * nc;
+                    if (!diag || a >= b) atomicAdd(&T[lr[a] * LDP + lc[b]], sr[a] * sc[b]);
+                }
             }
 #pragma unroll
             for (int d = 0; d < TA_DEPTH; d++) cur[d] = nxt[d];
@@ -1246,8 +1250,16 @@ __global__ __launch_bounds__(256) void k_assemble_tiles(const TileChunk* __restr
     if (C.part < 0) {
         const int64_t m = F.m[C.f];
         double* dst = fronts + F.off[C.f] + rb + (int64_t)cb * m;
-#pragma unroll 4
-        for (int c = lane >> 4; c < TS; c += 4) dst[r + c * m] += T[r * LDP + c];
+        // the 16 front entries loaded before the first store (the compiler
+        // cannot tell the columns apart and would wait out each one in turn)
+        double v[TS / 4];
+#pragma unroll
+        for (int i = 0; i < TS / 4; i++) v[i] = dst[r + (int64_t)((lane >> 4) + 4 * i) * m];
+#pragma unroll
+        for (int i = 0; i < TS / 4; i++) {
+            const int c = (lane >> 4) + 4 * i;
+            dst[r + (int64_t)c * m] = v[i] + T[r * LDP + c];
+        }
     } else {
         double* dst = parts + (int64_t)C.part * TS * TS;
 #pragma unroll 4
@@ -1263,10 +1275,21 @@ __global__ __launch_bounds__(64) void k_tiles_reduce(const TileRed* __restrict__
     const int lane = threadIdx.x;
     const int64_t m = F.m[R.f];
     double* dst = fronts + F.off[R.f] + TS * R.ti + (int64_t)TS * R.tj * m;
-    for (int c = 0; c < TS; c++) {
-        double v = 0.0;
-        for (int q = 0; q < R.np; q++) v += parts[(int64_t)(R.p0 + q) * TS * TS + lane + c * TS];
-        dst[lane + c * m] += v;
+    // eight columns at a time, every load of them ahead of their stores
+    for (int c0 = 0; c0 < TS; c0 += 8) {
+        double d[8], v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            d[u] = dst[lane + (int64_t)(c0 + u) * m];
+            v[u] = 0.0;
+        }
+        for (int q = 0; q < R.np; q++) {
+            const double* pp = parts + (int64_t)(R.p0 + q) * TS * TS + lane + c0 * TS;
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] += pp[u * TS];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) dst[lane + (int64_t)(c0 + u) * m] = d[u] + v[u];
     }
 }
 
