@@ -8,9 +8,10 @@ cube, disc-distributed stars, sigma ~ U[0.05, 0.2] mag), FP64 throughout.
 value = stars x steps / wall time of the timed steps (whole sweeps; inputs
 resident on the device).  The JSON line also carries the per-star-phase rate
 (stars / time of cavity + tilted moments + site update), the per-phase
-times, the dense-front MFMA roofline, the surrogate + mixed-precision form
-of the same sweeps with its error against the FP64 run, and the oracle's CPU
-baseline.
+times, the dense-front MFMA roofline, the two mixed-precision forms of the
+same sweeps (FP32 factor; FP32 selected inversion with FP64 partial sums),
+each with quadrature and with the surrogate and with its error against the
+FP64 run, and the oracle's CPU baseline.
 """
 from __future__ import annotations
 
@@ -642,6 +643,9 @@ def main():
     if args.mixed:
         line["surrogate_mixed"] = leg("mixed", "surrogate")
         line["mixed_quadrature"] = leg("mixed", "quadrature")
+        # FP64 factor, selected inversion on FP32 MFMA (FP64 partial sums)
+        line["surrogate_selinv32"] = leg("selinv32", "surrogate")
+        line["selinv32_quadrature"] = leg("selinv32", "quadrature")
         line["fp64_surrogate"] = leg("fp64", "surrogate")
         line["surrogate_gain"] = surrogate_gain()
     if args.variant:

@@ -54,7 +54,13 @@ typedef enum {
 } ep_status;
 
 typedef enum { EP_LIK_EXTINCTION = 0, EP_LIK_GAUSS_LINEAR = 1, EP_LIK_GMM = 2 } ep_likelihood;
-typedef enum { EP_PREC_FP64 = 0, EP_PREC_MIXED = 1 } ep_precision;
+/* SELINV32: the factor, solves and sites in FP64 and the selected inversion's
+ * dense block products (Sigma_21 = -Sigma_22 L21 L11^{-1}, Sigma_11) on FP32
+ * MFMA with FP64 storage: operands rounded to FP32, products summed in FP32
+ * over 64 terms at a time and those partial sums in FP64.  The marginal
+ * variances and the cavities then carry FP32 rounding (about 1e-6 relative
+ * on a 64^3 grid); the posterior mean does not. */
+typedef enum { EP_PREC_FP64 = 0, EP_PREC_MIXED = 1, EP_PREC_SELINV32 = 2 } ep_precision;
 typedef enum { EP_MOM_QUADRATURE = 0, EP_MOM_SURROGATE = 1 } ep_moments;
 typedef enum { EP_MEAN_CONSTANT = 0, EP_MEAN_DISC_BUMP = 1 } ep_mean_fn;
 
@@ -75,7 +81,9 @@ typedef struct ep_config {
     int32_t likelihood;        /* ep_likelihood */
     int32_t precision;         /* ep_precision: FP64, or MIXED = FP32 factor on FP32 MFMA
                                   with FP64 diagonal pivots, FP64 refinement of the
-                                  mean and FP64 selected inversion */
+                                  mean and FP64 selected inversion, or SELINV32 =
+                                  FP64 factor with the selected inversion's block
+                                  products on FP32 MFMA */
     int32_t moments;           /* ep_moments: QUADRATURE, or SURROGATE = gated network
                                   with quadrature fallback (needs ep_mlp_load) */
     /* EP controls */

@@ -681,7 +681,10 @@ static int validate(const ep_config* c, int64_t S, const double* xyz, const doub
         err = "unknown likelihood";
         return EP_ERR_INVALID_ARG;
     }
-    if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED) { err = "unknown precision"; return EP_ERR_INVALID_ARG; }
+    if (c->precision != EP_PREC_FP64 && c->precision != EP_PREC_MIXED && c->precision != EP_PREC_SELINV32) {
+        err = "unknown precision";
+        return EP_ERR_INVALID_ARG;
+    }
     if (c->pointers_on_device != 0 && c->pointers_on_device != 1) { err = "pointers_on_device must be 0 or 1"; return EP_ERR_INVALID_ARG; }
     if (c->mean_fn != EP_MEAN_CONSTANT && c->mean_fn != EP_MEAN_DISC_BUMP) { err = "unknown mean_fn"; return EP_ERR_INVALID_ARG; }
     if (c->mean_fn == EP_MEAN_DISC_BUMP) {
@@ -1551,7 +1554,10 @@ static void enqueue_selinv(ep_ctx* ctx) {
         kt_end(ctx, P.extend.ntasks, EP_KK_GATHER);
         for (const TaskRange* r : {&P.selW, &P.selS21, &P.selS11}) {
             kt_begin(ctx, r->n);
-            launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b, r->a32);
+            if (ctx->cfg.precision == EP_PREC_SELINV32)
+                launch_gemm_tasks_x32(st, ctx->d_tasks + r->off, r->n, b);
+            else
+                launch_gemm_tasks(st, ctx->d_tasks + r->off, r->n, b, r->a32);
             kt_end(ctx, r->n, EP_KK_GEMM);
         }
     }

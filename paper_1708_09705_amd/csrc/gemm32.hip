@@ -33,30 +33,37 @@ __device__ __forceinline__ int64_t xcd_task32(int64_t n) {
     return x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
 }
 
-// One R x 16 slab op(M)(i, k) into registers as 8-byte pairs (NP per
-// thread).  kc: k contiguous in memory (M[k + i ld]); else i contiguous.
-template <int R>
-__device__ __forceinline__ void load_slab(float* r, const float* M, int ld, bool kc) {
+template <typename T> struct Pair2;
+template <> struct Pair2<float> { typedef float2 type; };
+template <> struct Pair2<double> { typedef double2 type; };
+
+// One R x 16 slab op(M)(i, k) into registers as pairs (NP per thread),
+// read in the element type of the memory (T: float, or double for the FP64
+// buffers, rounded to FP32 in the registers).  kc: k contiguous in memory
+// (M[k + i ld]); else i contiguous.
+template <int R, typename T>
+__device__ __forceinline__ void load_slab(float* r, const T* M, int ld, bool kc) {
+    typedef typename Pair2<T>::type P2;
     constexpr int NP = R * KH / 2 / NT;
     const int t = threadIdx.x;
     if (!kc) {
         constexpr int PR = R / 2, KS = NT / PR;
         const int p = t % PR, k0 = t / PR;
-        const float* Mp = M + 2 * p + (int64_t)k0 * ld;
+        const T* Mp = M + 2 * p + (int64_t)k0 * ld;
 #pragma unroll
         for (int q = 0; q < NP; q++) {
-            const float2 v = *(const float2*)(Mp + (int64_t)(KS * q) * ld);
-            r[2 * q] = v.x;
-            r[2 * q + 1] = v.y;
+            const P2 v = *(const P2*)(Mp + (int64_t)(KS * q) * ld);
+            r[2 * q] = (float)v.x;
+            r[2 * q + 1] = (float)v.y;
         }
     } else {
         const int kp = t & 7, i0 = t >> 3;   // 64 i per round
-        const float* Mp = M + 2 * kp + (int64_t)i0 * ld;
+        const T* Mp = M + 2 * kp + (int64_t)i0 * ld;
 #pragma unroll
         for (int q = 0; q < NP; q++) {
-            const float2 v = *(const float2*)(Mp + (int64_t)(64 * q) * ld);
-            r[2 * q] = v.x;
-            r[2 * q + 1] = v.y;
+            const P2 v = *(const P2*)(Mp + (int64_t)(64 * q) * ld);
+            r[2 * q] = (float)v.x;
+            r[2 * q + 1] = (float)v.y;
         }
     }
 }
@@ -108,8 +115,24 @@ __device__ __forceinline__ void mma_slab(f4v acc[4][4], const float* sA, const f
 
 // One segment: acc += sum over its K of op(A) op(B).  Ends with a barrier
 // after the last read of smem.
-__device__ __forceinline__ void run_seg(f4v acc[4][4], float* smem, const float* A, const float* B, const GemmSeg& S,
-                                        bool active) {
+// Adds the FP32 sums into the FP64 accumulators and clears them.
+__device__ __forceinline__ void flush_wide(f4v acc[4][4], double wide[64]) {
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) wide[16 * x + 4 * y + r] += (double)acc[x][y][r];
+            acc[x][y] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+}
+
+// WIDE: the FP32 sums are added into the FP64 accumulators `wide` every four
+// slabs (64 k) and at the end of the segment, so that FP32 rounding grows
+// with 64 rather than with the whole K
+template <typename T, bool WIDE>
+__device__ __forceinline__ void run_seg(f4v acc[4][4], double* wide, float* smem, const T* A, const T* B,
+                                        const GemmSeg& S, bool active) {
     const bool ta = S.flags & 1, tb = (S.flags & 2) != 0;
     const float sgn = (S.flags & 4) ? -1.0f : 1.0f;
     const bool kca = ta, kcb = !tb;
@@ -120,17 +143,17 @@ __device__ __forceinline__ void run_seg(f4v acc[4][4], float* smem, const float*
     float* U1 = smem + SLA + SLB;
     float a0[BM * KH / NT], b0[BN * KH / NT];
     float a1[BM * KH / NT], b1[BN * KH / NT];
-    load_slab<BM>(a0, A, S.lda, kca);
-    load_slab<BN>(b0, B, S.ldb, kcb);
+    load_slab<BM, T>(a0, A, S.lda, kca);
+    load_slab<BN, T>(b0, B, S.ldb, kcb);
     if (nh > 1) {
-        load_slab<BM>(a1, A + ha, S.lda, kca);
-        load_slab<BN>(b1, B + hb, S.ldb, kcb);
+        load_slab<BM, T>(a1, A + ha, S.lda, kca);
+        load_slab<BN, T>(b1, B + hb, S.ldb, kcb);
     }
     store_slab<BM, LDA>(a0, U0, kca, sgn);
     store_slab<BN, LDB>(b0, U0 + SLA, kcb, 1.0f);
     if (nh > 2) {
-        load_slab<BM>(a0, A + 2 * ha, S.lda, kca);
-        load_slab<BN>(b0, B + 2 * hb, S.ldb, kcb);
+        load_slab<BM, T>(a0, A + 2 * ha, S.lda, kca);
+        load_slab<BN, T>(b0, B + 2 * hb, S.ldb, kcb);
     }
     __syncthreads();
     for (int h = 0; h < nh; h += 2) {
@@ -139,23 +162,25 @@ __device__ __forceinline__ void run_seg(f4v acc[4][4], float* smem, const float*
             store_slab<BM, LDA>(a1, U1, kca, sgn);
             store_slab<BN, LDB>(b1, U1 + SLA, kcb, 1.0f);
             if (h + 3 < nh) {
-                load_slab<BM>(a1, A + (h + 3) * ha, S.lda, kca);
-                load_slab<BN>(b1, B + (h + 3) * hb, S.ldb, kcb);
+                load_slab<BM, T>(a1, A + (h + 3) * ha, S.lda, kca);
+                load_slab<BN, T>(b1, B + (h + 3) * hb, S.ldb, kcb);
             }
         }
         __syncthreads();
         if (h + 1 >= nh) break;
         if (active) mma_slab(acc, U1, U1 + SLA);
+        if (WIDE && active && (h & 3) == 2) flush_wide(acc, wide);   // slabs h - 2 .. h + 1 done
         if (h + 2 < nh) {
             store_slab<BM, LDA>(a0, U0, kca, sgn);
             store_slab<BN, LDB>(b0, U0 + SLA, kcb, 1.0f);
             if (h + 4 < nh) {
-                load_slab<BM>(a0, A + (h + 4) * ha, S.lda, kca);
-                load_slab<BN>(b0, B + (h + 4) * hb, S.ldb, kcb);
+                load_slab<BM, T>(a0, A + (h + 4) * ha, S.lda, kca);
+                load_slab<BN, T>(b0, B + (h + 4) * hb, S.ldb, kcb);
             }
         }
         __syncthreads();
     }
+    if (WIDE && active) flush_wide(acc, wide);
 }
 
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_tasks_f32(const GemmTask* __restrict__ tasks, int64_t n, float* F32) {
@@ -178,7 +203,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int q = 0; q < 2; q++) {
         if (q >= nseg) break;
         const GemmSeg& S = T.s[q];
-        run_seg(acc, smem, F32 + S.a, F32 + S.b, S, mine);
+        run_seg<float, false>(acc, nullptr, smem, F32 + S.a, F32 + S.b, S, mine);
     }
     if (!mine) return;
     const bool over = T.flags & 1, atom = (T.flags & 2) != 0;
@@ -208,11 +233,71 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
 }
 
+__device__ __forceinline__ double* buf64(const Bufs& b, int id) {
+    return id == BUF_FRONTS ? b.fronts : (id == BUF_X ? b.X : b.W);
+}
+
+// The same tasks on the FP64 buffers with FP32 arithmetic (the selected
+// inversion of precision SELINV32): operands and outputs are addressed as in
+// the FP64 task kernel (buffer ids in the flags), the operand slabs are
+// rounded to FP32 as they are loaded, the products accumulate in FP32 on
+// v_mfma_f32_16x16x4f32 over 64 k at a time and those partial sums in FP64,
+// and the results are stored in FP64.  The FP64 accumulators take the
+// register file to 256 VGPRs (one block of eight waves per CU; a few spill).
+__global__ __launch_bounds__(NT) void k_gemm_tasks_x32(const GemmTask* __restrict__ tasks, int64_t n, Bufs bufs) {
+    __shared__ float smem[2 * (SLA + SLB)];
+    const int64_t t = xcd_task32(n);
+    if (t >= n) return;
+    const GemmTask& T = tasks[t];
+    const int nseg = (T.flags >> 4) & 3;
+    if (nseg == 0) return;   // padding entry
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qr = w >> 1, qc = w & 1;
+    const int nqa = gt_rows(T.flags), nqb = (T.flags & GT_COLS2) ? 2 : 1;
+    const bool mine = qr < nqa && qc < nqb && (!(T.flags & GT_LOWER) || gt_diag(T.flags) + qr - qc >= 0);
+    f4v acc[4][4];
+    double wide[64];
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) acc[x][y] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 64; q++) wide[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        if (q >= nseg) break;
+        const GemmSeg& S = T.s[q];
+        run_seg<double, true>(acc, wide, smem, buf64(bufs, (S.flags >> 8) & 3) + S.a,
+                              buf64(bufs, (S.flags >> 10) & 3) + S.b, S, mine);
+    }
+    if (!mine) return;
+    const bool over = T.flags & 1, atom = (T.flags & 2) != 0;
+    const int64_t rs = (T.flags & GT_TSTORE) ? T.ldc : 1, cs = (T.flags & GT_TSTORE) ? 1 : T.ldc;
+    double* C = buf64(bufs, (T.flags >> 8) & 3) + T.c + (qr * 64 + 4 * (lane >> 4)) * rs + (qc * 64 + (lane & 15)) * cs;
+    // v_mfma_f32_16x16x4f32 output: lane l, item r -> row 4(l/16) + r, column l%16
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                double* p = C + (16 * x + r) * rs + (16 * y) * cs;
+                const double v = wide[16 * x + 4 * y + r];
+                if (atom) atomicAdd(p, v);
+                else *p = over ? v : *p + v;
+            }
+}
+
 }  // namespace
 
 void launch_gemm_tasks_f32(hipStream_t st, const GemmTask* t, int64_t n, float* F32) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gemm_tasks_f32, dim3((unsigned)n), dim3(NT), 0, st, t, n, F32);
+}
+
+void launch_gemm_tasks_x32(hipStream_t st, const GemmTask* t, int64_t n, Bufs b) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gemm_tasks_x32, dim3((unsigned)n), dim3(NT), 0, st, t, n, b);
 }
 
 }  // namespace ep

@@ -113,6 +113,8 @@ void launch_scatter_const(hipStream_t st, double* base, const int64_t* dest, int
 void launch_gemm_tasks(hipStream_t st, const GemmTask* t, int64_t n, Bufs b, bool a32);
 // the same layout in FP32 on the FP32 copy of the fronts (every offset into F32)
 void launch_gemm_tasks_f32(hipStream_t st, const GemmTask* t, int64_t n, float* F32);
+// the FP64-buffer tasks of launch_gemm_tasks computed in FP32 arithmetic
+void launch_gemm_tasks_x32(hipStream_t st, const GemmTask* t, int64_t n, Bufs b);
 void launch_potrf(hipStream_t st, const int32_t* flist, int nf, int k, FrontsDev F, Bufs b, int* err);
 void launch_trsm_step(hipStream_t st, const BatchEnt* be, int nbe, int64_t ntasks, int k, FrontsDev F, Bufs b);
 // factor_err non-null: the launch also factors the diagonal tile of column

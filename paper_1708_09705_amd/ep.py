@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libep.so")
 EP_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "NOT_PD", -4: "DEVICE", -5: "STATE", -6: "NUMERIC"}
 LIKELIHOOD = {"extinction": 0, "gauss_linear": 1, "gmm": 2}
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "selinv32": 2}
 MOMENTS = {"quadrature": 0, "surrogate": 1}
 MEAN_FN = {"constant": 0, "disc_bump": 1}
 N_THETA = 5

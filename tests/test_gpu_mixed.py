@@ -78,3 +78,59 @@ def test_mixed_config2_against_fp64_gpu():
     assert em < 1e-4
     assert ev < 3e-3
     assert rms_m < 1e-6 and rms_v < 1e-4
+
+
+# Precision SELINV32: FP64 factor, solves and sites; the selected
+# inversion's block products on FP32 MFMA (operands rounded to FP32, FP32
+# sums over 64 terms, those partial sums in FP64, FP64 storage).  The
+# posterior mean comes from the FP64 factor alone.  The variances carry the
+# FP32 rounding of the block products: each level's
+# Sigma_11 = X^T X + W^T Sigma_22 W is a sum of positive semi-definite terms,
+# so the rounding is not amplified by the conditioning of Q as a rounded
+# factor's is.  With the whole K summed in FP32 the worst node at 64^3 /
+# 100k was 0.7-1.3e-4 (the sums' rounding, not the operands'); with FP64
+# partial sums it is 1e-6.  Bound: the required 1e-4 relative error in mean
+# and variance.
+
+
+@pytest.mark.parametrize("n,L,stars,leaf", [(8, 500.0, 60, 32), (12, 700.0, 300, 64)])
+def test_selinv32_against_oracle(n, L, stars, leaf):
+    E = _E()
+    cfg, gcfg, raw, f, A, sl = small_case(n=n, L=L, stars=stars, leaf=leaf)
+    ora = epo.DenseEP(cfg, raw["xyz"], A, raw["sigma"], sightlines=sl)
+    g = E.EP(dict(gcfg, precision="selinv32"), raw["xyz"], A, raw["sigma"])
+    for s in range(3):
+        ora.sweep()
+        g.sweep()
+    em = relerr(g.posterior_mean(), ora.posterior_mean())
+    ev = relerr(g.marginal_var(), ora.marginal_var())
+    print(f"selinv32 vs oracle: mean {em:.2e} var {ev:.2e}", flush=True)
+    assert em < 1e-4 and ev < 1e-4
+
+
+def test_selinv32_config2_against_fp64_gpu():
+    """64^3 / 100k on the FP64 run's state after two sweeps: the mean within
+    the FP64 parity bar (the same FP64 factor and solves; two FP64 contexts
+    loaded with one state differ by their atomic summation orders), the
+    variances within 1e-4."""
+    E = _E()
+    w = preset(2)
+    raw = draw(w)
+    cfg = E.make_config(w.ep_fields(), leaf_size=512)
+    f, A = E.ep_simulate(cfg, raw["xyz"], raw["sigma"], raw["eps"], raw["xi"])
+    g = E.EP(E.make_config(w.ep_fields(), leaf_size=512), raw["xyz"], A, raw["sigma"])
+    for _ in range(2):
+        g.sweep()
+    sites, lin = g.sites(), g.linpoint()
+    m64, v64 = g.posterior_mean(), g.marginal_var()
+    g.close()
+    g = E.EP(E.make_config(w.ep_fields(), leaf_size=512, precision="selinv32"), raw["xyz"], A, raw["sigma"])
+    g.set_sites(*sites)
+    g.set_linpoint(lin)
+    m32, v32 = g.posterior_mean(), g.marginal_var()
+    g.close()
+    em, ev = relerr(m32, m64), relerr(v32, v64)
+    rms_v = float(np.sqrt(np.mean(((v32 - v64) / v64) ** 2)))
+    print(f"config 2 selinv32 vs fp64 on the same state: mean {em:.2e} var {ev:.2e} (rms {rms_v:.1e})", flush=True)
+    assert em < 1e-8
+    assert ev < 1e-4
