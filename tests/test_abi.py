@@ -54,14 +54,21 @@ def test_invalid_inputs_rejected_before_device_work():
         with pytest.raises(E.EPError) as ei:
             E.ep_init(cfg, bad.get("xyz", xyz), bad.get("A", A), bad.get("s", s))
         assert ei.value.code == -1
-    for field, val in (("n", 1), ("damping", 0.0), ("box_pc", -1.0), ("precision", 7), ("relin_step", 0.0),
+    for field, val in (("n", 1), ("damping", 0.0), ("box_pc", -1.0), ("precision", 7), ("precision", 3),
+                       ("precision", -1), ("relin_step", 0.0),
                        ("relin_step", 1.5), ("deterministic", 2)):
         c = E.make_config(**{field: val})
         with pytest.raises(E.EPError) as ei:
             E.ep_init(c, xyz, A, s)
         assert ei.value.code == -1
-    for over in (dict(precision="mixed"), dict(mean_fn="disc_bump")):
+    for over in (dict(precision="mixed"), dict(precision="selinv32"), dict(mean_fn="disc_bump")):
         c = E.make_config(deterministic=1, **over)
+        with pytest.raises(E.EPError) as ei:
+            E.ep_init(c, xyz, A, s)
+        assert ei.value.code == -1
+    # the inferred mean needs FP64 throughout
+    for prec in ("mixed", "selinv32"):
+        c = E.make_config(precision=prec, mean_fn="disc_bump")
         with pytest.raises(E.EPError) as ei:
             E.ep_init(c, xyz, A, s)
         assert ei.value.code == -1
