@@ -280,17 +280,55 @@ def main():
             log(f"[variant] step {i}: {sts[-1]['ms_total']:.0f} ms")
         torch.cuda.synchronize()
         wv_s = time.perf_counter() - t0
-        g.close()
         n_st = max(1, side // 2)
-        return {"workload": wv.name, "grid": f"{wv.n}^3", "box_pc": wv.box_pc, "stars": wv.n_stars,
-                "value": wv.n_stars * n_st / wv_s, "unit": "star-updates/s", "ms_per_step": wv_s / n_st * 1e3,
-                "steps": n_st, "warmup": side_w, "init_s": init_s,
-                "phases_ms": {k: float(np.mean([s_[k] for s_ in sts])) for k in
-                              ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star",
-                               "ms_total")},
-                "structure": {k: stv[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front",
-                                                   "factor_flops", "selinv_flops", "trail_flops", "device_bytes")},
-                "note": "FP64, quadrature; the same spacing, prior and star law as 128^3 / 1M on a 5 kpc cube"}
+        phases = ("ms_linearise", "ms_assemble", "ms_factor", "ms_solve", "ms_selinv", "ms_star", "ms_total")
+        out = {"workload": wv.name, "grid": f"{wv.n}^3", "box_pc": wv.box_pc, "stars": wv.n_stars,
+               "value": wv.n_stars * n_st / wv_s, "unit": "star-updates/s", "ms_per_step": wv_s / n_st * 1e3,
+               "steps": n_st, "warmup": side_w, "init_s": init_s,
+               "phases_ms": {k: float(np.mean([s_[k] for s_ in sts])) for k in phases},
+               "structure": {k: stv[k] for k in ("n_fronts", "n_levels", "front_elems", "max_front",
+                                                  "factor_flops", "selinv_flops", "trail_flops", "device_bytes")},
+               "note": "FP64, quadrature; the same spacing, prior and star law as 128^3 / 1M on a 5 kpc cube"}
+        if not args.mixed:
+            g.close()
+            return out
+        # the surrogate + FP32 selected inversion form of the same workload,
+        # timed the same way; its error against FP64 on the FP64 run's final
+        # state (one context at a time: each takes most of the HBM)
+        state = (g.sites(), g.linpoint())
+        m64, v64 = g.posterior_mean(), g.marginal_var()
+        g.close()
+        try:
+            g = E.EP(E.make_config(wv.ep_fields(), leaf_size=args.leaf, device=0, precision="selinv32",
+                                   moments="surrogate"), rv["xyz"], Av, rv["sigma"])
+            g.load_surrogate(weights)
+            for i in range(side_w):
+                log(f"[variant selinv32] warmup {i}: {g.sweep()['ms_total']:.0f} ms")
+            torch.cuda.synchronize()
+            sts = []
+            t0 = time.perf_counter()
+            for i in range(n_st):
+                sts.append(g.sweep())
+                log(f"[variant selinv32] step {i}: {sts[-1]['ms_total']:.0f} ms")
+            torch.cuda.synchronize()
+            w32_s = time.perf_counter() - t0
+            g.set_sites(*state[0])
+            g.set_linpoint(state[1])
+            m32, v32 = g.posterior_mean(), g.marginal_var()
+            g.close()
+            em = float(np.max(np.abs(m32 - m64) / np.abs(m64)))
+            ev = float(np.max(np.abs(v32 - v64) / np.abs(v64)))
+            out["surrogate_selinv32"] = {
+                "value": wv.n_stars * n_st / w32_s, "unit": "star-updates/s", "ms_per_step": w32_s / n_st * 1e3,
+                "steps": n_st, "warmup": side_w,
+                "phases_ms": {k: float(np.mean([s_[k] for s_ in sts])) for k in phases},
+                "surrogate_fallbacks": int(sts[-1]["surrogate_fallbacks"]),
+                "rel_err_vs_fp64": {"posterior_mean": em, "marginal_var": ev,
+                                    "kind": "max over nodes of |x - x_fp64| / |x_fp64|"},
+                "meets_1e-4": bool(em <= 1e-4 and ev <= 1e-4)}
+        except E.EPError as e:
+            out["surrogate_selinv32"] = {"error": str(e)}
+        return out
 
     def surrogate_gain():
         # the gate centred at the network against the gate centred at the
